@@ -1,0 +1,116 @@
+/*
+ * pcbz.h -- C ABI of libpcbz, a GPU (MI355X / gfx950) implementation of the
+ * PC-bzip2 hot path for light-field microscopy frames (arXiv 2310.09467).
+ *
+ * A frame is H x W uint16 pixels, row-major, little-endian, made of
+ * pitch x pitch microlens images (paper Sec. 2.1, Fig. 1a).  It is cut into
+ * bands of whole lens rows, each within one bzip2 block.  For every band the
+ * library builds candidate arrangements (Sec. 2.1.1, Fig. 2a, Fig. 3):
+ *   PCBZ_RASTER   the band as stored (the paper's "no predictor" option),
+ *   PCBZ_VIEW     sub-aperture-view (phase-space) order,
+ *   PCBZ_VIEW_DX  view order with the lens-neighbour delta mod 2^16,
+ *   PCBZ_VIEW_DT  view order of the delta to the previous frame mod 2^16,
+ * scores them with the 2D image entropy criterion (Sec. 2.1.2, Eq. 1:
+ * first-byte-only rotation sort, last column, adjacent-byte pair entropy),
+ * codes the chosen arrangement with bzip2 (Sec. 2.1.3), and stores an 8-bit
+ * arrangement id per band in the container header (Sec. 2.1.4).
+ *
+ * Every compute step runs as HIP kernels on the GPU.  Pointers named d_* are
+ * device pointers owned by the caller; nothing is retained after a call
+ * returns.  `stream` is a hipStream_t (NULL = the null stream); work is
+ * stream-ordered, and calls that report a length synchronise that stream.
+ * A context is not thread-safe: use one per host thread.
+ *
+ * Errors are returned as pcbz_status codes; no exception or abort crosses the
+ * ABI.  pcbz_last_error() describes the last failure of a context.
+ */
+#ifndef PCBZ_H
+#define PCBZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCBZ_OK = 0,
+  PCBZ_EINVAL = -1,    /* bad parameters: h or w zero or not a multiple of pitch, pitch outside 1..90,
+                          level outside 1..9, cand_mask empty or with bits above 3, sizes too large */
+  PCBZ_ENOSPC = -2,    /* out_cap below the container size; *out_len receives the required size */
+  PCBZ_EDATA = -3,     /* corrupt container: bad magic, lengths or a CRC mismatch */
+  PCBZ_ENEEDPREV = -4, /* the temporal candidate is requested or stored but d_prev is NULL */
+  PCBZ_ENOMEM = -5,    /* workspace above the context's HBM budget, or allocation failed */
+  PCBZ_EDEVICE = -6    /* HIP runtime error (see pcbz_last_error) */
+} pcbz_status;
+
+enum { PCBZ_RASTER = 0, PCBZ_VIEW = 1, PCBZ_VIEW_DX = 2, PCBZ_VIEW_DT = 3 };
+
+/* Frame geometry and coding parameters.  level 1..9 sets the bzip2 block
+ * limit 100000*level-19 bytes; cand_mask bit i enables arrangement id i. */
+typedef struct {
+  uint32_t h, w, pitch, level, cand_mask;
+} pcbz_params;
+
+typedef struct pcbz_ctx pcbz_ctx;
+
+/* Creates a context on HIP device `hip_device`.  hbm_budget_bytes caps the
+ * device workspace (0 = no cap).  Returns PCBZ_EDEVICE if the device cannot
+ * be used. */
+int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes);
+void pcbz_destroy(pcbz_ctx *ctx);
+const char *pcbz_last_error(const pcbz_ctx *ctx);
+
+/* Band plan (bands of R = max(1, floor((100000*level-19)/(2*pitch*W))) lens
+ * rows) and an upper bound on the container size. */
+int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound);
+
+/* Entropy judgement only (Sec. 2.1.2, Eq. 1).  Writes d_choice[n_bands] (the
+ * lowest-entropy enabled arrangement per band, ties to the lowest id) and,
+ * when non-NULL, d_entropy[n_bands*4] (bits per pair; NaN for disabled ids)
+ * and d_score[n_bands*4] (the exact fixed-point sum of P*log2(P)*2^20 that
+ * decides the choice; INT64_MIN for disabled ids). */
+int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+               uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream);
+
+/* Compresses one frame into a PCBZ container in d_out (device).  With
+ * d_forced_choice (device, n_bands ids) the judgement is skipped.  The call
+ * synchronises `stream` and writes the container length to *out_len (host).
+ * d_choice_out (device, may be NULL) receives the per-band ids used.
+ * Container: "PCBZ", u8 version 1, u8 level, u16 pitch, u32 H, u32 W,
+ * u16 n_bands, u8 flags (bit 0: a band uses PCBZ_VIEW_DT), u8 0; then
+ * n_bands x (u8 id, u32 byte length); then each band's bzip2 streams (one
+ * stream per block) in band order.  All integers little-endian. */
+int pcbz_compress(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                  const uint8_t *d_forced_choice, uint8_t *d_out, size_t out_cap, size_t *out_len,
+                  uint8_t *d_choice_out, void *stream);
+
+/* Compresses n frames of possibly different shapes in one pass over all of
+ * their blocks.  Arrays are host arrays of n entries; d_prevs and
+ * d_forced may be NULL or hold NULL entries.  lens (host) receives each
+ * container length; each frame's bytes equal pcbz_compress of that frame
+ * alone.  Returns the first error; frames whose container exceeds caps[i]
+ * get PCBZ_ENOSPC with lens[i] set to the required size. */
+int pcbz_compress_batch(pcbz_ctx *ctx, uint32_t n, const pcbz_params *prm, const uint16_t *const *d_frames,
+                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced, uint8_t *const *d_outs,
+                        const size_t *caps, size_t *lens, void *stream);
+
+/* Reads a container header (host memory). */
+int pcbz_peek(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands);
+
+/* Decompresses a container held in host memory into d_out (device,
+ * out_elems >= H*W).  d_prev is required when a band uses PCBZ_VIEW_DT.
+ * Every block CRC is checked (PCBZ_EDATA on mismatch). */
+int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
+                    size_t out_elems, void *stream);
+
+/* Statistics of the last compress call on this context (for profiling):
+ * raw bytes, first-stage bytes, blocks, doubling rounds of the suffix sort. */
+int pcbz_last_stats(const pcbz_ctx *ctx, uint64_t *raw_bytes, uint64_t *rle_bytes, uint32_t *n_blocks,
+                    uint32_t *bwt_rounds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

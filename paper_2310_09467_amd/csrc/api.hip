@@ -1,0 +1,692 @@
+// api.hip -- C ABI of libpcbz: context, workspace arena, band planning and the
+// launch sequence of the compression path (all compute in HIP kernels).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcbz.h"
+#include "pcbz_internal.hpp"
+
+using namespace pcbz;
+
+namespace pcbz {
+int decode_container_host(const uint8_t *in, size_t in_len, const uint16_t *prev_host, uint16_t *frame_host,
+                          std::string &err);
+int peek_container(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands,
+                   std::vector<uint8_t> *ids, std::vector<uint32_t> *lens);
+}  // namespace pcbz
+
+struct pcbz_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::string err;
+  uint8_t *arena = nullptr;
+  size_t arena_size = 0;
+  int64_t *d_tq = nullptr;
+  size_t tq_n = 0;
+  uint32_t *d_xpow2 = nullptr;
+  uint32_t *d_xchunk = nullptr;
+  size_t xchunk_n = 0;
+  uint8_t *h_stage = nullptr;
+  size_t h_stage_size = 0;
+  uint32_t *h_small = nullptr;  // pinned read-back area (4 KB)
+  uint64_t last_raw = 0, last_rle = 0;
+  uint32_t last_blocks = 0, last_rounds = 0;
+};
+
+namespace {
+
+constexpr uint32_t kPoly = 0x04C11DB7u;
+constexpr uint32_t kMaxPitch = 90;
+
+int fail(pcbz_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(ctx, PCBZ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+uint32_t h_mulmod(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+  for (int i = 31; i >= 0; i--) {
+    r = (r & 0x80000000u) ? (r << 1) ^ kPoly : (r << 1);
+    if ((b >> i) & 1u) r ^= a;
+  }
+  return r;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the arena; with base == nullptr it only measures.
+struct Arena {
+  uint8_t *base;
+  size_t off = 0;
+  template <typename T>
+  T *get(size_t count) {
+    off = align_up(off, 256);
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += count * sizeof(T) + 16;
+    return p;
+  }
+};
+
+int check_params(const pcbz_params *p) {
+  if (!p) return PCBZ_EINVAL;
+  if (p->pitch == 0 || p->pitch > kMaxPitch || p->h == 0 || p->w == 0) return PCBZ_EINVAL;
+  if (p->h % p->pitch || p->w % p->pitch) return PCBZ_EINVAL;
+  if (p->level < 1 || p->level > 9) return PCBZ_EINVAL;
+  if (p->cand_mask == 0 || (p->cand_mask & ~0xFu)) return PCBZ_EINVAL;
+  uint64_t lens_row = 2ull * p->pitch * p->w;
+  uint64_t r = (100000ull * p->level - 19) / lens_row;
+  if (r < 1) r = 1;
+  uint64_t ns = p->h / p->pitch;
+  if ((ns + r - 1) / r > 65535) return PCBZ_EINVAL;
+  if (2ull * p->h * p->w >= (1ull << 31)) return PCBZ_EINVAL;
+  return PCBZ_OK;
+}
+
+void plan_rows(const pcbz_params *p, uint32_t *R, uint32_t *nb) {
+  uint64_t lens_row = 2ull * p->pitch * p->w;
+  uint64_t r = (100000ull * p->level - 19) / lens_row;
+  if (r < 1) r = 1;
+  uint32_t ns = p->h / p->pitch;
+  *R = (uint32_t)r;
+  *nb = (uint32_t)((ns + r - 1) / r);
+}
+
+struct FrameIn {
+  pcbz_params p;
+  const uint16_t *frame, *prev;
+  const uint8_t *forced;
+  uint8_t *out;
+  size_t cap;
+};
+
+struct Plan {
+  std::vector<BandDesc> bands;
+  std::vector<RowItem> rows;
+  std::vector<JudgeTask> tasks;
+  std::vector<uint32_t> tile_task, tile_local;
+  std::vector<int32_t> task_of;
+  std::vector<uint32_t> band_start;
+  std::vector<FrameOut> frames;
+  uint64_t ntot = 0;
+  uint32_t slots = 0, segs = 0, pitch_max = 1, nt_max = 1, band_n_max = 0, lens_per_wg = 1, remap_chunks = 1;
+  bool any_forced = false;
+};
+
+int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, Plan &P) {
+  for (size_t f = 0; f < fin.size(); f++) {
+    const FrameIn &F = fin[f];
+    int st = check_params(&F.p);
+    if (st) return fail(ctx, st, "frame %zu: invalid parameters", f);
+    if (!F.frame) return fail(ctx, PCBZ_EINVAL, "frame %zu: null frame", f);
+    if (!F.forced && (F.p.cand_mask & 8u) && !F.prev)
+      return fail(ctx, PCBZ_ENEEDPREV, "frame %zu: temporal candidate without a previous frame", f);
+    if (F.forced) P.any_forced = true;
+    uint32_t R, nb;
+    plan_rows(&F.p, &R, &nb);
+    const uint32_t p = F.p.pitch, W = F.p.w, ns = F.p.h / p;
+    const uint32_t lim = 100000u * F.p.level - 19u;
+    FrameOut fo;
+    fo.out = F.out;
+    fo.cap = F.cap;
+    fo.h = F.p.h;
+    fo.w = W;
+    fo.pitch = p;
+    fo.level = F.p.level;
+    fo.n_bands = nb;
+    fo.band_base = (uint32_t)P.bands.size();
+    P.frames.push_back(fo);
+    P.pitch_max = std::max(P.pitch_max, p);
+    P.nt_max = std::max(P.nt_max, W / p);
+    for (uint32_t k = 0; k < nb; k++) {
+      BandDesc B;
+      B.frame = F.frame;
+      B.prev = F.prev;
+      B.W = W;
+      B.pitch = p;
+      B.Nt = W / p;
+      B.Rb = std::min(R, ns - k * R);
+      B.y0 = k * R * p;
+      B.frame_id = (uint32_t)f;
+      B.band_in_frame = k;
+      B.cand_mask = F.p.cand_mask;
+      B.level = F.p.level;
+      B.n = 2u * B.Rb * p * W;
+      B.off = P.ntot;
+      uint64_t rle_max = (uint64_t)B.n + B.n / 4 + 8;
+      B.blk_slots = (uint32_t)((rle_max + (lim - 4) - 1) / (lim - 4) + 1);
+      B.blk_slot = P.slots;
+      P.slots += B.blk_slots;
+      const uint32_t bi = (uint32_t)P.bands.size();
+      P.band_start.push_back((uint32_t)P.ntot);
+      P.ntot += B.n;
+      P.band_n_max = std::max(P.band_n_max, B.n);
+      for (uint32_t s = 0; s < B.Rb; s++) P.rows.push_back(RowItem{bi, s});
+      for (int id = 0; id < kNumCand; id++) {
+        int32_t t = -1;
+        if (!F.forced && (F.p.cand_mask >> id) & 1u) {
+          JudgeTask T;
+          T.band = bi;
+          T.cand = id;
+          T.n = B.n;
+          T.seg_base = P.segs;
+          T.x_off = B.off;
+          P.segs += (B.n + 4095) / 4096;
+          t = (int32_t)P.tasks.size();
+          const uint32_t tiles = (B.n + 65535) / 65536;
+          for (uint32_t q = 0; q < tiles; q++) {
+            P.tile_task.push_back((uint32_t)t);
+            P.tile_local.push_back(q);
+          }
+          P.tasks.push_back(T);
+        }
+        P.task_of.push_back(t);
+      }
+      P.bands.push_back(B);
+    }
+  }
+  if (P.ntot >= (1ull << 31)) return fail(ctx, PCBZ_EINVAL, "batch too large (%llu bytes)", (unsigned long long)P.ntot);
+  P.band_start.push_back((uint32_t)P.ntot);
+  const uint32_t pm = P.pitch_max;
+  uint32_t tl = 16384u / (pm * pm);
+  tl = tl > 1 ? tl - 1 : 0;
+  if (tl > 32) tl = 32;
+  if (tl < 1) return fail(ctx, PCBZ_EINVAL, "pitch %u too large", pm);
+  P.lens_per_wg = tl;
+  P.remap_chunks = (P.nt_max + tl - 1) / tl;
+  (void)judge_only;
+  return PCBZ_OK;
+}
+
+// Device pointers of one call's workspace.
+struct Work {
+  BandDesc *bands;
+  RowItem *rows;
+  JudgeTask *tasks;
+  uint32_t *tile_task, *tile_local;
+  int32_t *task_of;
+  uint32_t *band_start;
+  FrameOut *frames;
+  uint8_t *forced;
+  uint32_t *ctr;  // [0] err flags, [1] n_blocks, [2] crc chunks, [3] bwt u, [4] n_chunks, [5] n_sym, [6] n_groups, [7] words, [8] cut err
+  uint8_t *choice;
+  CandBufs cb;
+  uint8_t *chosen;
+  uint32_t *hist;
+  uint16_t *seg_first, *seg_last;
+  unsigned long long *score;
+  // compression
+  uint32_t *runstart, *r1len, *r1off;
+  uint8_t *rle;
+  BlockDesc *slots, *blocks;
+  uint32_t *slot_count, *blk_raw_start, *blk_rle_start, *crc_chunk_base, *crc_acc;
+  BwtWork bw;
+  uint32_t *sa;
+  uint8_t *L;
+  BlockCode *codes;
+  MtfWork mw;
+  uint16_t *sym;
+  uint32_t *freq;
+  uint8_t *cost, *lens, *sel;
+  uint32_t *tfreq, *code_words, *group_base;
+  uint32_t *prefix, *sym_bits, *sym_off, *blk_sym_start, *word_start, *band_len;
+  uint64_t *frame_len;
+  void *scan_tmp;
+  // sizes
+  uint32_t max_blocks, n_rle_max, max_chunks, max_sym, max_groups, max_words;
+};
+
+size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
+  const uint32_t nbands = (uint32_t)P.bands.size();
+  w.bands = A.get<BandDesc>(nbands);
+  w.rows = A.get<RowItem>(P.rows.size());
+  w.tasks = A.get<JudgeTask>(P.tasks.size());
+  w.tile_task = A.get<uint32_t>(P.tile_task.size());
+  w.tile_local = A.get<uint32_t>(P.tile_local.size());
+  w.task_of = A.get<int32_t>(P.task_of.size());
+  w.band_start = A.get<uint32_t>(P.band_start.size());
+  w.frames = A.get<FrameOut>(P.frames.size());
+  w.forced = A.get<uint8_t>(nbands + 4);
+  w.ctr = A.get<uint32_t>(64);
+  w.choice = A.get<uint8_t>(nbands + 4);
+  for (int id = 0; id < kNumCand; id++) w.cb.p[id] = A.get<uint8_t>(P.ntot + 16);
+  w.hist = A.get<uint32_t>((size_t)P.tasks.size() * 65536);
+  w.seg_first = A.get<uint16_t>((size_t)P.segs * 256);
+  w.seg_last = A.get<uint16_t>((size_t)P.segs * 256);
+  w.score = A.get<unsigned long long>(P.tasks.size() + 1);
+  if (!compress) return A.off;
+  const uint64_t N = P.ntot;
+  w.chosen = A.get<uint8_t>(N + 16);
+  w.runstart = A.get<uint32_t>(N + 1);
+  w.r1len = A.get<uint32_t>(N + 1);
+  w.r1off = A.get<uint32_t>(N + 1);
+  const uint64_t nr = N + N / 4 + 8ull * nbands + 64;
+  w.n_rle_max = (uint32_t)nr;
+  w.rle = A.get<uint8_t>(nr + 16);
+  const uint32_t S = P.slots;
+  w.max_blocks = S;
+  w.slots = A.get<BlockDesc>(S);
+  w.blocks = A.get<BlockDesc>(S + 1);
+  w.slot_count = A.get<uint32_t>(nbands);
+  w.blk_raw_start = A.get<uint32_t>(S + 1);
+  w.blk_rle_start = A.get<uint32_t>(S + 1);
+  w.crc_chunk_base = A.get<uint32_t>(S + 1);
+  w.crc_acc = A.get<uint32_t>(S + 1);
+  w.bw.key[0] = A.get<uint64_t>(nr + 1);
+  w.bw.key[1] = A.get<uint64_t>(nr + 1);
+  w.bw.val[0] = A.get<uint32_t>(nr + 1);
+  w.bw.val[1] = A.get<uint32_t>(nr + 1);
+  w.bw.slot = A.get<uint32_t>(nr + 1);
+  w.bw.slot2 = A.get<uint32_t>(nr + 1);
+  w.bw.rank = A.get<uint32_t>(nr + 1);
+  w.bw.flag = A.get<uint32_t>(nr + 1);
+  w.bw.flag2 = A.get<uint32_t>(nr + 1);
+  w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr));
+  w.bw.d_u = w.ctr ? w.ctr + 3 : nullptr;
+  w.sa = A.get<uint32_t>(nr + 1);
+  w.L = A.get<uint8_t>(nr + 16);
+  w.codes = A.get<BlockCode>(S + 1);
+  w.max_chunks = (uint32_t)(nr / 4096 + S + 2);
+  w.mw.seq = A.get<uint8_t>((size_t)S * 256);
+  w.mw.used = A.get<uint32_t>((size_t)S * 8);
+  w.mw.chunk_block = A.get<uint32_t>(w.max_chunks + 1);
+  w.mw.plist = A.get<uint8_t>((size_t)w.max_chunks * 256);
+  w.mw.plen = A.get<uint32_t>(w.max_chunks);
+  w.mw.inlist = A.get<uint8_t>((size_t)w.max_chunks * 256);
+  w.mw.idx = A.get<uint8_t>(nr + 16);
+  // the MTF stage runs after the suffix sort: reuse the sort's key buffers
+  w.mw.zs = w.bw.key[0] ? (uint32_t *)w.bw.key[0] : nullptr;
+  w.mw.len = w.bw.key[0] ? (uint32_t *)w.bw.key[0] + (nr + 1) : nullptr;
+  w.mw.off = w.bw.key[1] ? (uint32_t *)w.bw.key[1] : nullptr;
+  w.mw.d_n_chunks = w.ctr ? w.ctr + 4 : nullptr;
+  w.max_sym = (uint32_t)(nr + S + 1);
+  w.sym = A.get<uint16_t>(w.max_sym + 16);
+  w.freq = A.get<uint32_t>((size_t)S * kMaxAlpha);
+  const size_t tab = (size_t)S * kMaxGroups * kMaxAlpha;
+  w.cost = A.get<uint8_t>(tab);
+  w.lens = A.get<uint8_t>(tab);
+  w.tfreq = A.get<uint32_t>(tab);
+  w.code_words = A.get<uint32_t>(tab);
+  w.group_base = A.get<uint32_t>(S + 1);
+  w.max_groups = w.max_sym / kGroupSize + S + 1;
+  w.sel = A.get<uint8_t>(w.max_groups + 16);
+  w.prefix = A.get<uint32_t>((size_t)S * kPrefixWords);
+  w.sym_bits = A.get<uint32_t>(w.max_sym + 1);
+  w.sym_off = A.get<uint32_t>(w.max_sym + 1);
+  w.blk_sym_start = A.get<uint32_t>(S + 1);
+  w.word_start = A.get<uint32_t>(S + 1);
+  w.band_len = A.get<uint32_t>(nbands);
+  w.frame_len = A.get<uint64_t>(P.frames.size());
+  // data bits <= 9 per symbol (a 9-bit code is always feasible), header < 20 KB
+  w.max_words = (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)w.max_sym * 9 / 8 + (uint64_t)S * 20600) / 4 + S);
+  size_t scan_n = std::max<size_t>((size_t)w.max_sym + 2, radix_counts_words((uint32_t)nr));
+  w.scan_tmp = A.get<uint8_t>(scan_tmp_bytes(scan_n));
+  w.bw.scan_tmp = w.scan_tmp;
+  w.mw.scan_tmp = w.scan_tmp;
+  return A.off;
+}
+
+int ensure_arena(pcbz_ctx *ctx, size_t need) {
+  if (ctx->budget && need > ctx->budget)
+    return fail(ctx, PCBZ_ENOMEM, "workspace %zu bytes exceeds the HBM budget %zu", need, ctx->budget);
+  if (need <= ctx->arena_size) return PCBZ_OK;
+  HIPCHK(ctx, hipDeviceSynchronize());
+  if (ctx->arena) HIPCHK(ctx, hipFree(ctx->arena));
+  ctx->arena = nullptr;
+  ctx->arena_size = 0;
+  size_t sz = align_up(need + need / 8, 1 << 20);
+  if (hipMalloc((void **)&ctx->arena, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->arena = nullptr;
+    return fail(ctx, PCBZ_ENOMEM, "hipMalloc(%zu) failed", sz);
+  }
+  ctx->arena_size = sz;
+  return PCBZ_OK;
+}
+
+int ensure_tables(pcbz_ctx *ctx, uint32_t band_n_max) {
+  if (!ctx->d_xpow2) {
+    uint32_t x[64];
+    x[0] = 2u;  // x^1
+    for (int k = 1; k < 64; k++) x[k] = h_mulmod(x[k - 1], x[k - 1]);
+    HIPCHK(ctx, hipMalloc((void **)&ctx->d_xpow2, sizeof x));
+    HIPCHK(ctx, hipMemcpy(ctx->d_xpow2, x, sizeof x, hipMemcpyHostToDevice));
+  }
+  const size_t need_chunks = (size_t)band_n_max / 256 + 4;
+  if (need_chunks > ctx->xchunk_n) {
+    const size_t n = std::max<size_t>(need_chunks, 4096);
+    std::vector<uint32_t> t(n);
+    uint32_t x2048 = 2u;
+    for (int k = 0; k < 11; k++) x2048 = h_mulmod(x2048, x2048);
+    t[0] = 1u;
+    for (size_t j = 1; j < n; j++) t[j] = h_mulmod(t[j - 1], x2048);
+    if (ctx->d_xchunk) HIPCHK(ctx, hipFree(ctx->d_xchunk));
+    HIPCHK(ctx, hipMalloc((void **)&ctx->d_xchunk, n * sizeof(uint32_t)));
+    HIPCHK(ctx, hipMemcpy(ctx->d_xchunk, t.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    ctx->xchunk_n = n;
+  }
+  const size_t need_tq = (size_t)band_n_max + 2;
+  if (need_tq > ctx->tq_n) {
+    const size_t n = std::max<size_t>(need_tq, 900002);
+    std::vector<int64_t> t(n);
+    for (size_t c = 0; c < n; c++) t[c] = c < 2 ? 0 : (int64_t)llround((double)c * log2((double)c) * 1048576.0);
+    if (ctx->d_tq) HIPCHK(ctx, hipFree(ctx->d_tq));
+    HIPCHK(ctx, hipMalloc((void **)&ctx->d_tq, n * sizeof(int64_t)));
+    HIPCHK(ctx, hipMemcpy(ctx->d_tq, t.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+    ctx->tq_n = n;
+  }
+  return PCBZ_OK;
+}
+
+// Uploads the plan tables (host -> device) through the pinned staging area.
+int upload_plan(pcbz_ctx *ctx, const Plan &P, const Work &w, hipStream_t s) {
+  std::vector<uint8_t> buf;
+  struct Item {
+    size_t off, bytes;
+    void *dst;
+  };
+  std::vector<Item> items;
+  auto add = [&](const void *src, size_t bytes, void *dst) {
+    if (!bytes || !dst) return;
+    size_t off = align_up(buf.size(), 256);
+    buf.resize(off + bytes);
+    memcpy(buf.data() + off, src, bytes);
+    items.push_back({off, bytes, dst});
+  };
+  add(P.bands.data(), P.bands.size() * sizeof(BandDesc), w.bands);
+  add(P.rows.data(), P.rows.size() * sizeof(RowItem), w.rows);
+  add(P.tasks.data(), P.tasks.size() * sizeof(JudgeTask), w.tasks);
+  add(P.tile_task.data(), P.tile_task.size() * sizeof(uint32_t), w.tile_task);
+  add(P.tile_local.data(), P.tile_local.size() * sizeof(uint32_t), w.tile_local);
+  add(P.task_of.data(), P.task_of.size() * sizeof(int32_t), w.task_of);
+  add(P.band_start.data(), P.band_start.size() * sizeof(uint32_t), w.band_start);
+  add(P.frames.data(), P.frames.size() * sizeof(FrameOut), w.frames);
+  if (buf.size() > ctx->h_stage_size) {
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (ctx->h_stage) HIPCHK(ctx, hipHostFree(ctx->h_stage));
+    ctx->h_stage = nullptr;
+    size_t sz = align_up(buf.size() * 2, 1 << 16);
+    HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_stage, sz, hipHostMallocDefault));
+    ctx->h_stage_size = sz;
+  } else {
+    // the previous call's copies from the staging area must be finished
+    HIPCHK(ctx, hipStreamSynchronize(s));
+  }
+  memcpy(ctx->h_stage, buf.data(), buf.size());
+  for (const Item &it : items)
+    HIPCHK(ctx, hipMemcpyAsync(it.dst, ctx->h_stage + it.off, it.bytes, hipMemcpyHostToDevice, s));
+  return PCBZ_OK;
+}
+
+int ensure_small(pcbz_ctx *ctx) {
+  if (!ctx->h_small) HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_small, 4096, hipHostMallocDefault));
+  return PCBZ_OK;
+}
+
+// Judge stages shared by pcbz_judge and the compress path.
+void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
+  const uint32_t nbands = (uint32_t)P.bands.size();
+  launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb,
+                P.any_forced ? w.forced : nullptr, 0xFu, s);
+  if (!P.tasks.empty()) {
+    fill_u32(w.hist, 0, (size_t)P.tasks.size() * 65536, s);
+    fill_u32((uint32_t *)w.score, 0, P.tasks.size() * 2, s);
+    launch_judge2(w.tasks, (uint32_t)P.tasks.size(), w.tile_task, w.tile_local, (uint32_t)P.tile_task.size(), w.cb,
+                  w.seg_first, w.seg_last, w.hist, ctx->d_tq, w.score, s);
+  }
+  (void)nbands;
+}
+
+int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, std::vector<size_t> &lens,
+                 std::vector<uint8_t *> choice_out) {
+  Plan P;
+  int st = build_plan(ctx, fin, false, P);
+  if (st) return st;
+  Work w{};
+  Arena meas{nullptr};
+  size_t need = layout(meas, P, true, w);
+  if ((st = ensure_arena(ctx, need))) return st;
+  if ((st = ensure_tables(ctx, P.band_n_max))) return st;
+  if ((st = ensure_small(ctx))) return st;
+  Arena A{ctx->arena};
+  layout(A, P, true, w);
+  if ((st = upload_plan(ctx, P, w, s))) return st;
+  const uint32_t nbands = (uint32_t)P.bands.size();
+  const uint32_t N = (uint32_t)P.ntot;
+  fill_u32(w.ctr, 0, 64, s);
+  if (P.any_forced) {
+    fill_u32((uint32_t *)w.forced, 0xFFFFFFFFu, (nbands + 4) / 4, s);
+    for (size_t f = 0; f < fin.size(); f++)
+      if (fin[f].forced)
+        HIPCHK(ctx, hipMemcpyAsync(w.forced + P.frames[f].band_base, fin[f].forced, P.frames[f].n_bands,
+                                   hipMemcpyDeviceToDevice, s));
+    launch_validate_forced(w.bands, nbands, w.forced, w.ctr, s);
+  }
+  enqueue_judge(ctx, P, w, s);
+  launch_choose2(w.bands, nbands, w.task_of, w.score, w.tasks, P.any_forced ? w.forced : nullptr, w.choice, nullptr,
+                 nullptr, s);
+  launch_gather2(w.band_start, nbands, w.cb, w.choice, w.chosen, P.ntot, s);
+  // first run-length stage, block cuts, CRCs
+  launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, s);
+  launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
+              w.blk_raw_start, w.blk_rle_start, w.crc_chunk_base, w.ctr + 1, w.ctr + 2, s);
+  const uint32_t max_crc_chunks = N / 256 + w.max_blocks + 1;
+  launch_crc2(w.chosen, w.blocks, w.ctr + 1, w.max_blocks, w.crc_chunk_base, w.ctr + 2, max_crc_chunks, ctx->d_xchunk,
+              ctx->d_xpow2, w.crc_acc, s);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_small + 16, w.r1off + N, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (ctx->h_small[8]) return fail(ctx, PCBZ_EDEVICE, "block slot overflow");
+  const uint32_t nb = ctx->h_small[1];
+  const uint32_t nrle = ctx->h_small[16];
+  // suffix sort of every block
+  int rounds = run_bwt(w.rle, nrle, nb, w.blk_rle_start, w.bw, w.sa, w.L, w.codes, ctx->h_small + 32, s);
+  if (rounds < 0) return fail(ctx, PCBZ_EDEVICE, "suffix sort did not converge");
+  // move-to-front, zero runs, tables, bit-packing
+  launch_mtf2(w.L, nrle, w.blk_rle_start, w.ctr + 1, nb, nrle / 4096 + nb + 1, w.mw, w.codes, w.sym, w.freq,
+              w.ctr + 5, s);
+  const uint32_t max_sym = nrle + nb;
+  launch_huff2(w.sym, w.ctr + 1, nb, max_sym / kGroupSize + nb + 1, w.codes, w.freq, w.cost, w.tfreq, w.group_base,
+               w.ctr + 6, w.sel, w.lens, w.code_words, s);
+  const uint32_t max_words = (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)max_sym * 9 / 8 + (uint64_t)nb * 20600) / 4 + nb);
+  launch_pack2(w.ctr + 1, nb, w.blocks, w.codes, w.mw.used, w.sel, w.lens, w.code_words, w.sym, w.ctr + 5, max_sym,
+               w.prefix, w.sym_bits, w.sym_off, w.blk_sym_start, w.scan_tmp, w.frames, (uint32_t)P.frames.size(),
+               w.bands, w.choice, w.band_len, w.frame_len, w.word_start, w.ctr + 7, max_words, s);
+  for (size_t f = 0; f < fin.size(); f++)
+    if (f < choice_out.size() && choice_out[f])
+      HIPCHK(ctx, hipMemcpyAsync(choice_out[f], w.choice + P.frames[f].band_base, P.frames[f].n_bands,
+                                 hipMemcpyDeviceToDevice, s));
+  uint64_t *hl = (uint64_t *)(ctx->h_small + 64);
+  const size_t nf = P.frames.size();
+  if (nf > (4096 - 256) / 8) {
+    std::vector<uint64_t> tmp(nf);
+    HIPCHK(ctx, hipMemcpyAsync(tmp.data(), w.frame_len, nf * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    lens.assign(tmp.begin(), tmp.end());
+  } else {
+    HIPCHK(ctx, hipMemcpyAsync(hl, w.frame_len, nf * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    lens.assign(hl, hl + nf);
+  }
+  HIPCHK(ctx, hipGetLastError());
+  ctx->last_raw = P.ntot;
+  ctx->last_rle = nrle;
+  ctx->last_blocks = nb;
+  ctx->last_rounds = (uint32_t)rounds;
+  const uint32_t ferr = ctx->h_small[0];
+  if (ferr & 1u) return fail(ctx, PCBZ_EINVAL, "forced arrangement id above 3");
+  if (ferr & 2u) return fail(ctx, PCBZ_ENEEDPREV, "forced temporal arrangement without a previous frame");
+  for (size_t f = 0; f < nf; f++)
+    if (lens[f] > fin[f].cap) return fail(ctx, PCBZ_ENOSPC, "frame %zu needs %zu bytes", f, lens[f]);
+  return PCBZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
+  if (!out) return PCBZ_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+    (void)hipGetLastError();
+    return PCBZ_EDEVICE;
+  }
+  if (hipSetDevice(hip_device) != hipSuccess) return PCBZ_EDEVICE;
+  pcbz_ctx *c = new pcbz_ctx();
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return PCBZ_OK;
+}
+
+void pcbz_destroy(pcbz_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->d_tq) (void)hipFree(c->d_tq);
+  if (c->d_xpow2) (void)hipFree(c->d_xpow2);
+  if (c->d_xchunk) (void)hipFree(c->d_xchunk);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->h_small) (void)hipHostFree(c->h_small);
+  delete c;
+}
+
+const char *pcbz_last_error(const pcbz_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound) {
+  int st = check_params(prm);
+  if (st) return st;
+  uint32_t R, nb;
+  plan_rows(prm, &R, &nb);
+  if (n_bands) *n_bands = nb;
+  if (compress_bound) {
+    const uint32_t lim = 100000u * prm->level - 19u;
+    const uint64_t raw = 2ull * prm->h * prm->w;
+    const uint64_t band_max = 2ull * R * prm->pitch * prm->w;
+    const uint64_t slots_per_band = (band_max + band_max / 4 + 8 + (lim - 4) - 1) / (lim - 4) + 1;
+    const uint64_t rle = raw + raw / 4 + 8ull * nb;
+    *compress_bound = (size_t)(20 + 5ull * nb + rle * 9 / 8 + 64 + nb * slots_per_band * 20600ull);
+  }
+  return PCBZ_OK;
+}
+
+int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+               uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream) {
+  if (!ctx || !prm || !d_frame || !d_choice) return fail(ctx, PCBZ_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<FrameIn> fin(1);
+  fin[0] = FrameIn{*prm, d_frame, d_prev, nullptr, nullptr, 0};
+  Plan P;
+  int st = build_plan(ctx, fin, true, P);
+  if (st) return st;
+  Work w{};
+  Arena meas{nullptr};
+  size_t need = layout(meas, P, false, w);
+  if ((st = ensure_arena(ctx, need))) return st;
+  if ((st = ensure_tables(ctx, P.band_n_max))) return st;
+  Arena A{ctx->arena};
+  layout(A, P, false, w);
+  if ((st = upload_plan(ctx, P, w, s))) return st;
+  enqueue_judge(ctx, P, w, s);
+  launch_choose2(w.bands, (uint32_t)P.bands.size(), w.task_of, w.score, w.tasks, nullptr, d_choice, d_entropy,
+                 d_score, s);
+  HIPCHK(ctx, hipGetLastError());
+  return PCBZ_OK;
+}
+
+int pcbz_compress(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                  const uint8_t *d_forced_choice, uint8_t *d_out, size_t out_cap, size_t *out_len,
+                  uint8_t *d_choice_out, void *stream) {
+  if (!ctx || !prm || !d_frame || !d_out || !out_len) return fail(ctx, PCBZ_EINVAL, "null argument");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<FrameIn> fin(1);
+  fin[0] = FrameIn{*prm, d_frame, d_prev, d_forced_choice, d_out, out_cap};
+  std::vector<size_t> lens;
+  int st = run_compress(ctx, fin, (hipStream_t)stream, lens, {d_choice_out});
+  if (!lens.empty()) *out_len = lens[0];
+  return st;
+}
+
+int pcbz_compress_batch(pcbz_ctx *ctx, uint32_t n, const pcbz_params *prm, const uint16_t *const *d_frames,
+                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced, uint8_t *const *d_outs,
+                        const size_t *caps, size_t *lens, void *stream) {
+  if (!ctx || !prm || !d_frames || !d_outs || !caps || !lens) return fail(ctx, PCBZ_EINVAL, "null argument");
+  if (n == 0) return PCBZ_OK;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<FrameIn> fin(n);
+  for (uint32_t i = 0; i < n; i++)
+    fin[i] = FrameIn{prm[i], d_frames[i], d_prevs ? d_prevs[i] : nullptr, d_forced ? d_forced[i] : nullptr, d_outs[i],
+                     caps[i]};
+  std::vector<size_t> out;
+  int st = run_compress(ctx, fin, (hipStream_t)stream, out, {});
+  for (uint32_t i = 0; i < n && i < out.size(); i++) lens[i] = out[i];
+  return st;
+}
+
+int pcbz_peek(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands) {
+  if (!in || !out) return PCBZ_EINVAL;
+  return peek_container(in, in_len, out, n_bands, nullptr, nullptr);
+}
+
+int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
+                    size_t out_elems, void *stream) {
+  if (!ctx || !in || !d_out) return fail(ctx, PCBZ_EINVAL, "null argument");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  pcbz_params p;
+  uint32_t nb = 0;
+  std::vector<uint8_t> ids;
+  int st = peek_container(in, in_len, &p, &nb, &ids, nullptr);
+  if (st) return fail(ctx, st, "bad container header");
+  const size_t npix = (size_t)p.h * p.w;
+  if (out_elems < npix) return fail(ctx, PCBZ_ENOSPC, "output holds %zu pixels, frame has %zu", out_elems, npix);
+  bool need_prev = false;
+  for (uint8_t id : ids) need_prev |= id == PCBZ_VIEW_DT;
+  std::vector<uint16_t> prev, frame(npix);
+  if (need_prev) {
+    if (!d_prev) return fail(ctx, PCBZ_ENEEDPREV, "container uses the temporal arrangement");
+    prev.resize(npix);
+    HIPCHK(ctx, hipMemcpyAsync(prev.data(), d_prev, npix * 2, hipMemcpyDeviceToHost, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));
+  }
+  st = decode_container_host(in, in_len, need_prev ? prev.data() : nullptr, frame.data(), ctx->err);
+  if (st) return st;
+  HIPCHK(ctx, hipMemcpyAsync(d_out, frame.data(), npix * 2, hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return PCBZ_OK;
+}
+
+int pcbz_last_stats(const pcbz_ctx *c, uint64_t *raw_bytes, uint64_t *rle_bytes, uint32_t *n_blocks,
+                    uint32_t *bwt_rounds) {
+  if (!c) return PCBZ_EINVAL;
+  if (raw_bytes) *raw_bytes = c->last_raw;
+  if (rle_bytes) *rle_bytes = c->last_rle;
+  if (n_blocks) *n_blocks = c->last_blocks;
+  if (bwt_rounds) *bwt_rounds = c->last_rounds;
+  return PCBZ_OK;
+}
+
+}  // extern "C"

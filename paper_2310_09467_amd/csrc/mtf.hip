@@ -1,0 +1,296 @@
+// mtf.hip -- move-to-front and the zero-run stage of bzip2.
+//
+// Move-to-front is sequential per block, so each block is cut into chunks of
+// 4096 positions.  The list after a chunk depends on the list before it only
+// through a fixed rule: the chunk's distinct symbols in order of last
+// occurrence (most recent first) move to the front, the rest keep their
+// order.  So (1) every chunk computes that partial list, (2) one wavefront per
+// block chains the partial lists to get each chunk's incoming list, and
+// (3) every chunk replays move-to-front from its incoming list.  The replay
+// keeps the 256-entry list in one wavefront's registers (four entries per
+// lane); a ballot finds the symbol and a one-byte shift across lanes moves it
+// to the front.
+//
+// Zero runs: a run of r zero indices becomes the bijective base-2 digits of
+// r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
+// non-zero index v becomes v + 1; each block ends with nInUse + 1.
+#include "pcbz_internal.hpp"
+
+namespace pcbz {
+namespace {
+
+constexpr uint32_t kChunk = 4096;
+
+__device__ __forceinline__ void chunk_range(uint32_t c, const uint32_t *chunk_base, const uint32_t *blk_start,
+                                            uint32_t nb, uint32_t &b, uint32_t &p0, uint32_t &p1, uint32_t &bs,
+                                            uint32_t &be) {
+  b = upper_index(chunk_base, nb, c);
+  bs = blk_start[b];
+  be = blk_start[b + 1];
+  p0 = bs + (c - chunk_base[b]) * kChunk;
+  p1 = min(be, p0 + kChunk);
+}
+
+// chunk bases per block (serial over blocks, tiny)
+__global__ void k_mtf_chunks(const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *chunk_base,
+                             uint32_t *d_n_chunks, BlockCode *codes) {
+  if (threadIdx.x != 0) return;
+  const uint32_t nb = *d_nb;
+  uint32_t acc = 0;
+  for (uint32_t b = 0; b < nb; b++) {
+    chunk_base[b] = acc;
+    uint32_t m = blk_start[b + 1] - blk_start[b];
+    uint32_t nc = (m + kChunk - 1) / kChunk;
+    codes[b].chunk_start = acc;
+    codes[b].n_chunks = nc;
+    acc += nc;
+  }
+  chunk_base[nb] = acc;
+  *d_n_chunks = acc;
+}
+
+__global__ __launch_bounds__(256) void k_used(const uint8_t *L, const uint32_t *chunk_base, const uint32_t *d_n_chunks,
+                                              const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *used) {
+  __shared__ uint32_t f[256];
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  f[threadIdx.x] = 0;
+  __syncthreads();
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) f[L[p]] = 1;
+  __syncthreads();
+  const uint64_t bal = ballot64(f[threadIdx.x] != 0);
+  if (lane_id() == 0) {
+    uint32_t wbase = threadIdx.x / 32;  // word index of this lane group
+    if ((uint32_t)bal) atomicOr(&used[b * 8 + wbase], (uint32_t)bal);
+    if ((uint32_t)(bal >> 32)) atomicOr(&used[b * 8 + wbase + 1], (uint32_t)(bal >> 32));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seq(const uint32_t *used, const uint32_t *d_nb, uint8_t *seq,
+                                             BlockCode *codes) {
+  const uint32_t b = blockIdx.x;
+  if (b >= *d_nb) return;
+  const uint32_t c = threadIdx.x;
+  const uint32_t *u = used + b * 8;
+  uint32_t before = 0;
+  for (uint32_t k = 0; k < c / 32; k++) before += __popc(u[k]);
+  before += __popc(u[c / 32] & ((1u << (c % 32)) - 1u));
+  seq[b * 256 + c] = (uint8_t)before;
+  if (c == 255) {
+    uint32_t nu = before + ((u[7] >> 31) & 1u);
+    codes[b].n_in_use = nu;
+    codes[b].alpha = nu + 2;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint32_t *chunk_base,
+                                                    const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                    const uint32_t *d_nb, const uint8_t *seq, uint8_t *plist,
+                                                    uint32_t *plen) {
+  __shared__ int lastpos[256];
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  for (int v = threadIdx.x; v < 256; v += 64) lastpos[v] = -1;
+  __syncthreads();
+  const uint8_t *sq = seq + b * 256;
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 64) atomicMax(&lastpos[sq[L[p]]], (int)(p - p0));
+  __syncthreads();
+  uint32_t cnt = 0;
+  for (int v = threadIdx.x; v < 256; v += 64) {
+    int lp = lastpos[v];
+    if (lp < 0) continue;
+    cnt++;
+    uint32_t r = 0;
+    for (int u = 0; u < 256; u++) r += lastpos[u] > lp ? 1u : 0u;
+    plist[(size_t)c * 256 + r] = (uint8_t)v;
+  }
+  for (int d = 32; d > 0; d >>= 1) cnt += __shfl_down(cnt, d);
+  if (threadIdx.x == 0) plen[c] = cnt;
+}
+
+__global__ __launch_bounds__(64) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
+                                                  const uint32_t *plen, uint8_t *inlist) {
+  __shared__ uint8_t cur[256], nxt[256], mem[256];
+  const uint32_t b = blockIdx.x;
+  if (b >= *d_nb) return;
+  const uint32_t nu = codes[b].n_in_use;
+  const uint32_t c0 = codes[b].chunk_start, nc = codes[b].n_chunks;
+  const int lane = lane_id();
+  const uint64_t lt = lanemask_lt();
+  for (int e = lane; e < 256; e += 64) cur[e] = (uint8_t)e;
+  __syncthreads();
+  for (uint32_t k = 0; k < nc; k++) {
+    const size_t ck = (size_t)(c0 + k) * 256;
+    for (int e = lane; e < 256; e += 64) {
+      inlist[ck + e] = cur[e];
+      mem[e] = 0;
+    }
+    __syncthreads();
+    const uint32_t pl = plen[c0 + k];
+    for (uint32_t e = lane; e < pl; e += 64) {
+      uint8_t v = plist[ck + e];
+      mem[v] = 1;
+      nxt[e] = v;
+    }
+    __syncthreads();
+    uint32_t base = pl;
+    for (int r = 0; r < 4; r++) {
+      const uint32_t e = r * 64 + lane;
+      const bool keep = e < nu && !mem[cur[e]];
+      const uint64_t bal = ballot64(keep);
+      if (keep) nxt[base + __popcll(bal & lt)] = cur[e];
+      base += (uint32_t)__popcll(bal);
+    }
+    __syncthreads();
+    for (int e = lane; e < 256; e += 64) cur[e] = nxt[e];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
+                                                const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
+                                                uint8_t *idx) {
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  const int lane = lane_id();
+  const uint8_t *sq = seq + b * 256;
+  const uint8_t *il = inlist + (size_t)c * 256;
+  uint32_t w = (uint32_t)il[4 * lane] | ((uint32_t)il[4 * lane + 1] << 8) | ((uint32_t)il[4 * lane + 2] << 16) |
+               ((uint32_t)il[4 * lane + 3] << 24);
+  for (uint32_t base = p0; base < p1; base += 64) {
+    const uint32_t p = base + lane;
+    const uint32_t vl = p < p1 ? sq[L[p]] : 0u;
+    const uint32_t steps = min(64u, p1 - base);
+    uint32_t mine = 0;
+    for (uint32_t k = 0; k < steps; k++) {
+      const uint32_t v = wave_read(vl, (int)k);
+      const uint32_t x = w ^ (v * 0x01010101u);
+      const uint32_t hz = (x - 0x01010101u) & ~x & 0x80808080u;
+      const uint64_t bal = ballot64(hz != 0);
+      const int ln = __ffsll((unsigned long long)bal) - 1;
+      const uint32_t hzl = wave_read(hz, ln);
+      const uint32_t pos = 4u * ln + (__ffs(hzl) - 1) / 8;
+      if ((uint32_t)lane == k) mine = pos;
+      if (pos != 0) {
+        uint32_t up = __shfl_up(w, 1) >> 24;
+        if (lane == 0) up = v;
+        const uint32_t shifted = (w << 8) | up;
+        const int kk = (int)pos - 4 * lane;
+        if (kk >= 3)
+          w = shifted;
+        else if (kk >= 0) {
+          const uint32_t mask = (1u << (8 * (kk + 1))) - 1u;
+          w = (shifted & mask) | (w & ~mask);
+        }
+      }
+    }
+    if (p < p1) idx[p] = (uint8_t)mine;
+  }
+}
+
+// zero-run start markers: a position starts a segment if it begins the block
+// or follows a non-zero index
+__global__ __launch_bounds__(256) void k_rle2_mark(const uint8_t *idx, const uint32_t *chunk_base,
+                                                   const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                   const uint32_t *d_nb, uint32_t *mark) {
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) mark[p] = (p == bs || idx[p - 1] != 0) ? p : 0u;
+}
+
+__device__ __forceinline__ uint32_t ndigits(uint32_t r) { return 31u - __clz(r + 1u); }
+
+__global__ __launch_bounds__(256) void k_rle2_len(const uint8_t *idx, const uint32_t *zs, const uint32_t *chunk_base,
+                                                  const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                  const uint32_t *d_nb, uint32_t *len) {
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    uint32_t l;
+    if (idx[p] != 0)
+      l = 1;
+    else if (p + 1 == be || idx[p + 1] != 0)
+      l = ndigits(p - zs[p] + 1);
+    else
+      l = 0;
+    if (p + 1 == be) l += 1;  // end-of-block symbol
+    len[p] = l;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const uint32_t *zs, const uint32_t *off,
+                                                    const uint32_t *chunk_base, const uint32_t *d_n_chunks,
+                                                    const uint32_t *blk_start, const uint32_t *d_nb,
+                                                    BlockCode *codes, uint16_t *sym, uint32_t *freq) {
+  __shared__ uint32_t f[kMaxAlpha];
+  const uint32_t c = blockIdx.x;
+  if (c >= *d_n_chunks) return;
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+  for (int i = threadIdx.x; i < kMaxAlpha; i += 256) f[i] = 0;
+  __syncthreads();
+  const uint32_t nu = codes[b].n_in_use;
+  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
+    uint32_t o = off[p];
+    const uint32_t v = idx[p];
+    if (v != 0) {
+      sym[o++] = (uint16_t)(v + 1);
+      atomicAdd(&f[v + 1], 1u);
+    } else if (p + 1 == be || idx[p + 1] != 0) {
+      uint32_t r = p - zs[p] + 1;
+      while (r > 0) {
+        const uint32_t d = (r & 1u) ? 0u : 1u;
+        sym[o++] = (uint16_t)d;
+        atomicAdd(&f[d], 1u);
+        r = (r - 1u - d) >> 1;
+      }
+    }
+    if (p + 1 == be) {
+      sym[o] = (uint16_t)(nu + 1);
+      atomicAdd(&f[nu + 1], 1u);
+      codes[b].sym_start = off[bs];
+      codes[b].n_mtf = o + 1 - off[bs];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kMaxAlpha; i += 256)
+    if (f[i]) atomicAdd(&freq[b * kMaxAlpha + i], f[i]);
+}
+
+}  // namespace
+
+void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
+                 uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
+                 uint32_t *d_n_sym, hipStream_t s) {
+  fill_u32(w.used, 0, (size_t)max_blocks * 8, s);
+  fill_u32(freq, 0, (size_t)max_blocks * kMaxAlpha, s);
+  hipLaunchKernelGGL(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
+  const uint32_t *cb = w.chunk_block;
+  hipLaunchKernelGGL(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used);
+  hipLaunchKernelGGL(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used, d_nb, w.seq, codes);
+  hipLaunchKernelGGL(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
+                     w.plist, w.plen);
+  hipLaunchKernelGGL(k_mtf_chain, dim3(max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.inlist);
+  hipLaunchKernelGGL(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
+                     w.inlist, w.idx);
+  hipLaunchKernelGGL(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);
+  scan_inclusive_max_u32(w.zs, w.zs, nullptr, N, w.scan_tmp, s);
+  hipLaunchKernelGGL(k_rle2_len, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, cb, w.d_n_chunks, blk_start, d_nb,
+                     w.len);
+  scan_exclusive_u32(w.len, w.off, nullptr, N, w.scan_tmp, d_n_sym, s);
+  hipLaunchKernelGGL(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks,
+                     blk_start, d_nb, codes, sym, freq);
+}
+
+}  // namespace pcbz

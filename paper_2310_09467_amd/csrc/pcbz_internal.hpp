@@ -1,0 +1,216 @@
+// pcbz_internal.hpp -- shared declarations of the HIP library (device structs,
+// wave64 helpers and the launchers each kernel file exports to the runtime).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pcbz {
+
+constexpr int kWave = 64;
+constexpr int kNumCand = 4;             // RASTER, VIEW, VIEW_DX, VIEW_DT
+constexpr uint32_t kNone16 = 0xFFFFu;   // "no byte" marker in 16-bit tables
+constexpr int kMaxAlpha = 258;          // bzip2 alphabet bound (256 byte ranks + RUNA/RUNB... + EOB)
+constexpr int kMaxGroups = 6;
+constexpr int kMaxCodeLen = 17;
+constexpr int kGroupSize = 50;          // symbols per selector group
+constexpr uint32_t kPrefixWords = 6144; // 24 KB of header bits per block (bounded below)
+
+// One band of one frame (whole lens rows).
+struct BandDesc {
+  const uint16_t *frame;  // frame base (H x W, row-major)
+  const uint16_t *prev;   // previous frame of the stream or nullptr
+  uint32_t W, pitch, Nt;  // width, lenslet pitch, lens columns
+  uint32_t Rb;            // lens rows in this band
+  uint32_t y0;            // first pixel row of the band
+  uint32_t frame_id;      // index of the frame in the batch
+  uint32_t band_in_frame;
+  uint32_t cand_mask;     // candidates the judge scores
+  uint32_t level;         // bzip2 level 1..9 (block limit 100000*level-19)
+  uint32_t n;             // band bytes = 2*Rb*pitch*W
+  uint64_t off;           // first byte of the band in the concatenated byte space
+  uint32_t blk_slot;      // first block slot of this band
+  uint32_t blk_slots;     // block slots reserved for this band
+};
+
+// Lens-row work item for the rearrangement kernel.
+struct RowItem {
+  uint32_t band;
+  uint32_t s;  // lens row inside the band
+};
+
+// One (band, candidate) entropy-judgement task.
+struct JudgeTask {
+  uint32_t band;
+  uint32_t cand;
+  uint32_t n;         // bytes
+  uint32_t seg_base;  // first 4096-byte segment of this task in the segment tables
+  uint64_t x_off;     // offset of the candidate bytes in the candidate buffer
+};
+
+// A bzip2 block after the first run-length stage (dense list, device-built).
+struct BlockDesc {
+  uint32_t band;
+  uint32_t frame_id;
+  uint32_t raw_start, raw_end;  // global raw byte positions covered
+  uint32_t rle_start, rle_end;  // global positions of its first-stage output
+  uint32_t level;
+  uint32_t crc;                 // CRC-32/BZIP2 of the raw bytes
+};
+
+// Per-block coding state (device-built).
+struct BlockCode {
+  uint32_t n_in_use;
+  uint32_t alpha;
+  uint32_t n_mtf;      // symbols including end-of-block
+  uint32_t sym_start;  // first symbol in the global symbol array
+  uint32_t n_groups;
+  uint32_t n_sel;
+  uint32_t sel_start;  // first selector in the global selector array
+  uint32_t orig_ptr;
+  uint32_t prefix_bits;
+  uint32_t data_bits;
+  uint32_t stream_bytes;
+  uint32_t stream_off;  // byte offset inside its frame's container
+  uint32_t word_start;  // first 32-bit output word of this stream in the writer's index space
+  uint32_t chunk_start; // first 4096-symbol MTF chunk of this block
+  uint32_t n_chunks;
+  uint32_t pad;
+};
+
+// ---------------------------------------------------------------- wave64 helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
+
+// Lanes of `active` whose 8-bit value equals this lane's value.
+__device__ __forceinline__ uint64_t match_any8(uint32_t v, uint64_t active) {
+  uint64_t m = active;
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    uint64_t bal = ballot64((v >> b) & 1u);
+    m &= ((v >> b) & 1u) ? bal : ~bal;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// Binary search: largest i in [0, n) with a[i] <= key (a sorted ascending, a[0] <= key).
+template <typename T>
+__device__ __forceinline__ uint32_t upper_index(const T *a, uint32_t n, T key) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- launchers
+struct CandBufs {
+  uint8_t *p[kNumCand];
+};
+
+// Per-frame output description for the container writer.
+struct FrameOut {
+  uint8_t *out;  // caller's device output buffer
+  uint64_t cap;  // its capacity in bytes
+  uint32_t h, w, pitch, level;
+  uint32_t n_bands;
+  uint32_t band_base;  // first band of this frame in the band table
+};
+
+// scan.hip: device-wide scans over n elements (n read from d_n when non-null,
+// capped by n_max).  `tmp` needs scan_tmp_bytes(n_max) bytes.  In-place is
+// allowed.
+size_t scan_tmp_bytes(size_t n_max);
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
+                        uint32_t *d_total, hipStream_t s);
+void scan_inclusive_max_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
+                            hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+
+// judge.hip
+size_t remap_lds_bytes(uint32_t pitch, uint32_t lens_per_wg);
+void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, uint32_t max_chunks,
+                   uint32_t lens_per_wg, uint32_t pitch_max, CandBufs cb, const uint8_t *forced,
+                   uint32_t write_mask, hipStream_t s);
+void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *tile_task, const uint32_t *tile_local,
+                   uint32_t n_tiles, CandBufs cb, uint16_t *seg_first, uint16_t *seg_last, uint32_t *hist,
+                   const int64_t *tq, unsigned long long *score, hipStream_t s);
+void launch_choose2(const BandDesc *bands, uint32_t n_bands, const int32_t *task_of,
+                    const unsigned long long *score, const JudgeTask *tasks, const uint8_t *forced, uint8_t *choice,
+                    double *entropy, int64_t *score_out, hipStream_t s);
+void launch_gather2(const uint32_t *band_start, uint32_t n_bands, CandBufs cb, const uint8_t *choice,
+                    uint8_t *chosen, uint64_t total, hipStream_t s);
+void launch_validate_forced(const BandDesc *bands, uint32_t n_bands, uint8_t *forced, uint32_t *err,
+                            hipStream_t s);
+
+// rle1.hip
+void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
+                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s);
+void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
+                 const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
+                 uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,
+                 uint32_t *crc_chunk_base, uint32_t *d_n_blocks, uint32_t *d_crc_chunks, hipStream_t s);
+void launch_crc2(const uint8_t *x, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
+                 const uint32_t *crc_chunk_base, const uint32_t *d_crc_chunks, uint32_t max_crc_chunks,
+                 const uint32_t *xpow_chunk, const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s);
+
+// bwt.hip
+struct BwtWork {
+  uint64_t *key[2];
+  uint32_t *val[2];
+  uint32_t *slot;
+  uint32_t *slot2;
+  uint32_t *rank;
+  uint32_t *flag;    // [N+1]
+  uint32_t *flag2;   // [N+1]
+  uint32_t *counts;  // radix tile counts
+  uint32_t *d_u;     // unresolved count (device)
+  void *scan_tmp;
+};
+size_t radix_counts_words(uint32_t n_max);
+int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_start, BwtWork w, uint32_t *sa,
+            uint8_t *L, BlockCode *codes, uint32_t *pinned_u, hipStream_t s);
+
+// mtf.hip
+struct MtfWork {
+  uint8_t *seq;          // [max_blocks * 256] byte -> rank among used bytes
+  uint32_t *used;        // [max_blocks * 8] used-byte bitmaps
+  uint32_t *chunk_block; // [max_chunks + 1] first chunk of each block
+  uint8_t *plist;        // [max_chunks * 256] chunk partial lists
+  uint32_t *plen;        // [max_chunks]
+  uint8_t *inlist;       // [max_chunks * 256]
+  uint8_t *idx;          // [N] MTF indices
+  uint32_t *zs;          // [N]
+  uint32_t *len;         // [N]
+  uint32_t *off;         // [N+1]
+  uint32_t *d_n_chunks;
+  void *scan_tmp;
+};
+void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
+                 uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
+                 uint32_t *d_n_sym, hipStream_t s);
+
+// huff.hip
+void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks, uint32_t max_groups,
+                  BlockCode *codes, const uint32_t *freq, uint8_t *cost, uint32_t *tfreq, uint32_t *group_base,
+                  uint32_t *d_n_groups, uint8_t *sel, uint8_t *lens, uint32_t *code_words, hipStream_t s);
+
+// pack.hip
+void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
+                  const uint32_t *used, const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words,
+                  const uint16_t *sym, const uint32_t *d_n_sym, uint32_t max_sym, uint32_t *prefix,
+                  uint32_t *sym_bits, uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp,
+                  const FrameOut *frames, uint32_t n_frames, const BandDesc *bands, const uint8_t *choice,
+                  uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words,
+                  uint32_t max_words, hipStream_t s);
+
+}  // namespace pcbz

@@ -1,0 +1,260 @@
+// rle1.hip -- bzip2's first run-length stage, greedy block cuts and block CRCs.
+//
+// Runs of equal bytes never cross a band.  A position's offset k inside its
+// run comes from an inclusive max-scan of run-start positions; pieces are
+// k / 255, and a piece of length L emits min(L,4) copies plus, when L >= 4,
+// a count byte L-4 (written by the piece's fourth position).  Output offsets
+// are an exclusive sum-scan of the per-position output lengths.
+//
+// Block cut: pieces are appended while the block stays within
+// 100000*level-19 bytes.  Output ends e(i) = off[i] + len[i] are monotone, so
+// the first piece that does not fit is found by binary search.
+//
+// CRC-32/BZIP2 of each block's raw bytes: every 256-byte chunk, counted back
+// from the block end, gets its zero-init register value R (table-driven,
+// MSB-first, polynomial 0x04C11DB7); the block register is the XOR of
+// R_j * x^(8*256*j) mod P over chunks, plus 0xFFFFFFFF * x^(8m) for the
+// initial value; the final XOR with 0xFFFFFFFF gives the CRC.
+#include "pcbz_internal.hpp"
+
+namespace pcbz {
+namespace {
+
+constexpr uint32_t kPoly = 0x04C11DB7u;
+constexpr int kCrcChunk = 256;
+
+__device__ __forceinline__ uint32_t piece_len_out(uint32_t o) { return o < 3 ? 1u : (o == 3 ? 2u : 0u); }
+
+__global__ void k_r1_starts(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N,
+                            uint32_t *v) {
+  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+  if (i0 >= N) return;
+  const uint32_t i1 = (uint32_t)min<uint64_t>(i0 + 16, N);
+  uint32_t b = upper_index(band_start, n_bands, (uint32_t)i0);
+  uint32_t next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
+  uint32_t prevc = i0 > 0 ? x[i0 - 1] : 0u;
+  for (uint32_t i = (uint32_t)i0; i < i1; i++) {
+    if (i == next) {
+      b++;
+      next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
+    }
+    uint32_t c = x[i];
+    bool start = (i == band_start[b]) || c != prevc;
+    v[i] = start ? i : 0u;
+    prevc = c;
+  }
+}
+
+__global__ void k_r1_len(const uint32_t *runstart, uint32_t N, uint32_t *len) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
+    len[i] = piece_len_out((uint32_t)((i - runstart[i]) % 255u));
+}
+
+__global__ void k_r1_write(const uint32_t *band_start, uint32_t n_bands, uint32_t N, const uint8_t *x,
+                           const uint32_t *runstart, const uint32_t *off, uint8_t *rle) {
+  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < N; gi += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = (uint32_t)gi;
+    const uint32_t o = (i - runstart[i]) % 255u;
+    if (o > 3) continue;
+    const uint8_t c = x[i];
+    const uint32_t q = off[i];
+    rle[q] = c;
+    if (o == 3) {
+      uint32_t b = upper_index(band_start, n_bands, i);
+      uint32_t bend = b + 1 < n_bands ? band_start[b + 1] : N;
+      uint32_t lim = min(bend, i + 252u);
+      uint32_t j = i + 1;
+      while (j < lim && x[j] == c) j++;
+      rle[q + 1] = (uint8_t)(j - i - 1);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t out_end(const uint32_t *runstart, const uint32_t *off, uint32_t i) {
+  return off[i] + piece_len_out((i - runstart[i]) % 255u);
+}
+
+// One thread per band: greedy cuts into block slots.
+__global__ void k_cut(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
+                      const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
+                      uint32_t *err) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n_bands) return;
+  const BandDesc B = bands[b];
+  const uint32_t s0 = band_start[b], e0 = s0 + B.n;
+  const uint32_t lim = 100000u * B.level - 19u;
+  uint32_t P = s0, q = off[s0], k = 0;
+  for (;;) {
+    const uint32_t limit = q + lim;
+    uint32_t cut = e0;
+    if (off[e0] > limit) {
+      uint32_t lo = P, hi = e0 - 1;  // out_end(hi) = off[e0] > limit
+      while (lo < hi) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (out_end(runstart, off, mid) > limit) hi = mid; else lo = mid + 1;
+      }
+      cut = lo - (lo - runstart[lo]) % 255u;
+      if (cut <= P) {  // cannot happen for consistent offsets; never loop without progress
+        atomicOr(err, 2u);
+        break;
+      }
+    }
+    if (k < B.blk_slots) {
+      BlockDesc d;
+      d.band = b;
+      d.frame_id = B.frame_id;
+      d.raw_start = P;
+      d.raw_end = cut;
+      d.rle_start = q;
+      d.rle_end = off[cut];
+      d.level = B.level;
+      d.crc = 0;
+      slots[B.blk_slot + k] = d;
+    } else {
+      atomicOr(err, 1u);
+    }
+    k++;
+    if (cut >= e0) break;
+    P = cut;
+    q = off[cut];
+  }
+  slot_count[b] = min(k, B.blk_slots);
+}
+
+// Dense block list in band order, with CRC chunk bases.  One workgroup.
+__global__ __launch_bounds__(1024) void k_blocks_compact(const BandDesc *bands, uint32_t n_bands,
+                                                         const BlockDesc *slots, const uint32_t *slot_count,
+                                                         BlockDesc *blocks, uint32_t *blk_raw_start,
+                                                         uint32_t *blk_rle_start, uint32_t *crc_chunk_base,
+                                                         uint32_t *d_n_blocks, uint32_t *d_crc_chunks) {
+  __shared__ uint32_t sh[1024];
+  __shared__ uint32_t carry_blocks;
+  if (threadIdx.x == 0) carry_blocks = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < n_bands; base += 1024) {
+    uint32_t b = base + threadIdx.x;
+    uint32_t cnt = b < n_bands ? slot_count[b] : 0;
+    sh[threadIdx.x] = cnt;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      uint32_t v = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += v;
+      __syncthreads();
+    }
+    uint32_t excl = carry_blocks + sh[threadIdx.x] - cnt;
+    if (b < n_bands)
+      for (uint32_t k = 0; k < cnt; k++) blocks[excl + k] = slots[bands[b].blk_slot + k];
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_blocks += sh[1023];
+    __syncthreads();
+  }
+  const uint32_t nb = carry_blocks;
+  // raw / rle starts and CRC chunk bases (serial over blocks, cheap)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < nb; k++) {
+      blk_raw_start[k] = blocks[k].raw_start;
+      blk_rle_start[k] = blocks[k].rle_start;
+      crc_chunk_base[k] = acc;
+      acc += (blocks[k].raw_end - blocks[k].raw_start + kCrcChunk - 1) / kCrcChunk;
+    }
+    crc_chunk_base[nb] = acc;
+    blk_raw_start[nb] = nb ? blocks[nb - 1].raw_end : 0;
+    blk_rle_start[nb] = nb ? blocks[nb - 1].rle_end : 0;
+    *d_n_blocks = nb;
+    *d_crc_chunks = acc;
+  }
+}
+
+__device__ uint32_t gf_mulmod(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+  for (int i = 31; i >= 0; i--) {
+    r = (r & 0x80000000u) ? (r << 1) ^ kPoly : (r << 1);
+    if ((b >> i) & 1u) r ^= a;
+  }
+  return r;
+}
+
+// One thread per 256-byte chunk counted back from its block's end.
+__global__ __launch_bounds__(256) void k_crc_chunks(const uint8_t *x, const BlockDesc *blocks,
+                                                    const uint32_t *d_n_blocks, const uint32_t *crc_chunk_base,
+                                                    const uint32_t *d_crc_chunks, const uint32_t *xpow_chunk,
+                                                    uint32_t *crc_acc) {
+  __shared__ uint32_t T[256];
+  {
+    uint32_t r = (uint32_t)threadIdx.x << 24;
+    for (int k = 0; k < 8; k++) r = (r & 0x80000000u) ? (r << 1) ^ kPoly : (r << 1);
+    T[threadIdx.x] = r;
+  }
+  __syncthreads();
+  const uint32_t nchunks = *d_crc_chunks;
+  const uint32_t nb = *d_n_blocks;
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += gridDim.x * blockDim.x) {
+    const uint32_t k = upper_index(crc_chunk_base, nb, c);
+    const uint32_t j = c - crc_chunk_base[k];
+    const BlockDesc B = blocks[k];
+    const uint32_t hi = B.raw_end - j * kCrcChunk;
+    const uint32_t lo = hi - B.raw_start > (uint32_t)kCrcChunk ? hi - kCrcChunk : B.raw_start;
+    uint32_t r = 0;
+    for (uint32_t i = lo; i < hi; i++) r = (r << 8) ^ T[(r >> 24) ^ x[i]];
+    r = gf_mulmod(r, xpow_chunk[j]);
+    atomicXor(&crc_acc[k], r);
+  }
+}
+
+__device__ uint32_t xpow8_bytes(uint32_t m, const uint32_t *xpow2) {
+  // x^(8m) mod P from x^(2^k) mod P, k = 0..63
+  uint64_t e = (uint64_t)m * 8u;
+  uint32_t r = 1u;  // x^0
+  for (int k = 0; e; k++, e >>= 1)
+    if (e & 1u) r = gf_mulmod(r, xpow2[k]);
+  return r;
+}
+
+__global__ void k_crc_final(BlockDesc *blocks, const uint32_t *d_n_blocks, const uint32_t *crc_acc,
+                            const uint32_t *xpow2) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= *d_n_blocks) return;
+  const uint32_t m = blocks[k].raw_end - blocks[k].raw_start;
+  const uint32_t init = gf_mulmod(0xFFFFFFFFu, xpow8_bytes(m, xpow2));
+  blocks[k].crc = crc_acc[k] ^ init ^ 0xFFFFFFFFu;
+}
+
+}  // namespace
+
+void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
+                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s) {
+  if (!N) return;
+  uint32_t thr = (N + 15) / 16;
+  hipLaunchKernelGGL(k_r1_starts, dim3((thr + 255) / 256), dim3(256), 0, s, band_start, n_bands, x, N, runstart);
+  scan_inclusive_max_u32(runstart, runstart, nullptr, N, scan_tmp, s);
+  uint32_t grid = std::min<uint32_t>((N + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_r1_len, dim3(grid), dim3(256), 0, s, runstart, N, len);
+  scan_exclusive_u32(len, off, nullptr, N, scan_tmp, off + N, s);
+  hipLaunchKernelGGL(k_r1_write, dim3(grid), dim3(256), 0, s, band_start, n_bands, N, x, runstart, off, rle);
+}
+
+void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
+                 const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
+                 uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,
+                 uint32_t *crc_chunk_base, uint32_t *d_n_blocks, uint32_t *d_crc_chunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_cut, dim3((n_bands + 63) / 64), dim3(64), 0, s, bands, n_bands, band_start, N, runstart, off,
+                     slots, slot_count, err);
+  hipLaunchKernelGGL(k_blocks_compact, dim3(1), dim3(1024), 0, s, bands, n_bands, slots, slot_count, blocks,
+                     blk_raw_start, blk_rle_start, crc_chunk_base, d_n_blocks, d_crc_chunks);
+}
+
+void launch_crc2(const uint8_t *x, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
+                 const uint32_t *crc_chunk_base, const uint32_t *d_crc_chunks, uint32_t max_crc_chunks,
+                 const uint32_t *xpow_chunk, const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s) {
+  fill_u32(crc_acc, 0, max_blocks, s);
+  uint32_t grid = std::min<uint32_t>((max_crc_chunks + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(k_crc_chunks, dim3(grid), dim3(256), 0, s, x, blocks, d_n_blocks, crc_chunk_base, d_crc_chunks,
+                     xpow_chunk, crc_acc);
+  hipLaunchKernelGGL(k_crc_final, dim3((max_blocks + 255) / 256), dim3(256), 0, s, blocks, d_n_blocks, crc_acc,
+                     xpow2);
+}
+
+}  // namespace pcbz

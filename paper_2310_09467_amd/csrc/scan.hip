@@ -1,0 +1,182 @@
+// scan.hip -- device-wide prefix scans (sum and max over uint32) and fills.
+//
+// Three phases: per-tile reduction, a single-workgroup scan of the tile
+// aggregates, then a per-tile rescan that applies the carry.  A tile is
+// 256 threads x 16 items, staged through LDS so that global accesses stay
+// coalesced while each thread scans 16 consecutive items.  Sums wrap mod
+// 2^32, so differences of prefix values inside any segment whose own total
+// stays below 2^32 are exact.
+#include "pcbz_internal.hpp"
+
+namespace pcbz {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kThreads * kItems;
+constexpr int kPad = kTile + kTile / 32;
+
+struct OpSum {
+  static __device__ __forceinline__ uint32_t f(uint32_t a, uint32_t b) { return a + b; }
+  static constexpr uint32_t id = 0u;
+};
+struct OpMax {
+  static __device__ __forceinline__ uint32_t f(uint32_t a, uint32_t b) { return a > b ? a : b; }
+  static constexpr uint32_t id = 0u;
+};
+
+__device__ __forceinline__ uint32_t get_n(const uint32_t *d_n, uint32_t n_max) {
+  if (!d_n) return n_max;
+  uint32_t n = *d_n;
+  return n < n_max ? n : n_max;
+}
+
+__device__ __forceinline__ int padi(int j) { return j + (j >> 5); }
+
+// Workgroup scan of one value per thread: inclusive and exclusive prefix of
+// this thread, and the workgroup total.
+template <typename Op>
+__device__ void block_scan(uint32_t v, uint32_t *sh_wave, uint32_t &incl, uint32_t &excl, uint32_t &total) {
+  const int lane = lane_id();
+  const int wave = threadIdx.x / kWave;
+  const int nwaves = blockDim.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t o = __shfl_up(x, d);
+    if (lane >= d) x = Op::f(o, x);
+  }
+  uint32_t xe = __shfl_up(x, 1);
+  if (lane == 0) xe = Op::id;
+  if (lane == kWave - 1) sh_wave[wave] = x;
+  __syncthreads();
+  uint32_t carry = Op::id, t = Op::id;
+  for (int w = 0; w < nwaves; w++) {
+    if (w < wave) carry = Op::f(carry, sh_wave[w]);
+    t = Op::f(t, sh_wave[w]);
+  }
+  __syncthreads();
+  incl = Op::f(carry, x);
+  excl = Op::f(carry, xe);
+  total = t;
+}
+
+template <typename Op>
+__global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *in, const uint32_t *d_n, uint32_t n_max,
+                                                     uint32_t *aggs) {
+  __shared__ uint32_t sh_wave[kThreads / kWave];
+  const uint32_t n = get_n(d_n, n_max);
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  uint32_t acc = Op::id;
+  if (base < n) {
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+      uint64_t j = base + (uint64_t)i * kThreads + threadIdx.x;
+      if (j < n) acc = Op::f(acc, in[j]);
+    }
+  }
+  uint32_t inc, exc, total;
+  block_scan<Op>(acc, sh_wave, inc, exc, total);
+  if (threadIdx.x == 0) aggs[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile aggregates in place (one workgroup of 1024).
+template <typename Op>
+__global__ __launch_bounds__(1024) void k_scan_aggs(uint32_t *aggs, const uint32_t *d_n, uint32_t n_max,
+                                                    uint32_t *d_total) {
+  __shared__ uint32_t sh_wave[1024 / kWave];
+  const uint32_t n = get_n(d_n, n_max);
+  const uint32_t ntiles = (n + kTile - 1) / kTile;
+  uint32_t carry = Op::id;
+  for (uint32_t base = 0; base < ntiles; base += 1024) {
+    uint32_t j = base + threadIdx.x;
+    uint32_t v = j < ntiles ? aggs[j] : Op::id;
+    uint32_t inc, own_excl, total;
+    block_scan<Op>(v, sh_wave, inc, own_excl, total);
+    if (j < ntiles) aggs[j] = Op::f(carry, own_excl);
+    carry = Op::f(carry, total);
+    __syncthreads();
+  }
+  if (d_total && threadIdx.x == 0) *d_total = carry;
+}
+
+template <typename Op, bool kInclusive>
+__global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t *in, uint32_t *out, const uint32_t *d_n,
+                                                        uint32_t n_max, const uint32_t *aggs) {
+  __shared__ uint32_t tile[kPad];
+  __shared__ uint32_t sh_wave[kThreads / kWave];
+  const uint32_t n = get_n(d_n, n_max);
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  if (base >= n) return;
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    int j = i * kThreads + threadIdx.x;
+    uint64_t g = base + j;
+    tile[padi(j)] = g < n ? in[g] : Op::id;
+  }
+  __syncthreads();
+  uint32_t v[kItems];
+  uint32_t acc = Op::id;
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    v[i] = tile[padi(threadIdx.x * kItems + i)];
+    acc = Op::f(acc, v[i]);
+  }
+  uint32_t inc, exc, total;
+  block_scan<Op>(acc, sh_wave, inc, exc, total);
+  uint32_t run = Op::f(aggs[blockIdx.x], exc);
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    uint32_t nv = Op::f(run, v[i]);
+    tile[padi(threadIdx.x * kItems + i)] = kInclusive ? nv : run;
+    run = nv;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kItems; i++) {
+    int j = i * kThreads + threadIdx.x;
+    uint64_t g = base + j;
+    if (g < n) out[g] = tile[padi(j)];
+  }
+}
+
+__global__ void k_fill(uint32_t *p, uint32_t v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+template <typename Op, bool kInclusive>
+void run_scan(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp, uint32_t *d_total,
+              hipStream_t s) {
+  if (n_max == 0) {
+    if (d_total) fill_u32(d_total, 0, 1, s);
+    return;
+  }
+  uint32_t ntiles = (n_max + kTile - 1) / kTile;
+  uint32_t *aggs = (uint32_t *)tmp;
+  hipLaunchKernelGGL((k_reduce<Op>), dim3(ntiles), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
+  hipLaunchKernelGGL((k_scan_aggs<Op>), dim3(1), dim3(1024), 0, s, aggs, d_n, n_max, d_total);
+  hipLaunchKernelGGL((k_downsweep<Op, kInclusive>), dim3(ntiles), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(size_t n_max) { return ((n_max + kTile - 1) / kTile + 64) * sizeof(uint32_t); }
+
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
+                        uint32_t *d_total, hipStream_t s) {
+  run_scan<OpSum, false>(in, out, d_n, n_max, tmp, d_total, s);
+}
+
+void scan_inclusive_max_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
+                            hipStream_t s) {
+  run_scan<OpMax, true>(in, out, d_n, n_max, tmp, nullptr, s);
+}
+
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
+}
+
+}  // namespace pcbz
