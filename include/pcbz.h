@@ -110,6 +110,18 @@ int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint1
 int pcbz_last_stats(const pcbz_ctx *ctx, uint64_t *raw_bytes, uint64_t *rle_bytes, uint32_t *n_blocks,
                     uint32_t *bwt_rounds);
 
+/* Kernel tracing for profiling (process-wide).  When enabled, every kernel
+ * launch whose name equals `filter` (all launches when filter is NULL) is
+ * bracketed by HIP events on the launch stream.  pcbz_trace_read waits for
+ * the recorded events and returns, per kernel name, the summed milliseconds,
+ * the launch count and the summed algorithmic bytes (what the step itself
+ * must read and write, as counted by the launcher; 0 where not counted).
+ * Names are written into rows of `name_stride` bytes.  *n receives the number
+ * of traced names (which may exceed `max`).  Any output array may be NULL. */
+int pcbz_trace_enable(pcbz_ctx *ctx, int on, const char *filter);
+int pcbz_trace_read(pcbz_ctx *ctx, char *names, size_t name_stride, double *ms, uint64_t *calls, uint64_t *bytes,
+                    uint32_t max, uint32_t *n, int reset);
+
 #ifdef __cplusplus
 }
 #endif

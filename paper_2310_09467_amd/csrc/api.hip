@@ -14,6 +14,86 @@
 using namespace pcbz;
 
 namespace pcbz {
+
+// ---------------------------------------------------------------- tracing
+bool g_trace_on = false;
+
+namespace {
+struct TraceRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+struct Tracer {
+  std::string filter;
+  std::vector<TraceRec> open, done;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<uint64_t> calls;
+  std::vector<uint64_t> bytes;
+  size_t slot(const char *name) {
+    size_t i = 0;
+    while (i < names.size() && names[i] != name) i++;
+    if (i == names.size()) {
+      names.push_back(name);
+      ms.push_back(0.0);
+      calls.push_back(0);
+      bytes.push_back(0);
+    }
+    return i;
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  // folds finished records into the per-name totals (waits for their events)
+  void collect() {
+    for (TraceRec &r : done) {
+      float t = 0.f;
+      (void)hipEventSynchronize(r.b);
+      (void)hipEventElapsedTime(&t, r.a, r.b);
+      const size_t i = slot(r.name);
+      ms[i] += t;
+      calls[i]++;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    done.clear();
+  }
+};
+Tracer g_tracer;
+}  // namespace
+
+void trace_begin_impl(const char *name, hipStream_t s) {
+  if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
+  TraceRec r{name, g_tracer.ev(), g_tracer.ev()};
+  (void)hipEventRecord(r.a, s);
+  g_tracer.open.push_back(r);
+}
+
+void trace_bytes_impl(const char *name, uint64_t bytes) {
+  if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
+  g_tracer.bytes[g_tracer.slot(name)] += bytes;
+}
+
+void trace_end_impl(const char *name, hipStream_t s) {
+  for (size_t i = g_tracer.open.size(); i-- > 0;) {
+    if (g_tracer.open[i].name == name || strcmp(g_tracer.open[i].name, name) == 0) {
+      (void)hipEventRecord(g_tracer.open[i].b, s);
+      g_tracer.done.push_back(g_tracer.open[i]);
+      g_tracer.open.erase(g_tracer.open.begin() + i);
+      break;
+    }
+  }
+  if (g_tracer.done.size() > 4096) g_tracer.collect();
+}
+
 int decode_container_host(const uint8_t *in, size_t in_len, const uint16_t *prev_host, uint16_t *frame_host,
                           std::string &err);
 int peek_container(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands,
@@ -29,6 +109,7 @@ struct pcbz_ctx {
   int64_t *d_tq = nullptr;
   size_t tq_n = 0;
   uint32_t *d_xpow2 = nullptr;
+  uint32_t *d_xbyte = nullptr;  // x^(8r) mod P, r < 256
   uint32_t *d_xchunk = nullptr;
   size_t xchunk_n = 0;
   uint8_t *h_stage = nullptr;
@@ -186,11 +267,11 @@ int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, 
           T.band = bi;
           T.cand = id;
           T.n = B.n;
+          const uint32_t tiles = (B.n + 65535) / 65536;  // 16 segments of 4096 bytes per workgroup
           T.seg_base = P.segs;
           T.x_off = B.off;
-          P.segs += (B.n + 4095) / 4096;
+          P.segs += tiles;
           t = (int32_t)P.tasks.size();
-          const uint32_t tiles = (B.n + 65535) / 65536;
           for (uint32_t q = 0; q < tiles; q++) {
             P.tile_task.push_back((uint32_t)t);
             P.tile_local.push_back(q);
@@ -368,6 +449,11 @@ int ensure_tables(pcbz_ctx *ctx, uint32_t band_n_max) {
     for (int k = 1; k < 64; k++) x[k] = h_mulmod(x[k - 1], x[k - 1]);
     HIPCHK(ctx, hipMalloc((void **)&ctx->d_xpow2, sizeof x));
     HIPCHK(ctx, hipMemcpy(ctx->d_xpow2, x, sizeof x, hipMemcpyHostToDevice));
+    uint32_t xb[256];
+    xb[0] = 1u;
+    for (int r = 1; r < 256; r++) xb[r] = h_mulmod(xb[r - 1], 0x100u);  // times x^8
+    HIPCHK(ctx, hipMalloc((void **)&ctx->d_xbyte, sizeof xb));
+    HIPCHK(ctx, hipMemcpy(ctx->d_xbyte, xb, sizeof xb, hipMemcpyHostToDevice));
   }
   const size_t need_chunks = (size_t)band_n_max / 256 + 4;
   if (need_chunks > ctx->xchunk_n) {
@@ -487,8 +573,7 @@ int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, 
   launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, s);
   launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
               w.blk_raw_start, w.blk_rle_start, w.crc_chunk_base, w.ctr + 1, w.ctr + 2, s);
-  const uint32_t max_crc_chunks = N / 256 + w.max_blocks + 1;
-  launch_crc2(w.chosen, w.blocks, w.ctr + 1, w.max_blocks, w.crc_chunk_base, w.ctr + 2, max_crc_chunks, ctx->d_xchunk,
+  launch_crc2(w.chosen, N, w.blocks, w.ctr + 1, w.max_blocks, w.blk_raw_start, ctx->d_xchunk, ctx->d_xbyte,
               ctx->d_xpow2, w.crc_acc, s);
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_small + 16, w.r1off + N, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -567,6 +652,7 @@ void pcbz_destroy(pcbz_ctx *c) {
   if (c->arena) (void)hipFree(c->arena);
   if (c->d_tq) (void)hipFree(c->d_tq);
   if (c->d_xpow2) (void)hipFree(c->d_xpow2);
+  if (c->d_xbyte) (void)hipFree(c->d_xbyte);
   if (c->d_xchunk) (void)hipFree(c->d_xchunk);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_small) (void)hipHostFree(c->h_small);
@@ -676,6 +762,39 @@ int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint1
   if (st) return st;
   HIPCHK(ctx, hipMemcpyAsync(d_out, frame.data(), npix * 2, hipMemcpyHostToDevice, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  return PCBZ_OK;
+}
+
+int pcbz_trace_enable(pcbz_ctx *c, int on, const char *filter) {
+  if (!c) return PCBZ_EINVAL;
+  pcbz::g_tracer.collect();
+  pcbz::g_tracer.filter = filter ? filter : "";
+  pcbz::g_trace_on = on != 0;
+  return PCBZ_OK;
+}
+
+int pcbz_trace_read(pcbz_ctx *c, char *names, size_t name_stride, double *ms, uint64_t *calls, uint64_t *bytes,
+                    uint32_t max, uint32_t *n, int reset) {
+  if (!c || !n) return PCBZ_EINVAL;
+  HIPCHK(c, hipSetDevice(c->device));
+  pcbz::g_tracer.collect();
+  const uint32_t k = (uint32_t)std::min<size_t>(max, pcbz::g_tracer.names.size());
+  for (uint32_t i = 0; i < k; i++) {
+    if (names && name_stride) {
+      strncpy(names + i * name_stride, pcbz::g_tracer.names[i].c_str(), name_stride - 1);
+      names[i * name_stride + name_stride - 1] = 0;
+    }
+    if (ms) ms[i] = pcbz::g_tracer.ms[i];
+    if (calls) calls[i] = pcbz::g_tracer.calls[i];
+    if (bytes) bytes[i] = pcbz::g_tracer.bytes[i];
+  }
+  *n = (uint32_t)pcbz::g_tracer.names.size();
+  if (reset) {
+    pcbz::g_tracer.names.clear();
+    pcbz::g_tracer.ms.clear();
+    pcbz::g_tracer.calls.clear();
+    pcbz::g_tracer.bytes.clear();
+  }
   return PCBZ_OK;
 }
 

@@ -15,6 +15,9 @@
 // keys with 32-bit values: per-tile digit counts, one exclusive scan over
 // the digit-major count table, then a stable scatter that ranks equal digits
 // inside each wavefront with ballot matching.
+#include <cstdio>
+#include <cstdlib>
+
 #include "pcbz_internal.hpp"
 
 namespace pcbz {
@@ -207,10 +210,12 @@ int radix_sort(uint64_t *keys[2], uint32_t *vals[2], uint32_t n, int bits, uint3
   if (n <= 1 || bits <= 0) return cur;
   const uint32_t ntiles = (n + kRsTile - 1) / kRsTile;
   for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], nullptr, n, shift, counts, ntiles);
+    PCBZ_LAUNCH(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], nullptr, n, shift, counts, ntiles);
     scan_exclusive_u32(counts, counts, nullptr, 256u * ntiles, scan_tmp, nullptr, s);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+    PCBZ_LAUNCH(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
                        vals[cur ^ 1], nullptr, n, shift, counts, ntiles);
+    // a scatter pass reads and writes every 8-byte key and 4-byte value once
+    trace_bytes("k_rs_scatter", 24ull * n);
     cur ^= 1;
   }
   return cur;
@@ -223,7 +228,7 @@ int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_sta
   uint64_t *keys[2] = {w.key[0], w.key[1]};
   uint32_t *vals[2] = {w.val[0], w.val[1]};
   uint32_t *slot = w.slot, *slot2 = w.slot2;
-  hipLaunchKernelGGL(k_bwt_init, dim3(grid_for(N)), dim3(256), 0, s, rle, N, blk_start, nb, keys[0], vals[0], slot);
+  PCBZ_LAUNCH(k_bwt_init, dim3(grid_for(N)), dim3(256), 0, s, rle, N, blk_start, nb, keys[0], vals[0], slot);
   int cur = radix_sort(keys, vals, N, 32 + bits_for(nb - 1), w.counts, w.scan_tmp, s);
   const int rbits = bits_for(N - 1);
   uint32_t U = N;
@@ -231,17 +236,18 @@ int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_sta
   int rounds = 0;
   for (;;) {
     // new ranks: max-scan of group-start slots
-    hipLaunchKernelGGL(k_bwt_heads, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], slot, U, w.flag);
+    PCBZ_LAUNCH(k_bwt_heads, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], slot, U, w.flag);
     scan_inclusive_max_u32(w.flag, w.flag, nullptr, U, w.scan_tmp, s);
-    hipLaunchKernelGGL(k_bwt_update, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, U,
+    PCBZ_LAUNCH(k_bwt_update, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, U,
                        blk_start, nb, compared, w.rank, sa, w.flag2);
     scan_exclusive_u32(w.flag2, w.flag, nullptr, U, w.scan_tmp, w.d_u, s);
-    hipLaunchKernelGGL(k_bwt_compact, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, U,
+    PCBZ_LAUNCH(k_bwt_compact, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, U,
                        vals[cur ^ 1], slot2);
     hipMemcpyAsync(pinned_u, w.d_u, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
     U = *pinned_u;
     rounds++;
+    if (getenv("PCBZ_DEBUG_BWT")) fprintf(stderr, "pcbz bwt: N=%u round %d compared=%u unresolved=%u\n", N, rounds, compared, U);
     if (U == 0) break;
     if (rounds > 40 || compared >= (1u << 31)) return -1;  // doubling must finish once 2h reaches the block length
     // compact list is now in (vals[cur^1], slot2)
@@ -250,7 +256,7 @@ int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_sta
     slot = slot2;
     slot2 = t;
     const uint32_t h = compared;
-    hipLaunchKernelGGL(k_bwt_keys, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], U, w.rank, blk_start, nb, h, rbits,
+    PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], U, w.rank, blk_start, nb, h, rbits,
                        keys[cur]);
     // sort keys[cur]/vals[cur]; radix_sort sorts buffer 0, so arrange the pair
     uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
@@ -259,7 +265,7 @@ int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_sta
     if (r == 1) cur ^= 1;
     compared = compared * 2;
   }
-  hipLaunchKernelGGL(k_bwt_emit, dim3(grid_for(N)), dim3(256), 0, s, sa, rle, N, blk_start, nb, L, codes);
+  PCBZ_LAUNCH(k_bwt_emit, dim3(grid_for(N)), dim3(256), 0, s, sa, rle, N, blk_start, nb, L, codes);
   return rounds;
 }
 

@@ -77,11 +77,33 @@ __global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const u
                                                     const uint32_t *d_n_groups, const uint8_t *cost, uint8_t *sel,
                                                     uint32_t *tfreq) {
   __shared__ uint32_t tf[kMaxGroups * kMaxAlpha];
+  __shared__ uint64_t c03[kMaxAlpha];  // costs of tables 0..3 in 16-bit lanes (a group sums to <= 50*17)
+  __shared__ uint32_t c45[kMaxAlpha];  // tables 4..5
+  __shared__ uint16_t ssym[256 * kGroupSize];
   const uint32_t ngroups = *d_n_groups, nb = *d_nb;
   const uint32_t g0 = blockIdx.x * blockDim.x;
   if (g0 >= ngroups) return;
   for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += 256) tf[i] = 0;
   const uint32_t b0 = upper_index(group_base, nb, g0);
+  const BlockCode C0 = codes[b0];
+  {
+    const uint8_t *cst = cost + (size_t)b0 * kMaxGroups * kMaxAlpha;
+    for (uint32_t s = threadIdx.x; s < C0.alpha; s += 256) {
+      c03[s] = (uint64_t)cst[s] | ((uint64_t)cst[kMaxAlpha + s] << 16) | ((uint64_t)cst[2 * kMaxAlpha + s] << 32) |
+               ((uint64_t)cst[3 * kMaxAlpha + s] << 48);
+      c45[s] = (uint32_t)cst[4 * kMaxAlpha + s] | ((uint32_t)cst[5 * kMaxAlpha + s] << 16);
+    }
+  }
+  // this workgroup's symbols, staged with coalesced loads
+  const uint32_t first_sym = C0.sym_start + (g0 - group_base[b0]) * kGroupSize;
+  uint32_t end_sym;
+  {
+    const uint32_t gl = min(g0 + 256u, ngroups) - 1u;
+    const uint32_t bl = upper_index(group_base, nb, gl);
+    const BlockCode CL = codes[bl];
+    end_sym = min(CL.sym_start + (gl - group_base[bl]) * kGroupSize + kGroupSize, CL.sym_start + CL.n_mtf);
+  }
+  stage_to_lds(ssym, sym + first_sym, end_sym - first_sym);
   __syncthreads();
   const uint32_t gi = g0 + threadIdx.x;
   if (gi < ngroups) {
@@ -90,12 +112,28 @@ __global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const u
     const uint32_t j = gi - group_base[b];
     const uint32_t lo = C.sym_start + j * kGroupSize;
     const uint32_t hi = min(C.sym_start + C.n_mtf, lo + kGroupSize);
-    const uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
     uint32_t c[kMaxGroups] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t k = lo; k < hi; k++) {
-      const uint32_t s = sym[k];
+    if (b == b0) {
+      uint64_t a03 = 0;
+      uint32_t a45 = 0;
+      for (uint32_t k = lo; k < hi; k++) {
+        const uint32_t s = ssym[k - first_sym];
+        a03 += c03[s];
+        a45 += c45[s];
+      }
+      c[0] = (uint32_t)(a03 & 0xFFFFu);
+      c[1] = (uint32_t)((a03 >> 16) & 0xFFFFu);
+      c[2] = (uint32_t)((a03 >> 32) & 0xFFFFu);
+      c[3] = (uint32_t)(a03 >> 48);
+      c[4] = a45 & 0xFFFFu;
+      c[5] = a45 >> 16;
+    } else {
+      const uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
+      for (uint32_t k = lo; k < hi; k++) {
+        const uint32_t s = ssym[k - first_sym];
 #pragma unroll
-      for (int g = 0; g < kMaxGroups; g++) c[g] += cst[g * kMaxAlpha + s];
+        for (int g = 0; g < kMaxGroups; g++) c[g] += cst[g * kMaxAlpha + s];
+      }
     }
     uint32_t best = 0, bc = c[0];
     for (uint32_t g = 1; g < C.n_groups; g++)
@@ -105,10 +143,10 @@ __global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const u
       }
     sel[C.sel_start + j] = (uint8_t)best;
     if (b == b0) {
-      for (uint32_t k = lo; k < hi; k++) atomicAdd(&tf[best * kMaxAlpha + sym[k]], 1u);
+      for (uint32_t k = lo; k < hi; k++) atomicAdd(&tf[best * kMaxAlpha + ssym[k - first_sym]], 1u);
     } else {
       uint32_t *t = tfreq + ((size_t)b * kMaxGroups + best) * kMaxAlpha;
-      for (uint32_t k = lo; k < hi; k++) atomicAdd(&t[sym[k]], 1u);
+      for (uint32_t k = lo; k < hi; k++) atomicAdd(&t[ssym[k - first_sym]], 1u);
     }
   }
   __syncthreads();
@@ -134,54 +172,58 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t *a, uint32_t n, uint
   return lo;
 }
 
-// One wavefront per (block, table).
-__global__ __launch_bounds__(64) void k_tab_lengths(const uint32_t *d_nb, const BlockCode *codes, uint32_t *tfreq,
-                                                    uint8_t *cost, uint8_t *lens, uint32_t *code_words, int last) {
+// One workgroup of 512 threads per (block, table): each leaf and each
+// package of a level has its own thread, so a level costs one binary search.
+constexpr int kPmThreads = 512;
+
+__global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb, const BlockCode *codes,
+                                                            uint32_t *tfreq, uint8_t *cost, uint8_t *lens,
+                                                            uint32_t *code_words, int last) {
+  __shared__ uint32_t key_s[kMaxAlpha];
   __shared__ uint32_t lw[kMaxAlpha];
   __shared__ uint16_t lsym[kMaxAlpha];
   __shared__ uint32_t wt[2][kMaxItems];
   __shared__ uint32_t pw[kMaxItems / 2 + 2];
   __shared__ uint8_t pk[kLevels + 1][kMaxItems];
   __shared__ uint8_t ln[kMaxAlpha];
+  __shared__ uint32_t nlen[kMaxCodeLen + 2], base[kMaxCodeLen + 2];
   const uint32_t b = blockIdx.x / kMaxGroups, g = blockIdx.x % kMaxGroups;
   if (b >= *d_nb) return;
   const BlockCode C = codes[b];
   if (g >= C.n_groups) return;
-  const uint32_t n = C.alpha;
-  const int lane = lane_id();
+  const uint32_t n = C.alpha, t = threadIdx.x;
   uint32_t *tfr = tfreq + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
-  // leaves sorted by (weight, symbol)
-  for (uint32_t s = lane; s < n; s += 64) {
-    const uint32_t ws = max(tfr[s], 1u);
-    const uint32_t key = (ws << 9) | s;
+  // leaves sorted by (weight, symbol): rank = number of smaller keys
+  if (t < n) key_s[t] = (max(tfr[t], 1u) << 9) | t;
+  if (t < kMaxCodeLen + 2) nlen[t] = 0;
+  __syncthreads();
+  if (t < n) {
+    const uint32_t key = key_s[t];
     uint32_t r = 0;
-    for (uint32_t t = 0; t < n; t++) {
-      const uint32_t wt2 = max(tfr[t], 1u);
-      r += ((wt2 << 9) | t) < key ? 1u : 0u;
-    }
-    lw[r] = ws;
-    lsym[r] = (uint16_t)s;
+    for (uint32_t u = 0; u < n; u++) r += key_s[u] < key ? 1u : 0u;
+    lw[r] = key >> 9;
+    lsym[r] = (uint16_t)t;
   }
   __syncthreads();
+  if (t < n) {
+    wt[0][t] = lw[t];
+    pk[kLevels][t] = 0;
+  }
   int cur = 0;
   uint32_t size = n;
-  for (uint32_t i = lane; i < n; i += 64) {
-    wt[0][i] = lw[i];
-    pk[kLevels][i] = 0;
-  }
   __syncthreads();
   for (int j = kLevels - 1; j >= 1; j--) {
     const uint32_t np = size / 2;
-    for (uint32_t k = lane; k < np; k += 64) pw[k] = wt[cur][2 * k] + wt[cur][2 * k + 1];
+    if (t < np) pw[t] = wt[cur][2 * t] + wt[cur][2 * t + 1];
     __syncthreads();
-    for (uint32_t i = lane; i < n; i += 64) {
-      const uint32_t pos = i + count_less(pw, np, lw[i]);
-      wt[cur ^ 1][pos] = lw[i];
+    if (t < n) {
+      const uint32_t pos = t + count_less(pw, np, lw[t]);
+      wt[cur ^ 1][pos] = lw[t];
       pk[j][pos] = 0;
     }
-    for (uint32_t k = lane; k < np; k += 64) {
-      const uint32_t pos = k + count_le(lw, n, pw[k]);
-      wt[cur ^ 1][pos] = pw[k];
+    if (t < np) {
+      const uint32_t pos = t + count_le(lw, n, pw[t]);
+      wt[cur ^ 1][pos] = pw[t];
       pk[j][pos] = 1;
     }
     size = n + np;
@@ -189,41 +231,42 @@ __global__ __launch_bounds__(64) void k_tab_lengths(const uint32_t *d_nb, const 
     __syncthreads();
   }
   // select the first 2(n-1) items at the top and follow the packages down
-  uint32_t cnt[(kMaxAlpha + 63) / 64] = {0, 0, 0, 0, 0};
+  uint32_t cnt = 0;
   uint32_t selc = 2 * (n - 1);
   for (int j = 1; j <= kLevels; j++) {
-    uint32_t p = 0;
-    for (uint32_t i = lane; i < selc; i += 64) p += pk[j][i];
-    for (int d = 32; d > 0; d >>= 1) p += __shfl_xor(p, d);
-    const uint32_t q = selc - p;
-#pragma unroll
-    for (int r = 0; r < (kMaxAlpha + 63) / 64; r++) {
-      const uint32_t i = r * 64 + lane;
-      if (i < n && i < q) cnt[r]++;
-    }
+    const uint32_t p = (uint32_t)__syncthreads_count(t < selc && pk[j][t]) +
+                       (uint32_t)__syncthreads_count(t + kPmThreads < selc && pk[j][t + kPmThreads]);
+    if (t < n && t < selc - p) cnt++;
     selc = 2 * p;
   }
-#pragma unroll
-  for (int r = 0; r < (kMaxAlpha + 63) / 64; r++) {
-    const uint32_t i = r * 64 + lane;
-    if (i < n) ln[lsym[i]] = (uint8_t)cnt[r];
+  if (t < n) {
+    ln[lsym[t]] = (uint8_t)cnt;
+    atomicAdd(&nlen[cnt], 1u);
   }
   __syncthreads();
   uint8_t *L = lens + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
   uint8_t *cst = cost + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
-  for (uint32_t s = lane; s < n; s += 64) {
-    L[s] = ln[s];
-    cst[s] = ln[s];
+  if (t < n) {
+    L[t] = ln[t];
+    cst[t] = ln[t];
   }
-  for (uint32_t s = lane; s < kMaxAlpha; s += 64) tfr[s] = 0;
-  if (last && lane == 0) {
-    // canonical codes in (length, symbol) order
-    uint32_t *cw = code_words + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
-    uint32_t c = 0;
-    for (uint32_t l = 1; l <= kMaxCodeLen; l++) {
-      for (uint32_t s = 0; s < n; s++)
-        if (ln[s] == l) cw[s] = c++;
-      c <<= 1;
+  if (t < (uint32_t)kMaxAlpha) tfr[t] = 0;
+  if (last) {
+    // canonical codes in (length, symbol) order: first code of each length,
+    // plus the symbol's rank among the symbols of that length
+    if (t == 0) {
+      uint32_t c = 0;
+      for (uint32_t l = 1; l <= (uint32_t)kMaxCodeLen; l++) {
+        base[l] = c;
+        c = (c + nlen[l]) << 1;
+      }
+    }
+    __syncthreads();
+    if (t < n) {
+      const uint32_t l = ln[t];
+      uint32_t r = 0;
+      for (uint32_t u = 0; u < t; u++) r += ln[u] == l ? 1u : 0u;
+      code_words[((size_t)b * kMaxGroups + g) * kMaxAlpha + t] = base[l] + r;
     }
   }
 }
@@ -234,12 +277,12 @@ void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks
                   BlockCode *codes, const uint32_t *freq, uint8_t *cost, uint32_t *tfreq, uint32_t *group_base,
                   uint32_t *d_n_groups, uint8_t *sel, uint8_t *lens, uint32_t *code_words, hipStream_t s) {
   fill_u32(tfreq, 0, (size_t)max_blocks * kMaxGroups * kMaxAlpha, s);
-  hipLaunchKernelGGL(k_tab_init, dim3((max_blocks + 63) / 64), dim3(64), 0, s, d_nb, codes, freq, cost);
-  hipLaunchKernelGGL(k_sel_bases, dim3(1), dim3(64), 0, s, d_nb, codes, group_base, d_n_groups);
+  PCBZ_LAUNCH(k_tab_init, dim3((max_blocks + 63) / 64), dim3(64), 0, s, d_nb, codes, freq, cost);
+  PCBZ_LAUNCH(k_sel_bases, dim3(1), dim3(64), 0, s, d_nb, codes, group_base, d_n_groups);
   for (int it = 0; it < 4; it++) {
-    hipLaunchKernelGGL(k_tab_select, dim3((max_groups + 255) / 256), dim3(256), 0, s, sym, d_nb, codes, group_base,
+    PCBZ_LAUNCH(k_tab_select, dim3((max_groups + 255) / 256), dim3(256), 0, s, sym, d_nb, codes, group_base,
                        d_n_groups, cost, sel, tfreq);
-    hipLaunchKernelGGL(k_tab_lengths, dim3(max_blocks * kMaxGroups), dim3(64), 0, s, d_nb, codes, tfreq, cost, lens,
+    PCBZ_LAUNCH(k_tab_lengths, dim3(max_blocks * kMaxGroups), dim3(kPmThreads), 0, s, d_nb, codes, tfreq, cost, lens,
                        code_words, it == 3 ? 1 : 0);
   }
 }

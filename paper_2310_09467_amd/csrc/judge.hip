@@ -18,7 +18,8 @@
 // one wavefront per 4096-byte segment (ballot match on the byte value finds
 // the previous occurrence inside the 64-byte step; a per-wave LDS table
 // carries the last one across steps) into a 65536-bin 16-bit LDS histogram
-// per workgroup, then a fix-up pass links segments and adds (b).  The score
+// per workgroup of 16 segments; the workgroup links each byte's chain across
+// its segments, and a fix-up pass links workgroup tiles and adds (b).  The score
 // S = sum_t Tq(P[t]) with Tq(c) = round(c*log2(c)*2^20) is an exact integer,
 // so the lowest-entropy choice (largest S, ties to the lowest id) does not
 // depend on summation order.
@@ -30,6 +31,7 @@ namespace {
 
 constexpr int kSeg = 4096;
 constexpr int kJWaves = 16;
+constexpr int kJTile = kSeg * kJWaves;  // positions per workgroup tile
 
 // ---------------------------------------------------------------- rearrangement
 __global__ __launch_bounds__(256) void k_remap(const BandDesc *bands, const RowItem *rows, CandBufs cb,
@@ -162,11 +164,27 @@ __global__ __launch_bounds__(1024) void k_judge_pairs(const JudgeTask *tasks, co
         if (!later) lastp[w][c] = (uint16_t)pr;
       }
     }
-    const size_t sb = (size_t)(T.seg_base + seg) * 256;
-    for (int c = lane; c < 256; c += kWave) {
-      seg_first[sb + c] = firstp[w][c];
-      seg_last[sb + c] = lastp[w][c];
+  }
+  __syncthreads();
+  // link each byte's occurrence chain across the waves of this tile; the
+  // tile's first and last predecessor per byte go to the tile tables
+  if (threadIdx.x < 256) {
+    const uint32_t c = threadIdx.x;
+    uint32_t last = kNone16, first = kNone16;
+    for (int wv = 0; wv < kJWaves; wv++) {
+      const uint32_t f = firstp[wv][c];
+      if (f == kNone16) continue;
+      if (last != kNone16) {
+        const uint32_t q = (last << 8) | f;
+        atomicAdd(&hist[q >> 1], 1u << ((q & 1u) * 16u));
+      } else {
+        first = f;
+      }
+      last = lastp[wv][c];
     }
+    const size_t tb = (size_t)(T.seg_base + tile_local[blockIdx.x]) * 256 + c;
+    seg_first[tb] = (uint16_t)first;
+    seg_last[tb] = (uint16_t)last;
   }
   __syncthreads();
   uint32_t *H = hist_g + (size_t)ti * 65536;
@@ -177,25 +195,46 @@ __global__ __launch_bounds__(1024) void k_judge_pairs(const JudgeTask *tasks, co
   }
 }
 
-// Links each byte's occurrence chain across segments and adds the pairs at
-// bucket boundaries.  One workgroup per task, one thread per byte value.
-__global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, const uint16_t *seg_first,
-                                                     const uint16_t *seg_last, uint32_t *hist_g) {
+// Links each byte's occurrence chain across the tiles of a task and adds the
+// pairs at bucket boundaries.  One workgroup per task, one thread per byte
+// value; pairs are counted in a 16-bit LDS histogram (at most 256 per tile
+// boundary plus 255 bucket boundaries per bin) and flushed once.
+__global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, const uint16_t *tile_first,
+                                                     const uint16_t *tile_last, uint32_t *hist_g) {
+  __shared__ uint32_t lh[32768];
   __shared__ uint16_t fe[256], le[256];
   const JudgeTask T = tasks[blockIdx.x];
   const uint32_t c = threadIdx.x;
-  const uint32_t nseg = (T.n + kSeg - 1) / kSeg;
+  const uint32_t ntile = (T.n + kJTile - 1) / kJTile;
   uint32_t *H = hist_g + (size_t)blockIdx.x * 65536;
-  uint32_t last = kNone16, first_ever = kNone16;
-  for (uint32_t sgi = 0; sgi < nseg; sgi++) {
-    const size_t sb = (size_t)(T.seg_base + sgi) * 256 + c;
-    uint32_t f = seg_first[sb];
-    if (f == kNone16) continue;
-    if (last != kNone16)
-      atomicAdd(&H[(last << 8) | f], 1u);
+  const bool use_lds = ntile <= 200;  // keeps every 16-bit LDS bin below 65536
+  for (int i = threadIdx.x; i < 32768; i += 256) lh[i] = 0;
+  __syncthreads();
+  auto add = [&](uint32_t q) {
+    if (use_lds)
+      atomicAdd(&lh[q >> 1], 1u << ((q & 1u) * 16u));
     else
-      first_ever = f;
-    last = seg_last[sb];
+      atomicAdd(&H[q], 1u);
+  };
+  uint32_t last = kNone16, first_ever = kNone16;
+  constexpr uint32_t kBatch = 16;  // independent loads in flight per step
+  for (uint32_t s0 = 0; s0 < ntile; s0 += kBatch) {
+    uint32_t f[kBatch], l[kBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; k++) {
+      const size_t sb = (size_t)(T.seg_base + s0 + k) * 256 + c;
+      f[k] = s0 + k < ntile ? tile_first[sb] : kNone16;
+      l[k] = s0 + k < ntile ? tile_last[sb] : kNone16;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; k++) {
+      if (f[k] == kNone16) continue;
+      if (last != kNone16)
+        add((last << 8) | f[k]);
+      else
+        first_ever = f[k];
+      last = l[k];
+    }
   }
   fe[c] = (uint16_t)first_ever;
   le[c] = (uint16_t)last;
@@ -203,9 +242,17 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
   if (last != kNone16) {
     for (uint32_t c2 = c + 1; c2 < 256; c2++) {
       if (fe[c2] != kNone16) {
-        atomicAdd(&H[(last << 8) | fe[c2]], 1u);
+        add((last << 8) | fe[c2]);
         break;
       }
+    }
+  }
+  __syncthreads();
+  if (use_lds) {
+    for (int i = threadIdx.x; i < 32768; i += 256) {
+      const uint32_t v = lh[i];
+      if (v & 0xFFFFu) atomicAdd(&H[2 * i], v & 0xFFFFu);
+      if (v >> 16) atomicAdd(&H[2 * i + 1], v >> 16);
     }
   }
 }
@@ -318,7 +365,7 @@ void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, 
                    uint32_t write_mask, hipStream_t s) {
   if (!n_rows) return;
   size_t lds = remap_lds_bytes(pitch_max, lens_per_wg);
-  hipLaunchKernelGGL(k_remap, dim3(n_rows, max_chunks), dim3(256), lds, s, bands, rows, cb, forced, write_mask,
+  PCBZ_LAUNCH(k_remap, dim3(n_rows, max_chunks), dim3(256), lds, s, bands, rows, cb, forced, write_mask,
                      lens_per_wg);
 }
 
@@ -326,31 +373,31 @@ void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *til
                    uint32_t n_tiles, CandBufs cb, uint16_t *seg_first, uint16_t *seg_last, uint32_t *hist,
                    const int64_t *tq, unsigned long long *score, hipStream_t s) {
   if (!n_tasks) return;
-  hipLaunchKernelGGL(k_judge_pairs, dim3(n_tiles), dim3(1024), 0, s, tasks, tile_task, tile_local, cb, seg_first,
+  PCBZ_LAUNCH(k_judge_pairs, dim3(n_tiles), dim3(1024), 0, s, tasks, tile_task, tile_local, cb, seg_first,
                      seg_last, hist);
-  hipLaunchKernelGGL(k_judge_fixup, dim3(n_tasks), dim3(256), 0, s, tasks, seg_first, seg_last, hist);
-  hipLaunchKernelGGL(k_judge_score, dim3(64, n_tasks), dim3(256), 0, s, hist, tq, score);
+  PCBZ_LAUNCH(k_judge_fixup, dim3(n_tasks), dim3(256), 0, s, tasks, seg_first, seg_last, hist);
+  PCBZ_LAUNCH(k_judge_score, dim3(64, n_tasks), dim3(256), 0, s, hist, tq, score);
 }
 
 void launch_choose2(const BandDesc *bands, uint32_t n_bands, const int32_t *task_of,
                     const unsigned long long *score, const JudgeTask *tasks, const uint8_t *forced, uint8_t *choice,
                     double *entropy, int64_t *score_out, hipStream_t s) {
   if (!n_bands) return;
-  hipLaunchKernelGGL(k_choose, dim3((n_bands + 127) / 128), dim3(128), 0, s, bands, n_bands, task_of, score, tasks,
+  PCBZ_LAUNCH(k_choose, dim3((n_bands + 127) / 128), dim3(128), 0, s, bands, n_bands, task_of, score, tasks,
                      forced, choice, entropy, score_out);
 }
 
 void launch_validate_forced(const BandDesc *bands, uint32_t n_bands, uint8_t *forced, uint32_t *err,
                             hipStream_t s) {
   if (!n_bands) return;
-  hipLaunchKernelGGL(k_validate_forced, dim3((n_bands + 127) / 128), dim3(128), 0, s, bands, n_bands, forced, err);
+  PCBZ_LAUNCH(k_validate_forced, dim3((n_bands + 127) / 128), dim3(128), 0, s, bands, n_bands, forced, err);
 }
 
 void launch_gather2(const uint32_t *band_start, uint32_t n_bands, CandBufs cb, const uint8_t *choice,
                     uint8_t *chosen, uint64_t total, hipStream_t s) {
   if (!total) return;
   uint64_t threads = (total + 15) / 16;
-  hipLaunchKernelGGL(k_gather_chosen, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, band_start, n_bands,
+  PCBZ_LAUNCH(k_gather_chosen, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, band_start, n_bands,
                      cb, choice, chosen, total);
 }
 

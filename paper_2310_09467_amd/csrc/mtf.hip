@@ -112,41 +112,52 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
   if (threadIdx.x == 0) plen[c] = cnt;
 }
 
-__global__ __launch_bounds__(64) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
-                                                  const uint32_t *plen, uint8_t *inlist) {
+// Chains the partial lists of a block's chunks: the list entering chunk k+1
+// is chunk k's partial list followed by the entering list without those
+// symbols.  The block's partial lists are staged in LDS first; one thread
+// per list entry.
+constexpr uint32_t kMaxBlockChunks = (899981u + kChunk - 1) / kChunk + 1;
+
+__global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes,
+                                                   const uint8_t *plist, const uint32_t *plen, uint8_t *inlist) {
+  __shared__ uint4 pl4[kMaxBlockChunks * 16];
+  __shared__ uint32_t pn[kMaxBlockChunks];
   __shared__ uint8_t cur[256], nxt[256], mem[256];
+  __shared__ uint32_t wcnt[4];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
   const uint32_t nu = codes[b].n_in_use;
-  const uint32_t c0 = codes[b].chunk_start, nc = codes[b].n_chunks;
-  const int lane = lane_id();
+  const uint32_t c0 = codes[b].chunk_start, nc = min(codes[b].n_chunks, kMaxBlockChunks);
+  const uint32_t e = threadIdx.x;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t lt = lanemask_lt();
-  for (int e = lane; e < 256; e += 64) cur[e] = (uint8_t)e;
+  const uint4 *src = (const uint4 *)(plist + (size_t)c0 * 256);
+  stage_to_lds(pl4, src, nc * 16);
+  stage_to_lds(pn, plen + c0, nc);
+  const uint8_t *pl = (const uint8_t *)pl4;
+  cur[e] = (uint8_t)e;
+  nxt[e] = (uint8_t)e;
   __syncthreads();
   for (uint32_t k = 0; k < nc; k++) {
-    const size_t ck = (size_t)(c0 + k) * 256;
-    for (int e = lane; e < 256; e += 64) {
-      inlist[ck + e] = cur[e];
-      mem[e] = 0;
-    }
+    inlist[(size_t)(c0 + k) * 256 + e] = cur[e];
+    mem[e] = 0;
     __syncthreads();
-    const uint32_t pl = plen[c0 + k];
-    for (uint32_t e = lane; e < pl; e += 64) {
-      uint8_t v = plist[ck + e];
+    const uint32_t pln = pn[k];
+    if (e < pln) {
+      const uint8_t v = pl[k * 256 + e];
       mem[v] = 1;
       nxt[e] = v;
     }
     __syncthreads();
-    uint32_t base = pl;
-    for (int r = 0; r < 4; r++) {
-      const uint32_t e = r * 64 + lane;
-      const bool keep = e < nu && !mem[cur[e]];
-      const uint64_t bal = ballot64(keep);
-      if (keep) nxt[base + __popcll(bal & lt)] = cur[e];
-      base += (uint32_t)__popcll(bal);
-    }
+    const bool keep = e < nu && !mem[cur[e]];
+    const uint64_t bal = ballot64(keep);
+    if (lane == 0) wcnt[w] = (uint32_t)__popcll(bal);
     __syncthreads();
-    for (int e = lane; e < 256; e += 64) cur[e] = nxt[e];
+    uint32_t off = (uint32_t)__popcll(bal & lt);
+    for (int q = 0; q < w; q++) off += wcnt[q];
+    if (keep) nxt[pln + off] = cur[e];
+    __syncthreads();
+    cur[e] = nxt[e];
     __syncthreads();
   }
 }
@@ -275,21 +286,21 @@ void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const 
                  uint32_t *d_n_sym, hipStream_t s) {
   fill_u32(w.used, 0, (size_t)max_blocks * 8, s);
   fill_u32(freq, 0, (size_t)max_blocks * kMaxAlpha, s);
-  hipLaunchKernelGGL(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
+  PCBZ_LAUNCH(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
   const uint32_t *cb = w.chunk_block;
-  hipLaunchKernelGGL(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used);
-  hipLaunchKernelGGL(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used, d_nb, w.seq, codes);
-  hipLaunchKernelGGL(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
+  PCBZ_LAUNCH(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used);
+  PCBZ_LAUNCH(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used, d_nb, w.seq, codes);
+  PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.plist, w.plen);
-  hipLaunchKernelGGL(k_mtf_chain, dim3(max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.inlist);
-  hipLaunchKernelGGL(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
+  PCBZ_LAUNCH(k_mtf_chain, dim3(max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.inlist);
+  PCBZ_LAUNCH(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.inlist, w.idx);
-  hipLaunchKernelGGL(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);
+  PCBZ_LAUNCH(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);
   scan_inclusive_max_u32(w.zs, w.zs, nullptr, N, w.scan_tmp, s);
-  hipLaunchKernelGGL(k_rle2_len, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, cb, w.d_n_chunks, blk_start, d_nb,
+  PCBZ_LAUNCH(k_rle2_len, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, cb, w.d_n_chunks, blk_start, d_nb,
                      w.len);
   scan_exclusive_u32(w.len, w.off, nullptr, N, w.scan_tmp, d_n_sym, s);
-  hipLaunchKernelGGL(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks,
+  PCBZ_LAUNCH(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks,
                      blk_start, d_nb, codes, sym, freq);
 }
 

@@ -109,34 +109,53 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
   }
   o = 137 + 16 + 16 * nranges + 18;
   __syncthreads();
-  // selectors
-  for (uint32_t t0 = 0; t0 < nsel; t0 += 256) {
-    const uint32_t j = t0 + threadIdx.x;
-    const int s = j < nsel ? (int)sel[C.sel_start + j] : -1;
-    int last[kMaxGroups];
-    for (uint32_t g = 0; g < G; g++) {
-      int e = block_excl_max(s == (int)g ? (int)j : -1, shi);
-      last[g] = max(e, carry_last[g]);
-      if (threadIdx.x == 255) tile_last[g] = max(last[g], s == (int)g ? (int)j : -1);
-    }
-    uint32_t idx = 0;
-    if (s >= 0) {
-      const int ls = last[s];
-      if (ls >= 0) {
-        for (uint32_t g = 0; g < G; g++) idx += ((int)g != s && last[g] > ls) ? 1u : 0u;
-      } else {
-        for (uint32_t g = 0; g < G; g++) idx += (last[g] >= 0 || (int)g < s) ? ((int)g != s ? 1u : 0u) : 0u;
+  // selectors: staged in LDS by the whole workgroup, then one wavefront walks
+  // them 64 per step; the last use of each table before a lane comes from a
+  // ballot inside the step or from the carried last use
+  __shared__ uint8_t ssel[kMaxSelectors];
+  stage_to_lds(ssel, sel + C.sel_start, min(nsel, kMaxSelectors));
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    int carry[kMaxGroups];
+    for (int g = 0; g < kMaxGroups; g++) carry[g] = -1;
+    uint32_t pos = o;
+    for (uint32_t t0 = 0; t0 < nsel; t0 += kWave) {
+      const uint32_t j = t0 + lane;
+      const int s = j < nsel ? (int)ssel[j] : -1;
+      int last[kMaxGroups];
+      for (uint32_t g = 0; g < G; g++) {
+        const uint64_t bal = ballot64(s == (int)g);
+        const uint64_t before = bal & lt;
+        last[g] = before ? (int)(t0 + 63 - __clzll(before)) : carry[g];
+        if (bal) carry[g] = (int)(t0 + 63 - __clzll(bal));
       }
+      uint32_t idx = 0;
+      if (s >= 0) {
+        const int ls = last[s];
+        for (uint32_t g = 0; g < G; g++) {
+          if ((int)g == s) continue;
+          if (ls >= 0)
+            idx += last[g] > ls ? 1u : 0u;
+          else
+            idx += (last[g] >= 0 || (int)g < s) ? 1u : 0u;
+        }
+      }
+      const uint32_t nbits = s >= 0 ? idx + 1 : 0;
+      uint32_t incl = nbits;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+      }
+      if (s >= 0 && idx > 0) put_bits(w, pos + incl - nbits, idx, (1u << idx) - 1u);  // idx ones; the zero is there
+      pos += wave_read(incl, kWave - 1);
     }
-    const uint32_t nbits = s >= 0 ? idx + 1 : 0;
-    uint32_t tot;
-    const uint32_t off = block_excl_sum<uint32_t>(nbits, shu, tot);
-    if (s >= 0 && idx > 0) put_bits(w, o + off, idx, (1u << idx) - 1u);  // idx ones, then the zero already there
-    o += tot;
-    __syncthreads();
-    if (threadIdx.x < G) carry_last[threadIdx.x] = tile_last[threadIdx.x];
-    __syncthreads();
+    if (lane == 0) shu[0] = pos;
   }
+  __syncthreads();
+  o = shu[0];
+  __syncthreads();
   // code lengths, per table: 5-bit start, then per symbol +1 ("10") / -1 ("11") steps and "0"
   for (uint32_t g = 0; g < G; g++) {
     const uint8_t *L = lens + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
@@ -350,19 +369,19 @@ void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *bl
                   const FrameOut *frames, uint32_t n_frames, const BandDesc *bands, const uint8_t *choice,
                   uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words,
                   uint32_t max_words, hipStream_t s) {
-  hipLaunchKernelGGL(k_prefix, dim3(max_blocks), dim3(256), 0, s, d_nb, blocks, codes, used, sel, lens, prefix);
-  hipLaunchKernelGGL(k_blk_sym_start, dim3((max_blocks + 256) / 256), dim3(256), 0, s, d_nb, codes, blk_sym_start);
+  PCBZ_LAUNCH(k_prefix, dim3(max_blocks), dim3(256), 0, s, d_nb, blocks, codes, used, sel, lens, prefix);
+  PCBZ_LAUNCH(k_blk_sym_start, dim3((max_blocks + 256) / 256), dim3(256), 0, s, d_nb, codes, blk_sym_start);
   const uint32_t g = std::min<uint32_t>((max_sym + 255) / 256 + 1, 16384);
-  hipLaunchKernelGGL(k_sym_bits, dim3(g), dim3(256), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
+  PCBZ_LAUNCH(k_sym_bits, dim3(g), dim3(256), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
                      sym_bits);
   // exclusive scan over n_sym + 1 entries so that sym_off[n_sym] is the total
   scan_exclusive_u32(sym_bits, sym_off, nullptr, max_sym + 1, scan_tmp, nullptr, s);
-  hipLaunchKernelGGL(k_layout, dim3(1), dim3(64), 0, s, d_nb, blocks, codes, sym_off, blk_sym_start, frames, n_frames,
+  PCBZ_LAUNCH(k_layout, dim3(1), dim3(64), 0, s, d_nb, blocks, codes, sym_off, blk_sym_start, frames, n_frames,
                      bands, band_len, frame_len, word_start, d_words);
   const uint32_t gw = std::min<uint32_t>((max_words + 255) / 256 + 1, 16384);
-  hipLaunchKernelGGL(k_write, dim3(gw), dim3(256), 0, s, d_words, word_start, d_nb, blocks, codes, prefix, sym,
+  PCBZ_LAUNCH(k_write, dim3(gw), dim3(256), 0, s, d_words, word_start, d_nb, blocks, codes, prefix, sym,
                      sym_off, blk_sym_start, sel, lens, code_words, frames, frame_len);
-  hipLaunchKernelGGL(k_header, dim3(n_frames), dim3(256), 0, s, frames, frame_len, bands, choice, band_len);
+  PCBZ_LAUNCH(k_header, dim3(n_frames), dim3(256), 0, s, frames, frame_len, bands, choice, band_len);
 }
 
 }  // namespace pcbz

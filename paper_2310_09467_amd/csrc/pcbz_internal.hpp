@@ -18,6 +18,7 @@ constexpr int kMaxGroups = 6;
 constexpr int kMaxCodeLen = 17;
 constexpr int kGroupSize = 50;          // symbols per selector group
 constexpr uint32_t kPrefixWords = 6144; // 24 KB of header bits per block (bounded below)
+constexpr uint32_t kMaxSelectors = 18002;  // ceil((899981 + 1) / 50) for the largest block, plus slack
 
 // One band of one frame (whole lens rows).
 struct BandDesc {
@@ -112,6 +113,53 @@ __device__ __forceinline__ uint32_t upper_index(const T *a, uint32_t n, T key) {
   return lo;
 }
 
+// Copies n elements from global memory into LDS with the whole workgroup,
+// keeping 16 loads in flight per thread (a plain strided loop waits for each
+// load before the next).
+template <typename T>
+__device__ __forceinline__ void stage_to_lds(T *dst, const T *src, uint32_t n) {
+  constexpr uint32_t kInFlight = 16;
+  const uint32_t step = blockDim.x;
+  for (uint32_t base = 0; base < n; base += step * kInFlight) {
+    T v[kInFlight];
+#pragma unroll
+    for (uint32_t k = 0; k < kInFlight; k++) {
+      const uint32_t i = base + k * step + threadIdx.x;
+      if (i < n) v[k] = src[i];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kInFlight; k++) {
+      const uint32_t i = base + k * step + threadIdx.x;
+      if (i < n) dst[i] = v[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tracing
+// Optional HIP-event timing of named kernel launches (see pcbz_trace_*).
+// When tracing is off these are a single branch.
+extern bool g_trace_on;
+void trace_begin_impl(const char *name, hipStream_t s);
+void trace_end_impl(const char *name, hipStream_t s);
+inline void trace_begin(const char *name, hipStream_t s) {
+  if (g_trace_on) trace_begin_impl(name, s);
+}
+inline void trace_end(const char *name, hipStream_t s) {
+  if (g_trace_on) trace_end_impl(name, s);
+}
+// Adds algorithmic bytes (what the step must read and write) to a kernel's
+// trace record; the name is the kernel's launch spelling.
+void trace_bytes_impl(const char *name, uint64_t bytes);
+inline void trace_bytes(const char *name, uint64_t bytes) {
+  if (g_trace_on) trace_bytes_impl(name, bytes);
+}
+#define PCBZ_LAUNCH(kernel, grid, block, lds, stream, ...)                  \
+  do {                                                                      \
+    ::pcbz::trace_begin(#kernel, stream);                                   \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);      \
+    ::pcbz::trace_end(#kernel, stream);                                     \
+  } while (0)
+
 // ---------------------------------------------------------------- launchers
 struct CandBufs {
   uint8_t *p[kNumCand];
@@ -159,9 +207,9 @@ void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_s
                  const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
                  uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,
                  uint32_t *crc_chunk_base, uint32_t *d_n_blocks, uint32_t *d_crc_chunks, hipStream_t s);
-void launch_crc2(const uint8_t *x, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
-                 const uint32_t *crc_chunk_base, const uint32_t *d_crc_chunks, uint32_t max_crc_chunks,
-                 const uint32_t *xpow_chunk, const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s);
+void launch_crc2(const uint8_t *x, uint32_t N, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
+                 const uint32_t *blk_raw_start, const uint32_t *xpow_chunk, const uint32_t *xpow_byte,
+                 const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s);
 
 // bwt.hip
 struct BwtWork {

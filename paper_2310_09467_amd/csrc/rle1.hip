@@ -33,12 +33,15 @@ __global__ void k_r1_starts(const uint32_t *band_start, uint32_t n_bands, const 
   uint32_t b = upper_index(band_start, n_bands, (uint32_t)i0);
   uint32_t next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
   uint32_t prevc = i0 > 0 ? x[i0 - 1] : 0u;
+  const uint4 v16 = *(const uint4 *)(x + i0);  // the buffer has 16 bytes of slack past N
+  const uint32_t wd[4] = {v16.x, v16.y, v16.z, v16.w};
   for (uint32_t i = (uint32_t)i0; i < i1; i++) {
     if (i == next) {
       b++;
       next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
     }
-    uint32_t c = x[i];
+    const uint32_t k = i - (uint32_t)i0;
+    uint32_t c = (wd[k >> 2] >> (8 * (k & 3))) & 255u;
     bool start = (i == band_start[b]) || c != prevc;
     v[i] = start ? i : 0u;
     prevc = c;
@@ -177,31 +180,75 @@ __device__ uint32_t gf_mulmod(uint32_t a, uint32_t b) {
   return r;
 }
 
-// One thread per 256-byte chunk counted back from its block's end.
-__global__ __launch_bounds__(256) void k_crc_chunks(const uint8_t *x, const BlockDesc *blocks,
-                                                    const uint32_t *d_n_blocks, const uint32_t *crc_chunk_base,
-                                                    const uint32_t *d_crc_chunks, const uint32_t *xpow_chunk,
-                                                    uint32_t *crc_acc) {
-  __shared__ uint32_t T[256];
+// One thread per aligned 256-byte chunk of the raw byte space.  A chunk
+// inside one block is folded four bytes at a time with slice-by-4 tables
+// (T[k][v] = v * x^(32+8k) mod P); a chunk that crosses block edges is folded
+// byte by byte per block part.  Each part's register is carried to its block
+// end by x^(8d) mod P, d = bytes after the part = 256 q + r, from the tables
+// x^(2048 q) and x^(8 r).
+__global__ __launch_bounds__(256) void k_crc_chunks(const uint8_t *x, uint32_t N, const uint32_t *d_n_blocks,
+                                                    const uint32_t *blk_raw_start, const uint32_t *xpow_chunk,
+                                                    const uint32_t *xpow_byte, uint32_t *crc_acc) {
+  __shared__ uint32_t T[4][256];
   {
     uint32_t r = (uint32_t)threadIdx.x << 24;
     for (int k = 0; k < 8; k++) r = (r & 0x80000000u) ? (r << 1) ^ kPoly : (r << 1);
-    T[threadIdx.x] = r;
+    T[0][threadIdx.x] = r;
+    for (int t = 1; t < 4; t++) {
+      for (int k = 0; k < 8; k++) r = (r & 0x80000000u) ? (r << 1) ^ kPoly : (r << 1);
+      T[t][threadIdx.x] = r;
+    }
   }
-  __syncthreads();
-  const uint32_t nchunks = *d_crc_chunks;
+  // XOR accumulators for the first blocks this workgroup touches; parts of
+  // later blocks (only with many tiny blocks) go straight to global memory
+  constexpr uint32_t kSlots = 16;
+  __shared__ uint32_t acc[kSlots];
   const uint32_t nb = *d_n_blocks;
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < nchunks; c += gridDim.x * blockDim.x) {
-    const uint32_t k = upper_index(crc_chunk_base, nb, c);
-    const uint32_t j = c - crc_chunk_base[k];
-    const BlockDesc B = blocks[k];
-    const uint32_t hi = B.raw_end - j * kCrcChunk;
-    const uint32_t lo = hi - B.raw_start > (uint32_t)kCrcChunk ? hi - kCrcChunk : B.raw_start;
-    uint32_t r = 0;
-    for (uint32_t i = lo; i < hi; i++) r = (r << 8) ^ T[(r >> 24) ^ x[i]];
-    r = gf_mulmod(r, xpow_chunk[j]);
-    atomicXor(&crc_acc[k], r);
+  const uint32_t nchunks = (N + kCrcChunk - 1) / kCrcChunk;
+  const uint32_t cfirst = blockIdx.x * blockDim.x;
+  const uint32_t kfirst = cfirst < nchunks ? upper_index(blk_raw_start, nb, cfirst * kCrcChunk) : 0;
+  if (threadIdx.x < kSlots) acc[threadIdx.x] = 0;
+  __syncthreads();
+  {
+    const uint32_t c = cfirst + threadIdx.x;
+    if (c >= nchunks) goto flush;
+    const uint32_t c0 = c * kCrcChunk, c1 = min(N, c0 + kCrcChunk);
+    uint32_t k = upper_index(blk_raw_start, nb, c0);
+    for (;;) {
+      const uint32_t bs = blk_raw_start[k], be = blk_raw_start[k + 1];
+      const uint32_t lo = max(c0, bs), hi = min(c1, be);
+      uint32_t r = 0;
+      if (lo == c0 && hi == c0 + kCrcChunk) {
+        const uint4 *p = (const uint4 *)(x + c0);
+        uint4 v[16];
+#pragma unroll
+        for (int i = 0; i < 16; i++) v[i] = p[i];
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+          const uint32_t wds[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            r ^= __builtin_bswap32(wds[q]);
+            r = T[0][r & 255u] ^ T[1][(r >> 8) & 255u] ^ T[2][(r >> 16) & 255u] ^ T[3][r >> 24];
+          }
+        }
+      } else {
+        for (uint32_t i = lo; i < hi; i++) r = (r << 8) ^ T[0][(r >> 24) ^ x[i]];
+      }
+      const uint32_t d = be - hi;
+      r = gf_mulmod(gf_mulmod(r, xpow_chunk[d >> 8]), xpow_byte[d & 255u]);
+      if (k - kfirst < kSlots)
+        atomicXor(&acc[k - kfirst], r);
+      else
+        atomicXor(&crc_acc[k], r);
+      if (be >= c1 || k + 1 >= nb) break;
+      k++;
+    }
   }
+flush:
+  __syncthreads();
+  if (threadIdx.x < kSlots && kfirst + threadIdx.x < nb && acc[threadIdx.x])
+    atomicXor(&crc_acc[kfirst + threadIdx.x], acc[threadIdx.x]);
 }
 
 __device__ uint32_t xpow8_bytes(uint32_t m, const uint32_t *xpow2) {
@@ -228,32 +275,34 @@ void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *
                    uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s) {
   if (!N) return;
   uint32_t thr = (N + 15) / 16;
-  hipLaunchKernelGGL(k_r1_starts, dim3((thr + 255) / 256), dim3(256), 0, s, band_start, n_bands, x, N, runstart);
+  PCBZ_LAUNCH(k_r1_starts, dim3((thr + 255) / 256), dim3(256), 0, s, band_start, n_bands, x, N, runstart);
   scan_inclusive_max_u32(runstart, runstart, nullptr, N, scan_tmp, s);
   uint32_t grid = std::min<uint32_t>((N + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_r1_len, dim3(grid), dim3(256), 0, s, runstart, N, len);
+  PCBZ_LAUNCH(k_r1_len, dim3(grid), dim3(256), 0, s, runstart, N, len);
   scan_exclusive_u32(len, off, nullptr, N, scan_tmp, off + N, s);
-  hipLaunchKernelGGL(k_r1_write, dim3(grid), dim3(256), 0, s, band_start, n_bands, N, x, runstart, off, rle);
+  PCBZ_LAUNCH(k_r1_write, dim3(grid), dim3(256), 0, s, band_start, n_bands, N, x, runstart, off, rle);
 }
 
 void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
                  const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
                  uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,
                  uint32_t *crc_chunk_base, uint32_t *d_n_blocks, uint32_t *d_crc_chunks, hipStream_t s) {
-  hipLaunchKernelGGL(k_cut, dim3((n_bands + 63) / 64), dim3(64), 0, s, bands, n_bands, band_start, N, runstart, off,
+  PCBZ_LAUNCH(k_cut, dim3((n_bands + 63) / 64), dim3(64), 0, s, bands, n_bands, band_start, N, runstart, off,
                      slots, slot_count, err);
-  hipLaunchKernelGGL(k_blocks_compact, dim3(1), dim3(1024), 0, s, bands, n_bands, slots, slot_count, blocks,
+  PCBZ_LAUNCH(k_blocks_compact, dim3(1), dim3(1024), 0, s, bands, n_bands, slots, slot_count, blocks,
                      blk_raw_start, blk_rle_start, crc_chunk_base, d_n_blocks, d_crc_chunks);
 }
 
-void launch_crc2(const uint8_t *x, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
-                 const uint32_t *crc_chunk_base, const uint32_t *d_crc_chunks, uint32_t max_crc_chunks,
-                 const uint32_t *xpow_chunk, const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s) {
+void launch_crc2(const uint8_t *x, uint32_t N, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
+                 const uint32_t *blk_raw_start, const uint32_t *xpow_chunk, const uint32_t *xpow_byte,
+                 const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s) {
   fill_u32(crc_acc, 0, max_blocks, s);
-  uint32_t grid = std::min<uint32_t>((max_crc_chunks + 255) / 256 + 1, 4096);
-  hipLaunchKernelGGL(k_crc_chunks, dim3(grid), dim3(256), 0, s, x, blocks, d_n_blocks, crc_chunk_base, d_crc_chunks,
-                     xpow_chunk, crc_acc);
-  hipLaunchKernelGGL(k_crc_final, dim3((max_blocks + 255) / 256), dim3(256), 0, s, blocks, d_n_blocks, crc_acc,
+  const uint32_t chunks = (N + kCrcChunk - 1) / kCrcChunk;
+  const uint32_t grid = (chunks + 255) / 256;  // one chunk per thread
+  if (!grid) return;
+  PCBZ_LAUNCH(k_crc_chunks, dim3(grid), dim3(256), 0, s, x, N, d_n_blocks, blk_raw_start, xpow_chunk, xpow_byte,
+              crc_acc);
+  PCBZ_LAUNCH(k_crc_final, dim3((max_blocks + 255) / 256), dim3(256), 0, s, blocks, d_n_blocks, crc_acc,
                      xpow2);
 }
 

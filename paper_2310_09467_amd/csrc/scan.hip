@@ -153,9 +153,9 @@ void run_scan(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n
   }
   uint32_t ntiles = (n_max + kTile - 1) / kTile;
   uint32_t *aggs = (uint32_t *)tmp;
-  hipLaunchKernelGGL((k_reduce<Op>), dim3(ntiles), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
-  hipLaunchKernelGGL((k_scan_aggs<Op>), dim3(1), dim3(1024), 0, s, aggs, d_n, n_max, d_total);
-  hipLaunchKernelGGL((k_downsweep<Op, kInclusive>), dim3(ntiles), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
+  PCBZ_LAUNCH((k_reduce<Op>), dim3(ntiles), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
+  PCBZ_LAUNCH((k_scan_aggs<Op>), dim3(1), dim3(1024), 0, s, aggs, d_n, n_max, d_total);
+  PCBZ_LAUNCH((k_downsweep<Op, kInclusive>), dim3(ntiles), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
 }
 
 }  // namespace
@@ -176,7 +176,7 @@ void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
   if (n == 0) return;
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
+  PCBZ_LAUNCH(k_fill, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
 }
 
 }  // namespace pcbz

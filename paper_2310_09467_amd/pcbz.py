@@ -20,7 +20,8 @@ _NAMES = {EINVAL: "EINVAL", ENOSPC: "ENOSPC", EDATA: "EDATA", ENEEDPREV: "ENEEDP
           EDEVICE: "EDEVICE"}
 
 EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_judge", "pcbz_compress",
-           "pcbz_compress_batch", "pcbz_peek", "pcbz_decompress", "pcbz_last_stats")
+           "pcbz_compress_batch", "pcbz_peek", "pcbz_decompress", "pcbz_last_stats", "pcbz_trace_enable",
+           "pcbz_trace_read")
 
 
 class PcbzError(RuntimeError):
@@ -57,6 +58,8 @@ def load():
             "pcbz_peek": (i32, [vp, sz, pp, vp]),
             "pcbz_decompress": (i32, [vp, vp, sz, vp, vp, sz, vp]),
             "pcbz_last_stats": (i32, [vp, vp, vp, vp, vp]),
+            "pcbz_trace_enable": (i32, [vp, i32, ctypes.c_char_p]),
+            "pcbz_trace_read": (i32, [vp, vp, sz, vp, vp, vp, u32, vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -226,6 +229,30 @@ class Context:
                                     out.numel(), _stream())
         if st:
             self._err(st, "decompress")
+        return out
+
+    def trace(self, on=True, kernel=None):
+        """Enables HIP-event timing of launches of `kernel` (all kernels when None)."""
+        st = load().pcbz_trace_enable(self._h, 1 if on else 0, None if kernel is None else kernel.encode())
+        if st:
+            self._err(st, "trace_enable")
+
+    def trace_read(self, reset=True, max_names=256):
+        """Returns {kernel name: (total ms, launches, algorithmic bytes)} for the traced launches."""
+        stride = 96
+        names = ctypes.create_string_buffer(stride * max_names)
+        ms = (ctypes.c_double * max_names)()
+        calls = (ctypes.c_uint64 * max_names)()
+        nbytes = (ctypes.c_uint64 * max_names)()
+        n = ctypes.c_uint32()
+        st = load().pcbz_trace_read(self._h, names, stride, ms, calls, nbytes, max_names, ctypes.byref(n),
+                                    1 if reset else 0)
+        if st:
+            self._err(st, "trace_read")
+        out = {}
+        for i in range(min(n.value, max_names)):
+            nm = names.raw[i * stride:(i + 1) * stride].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[i], calls[i], nbytes[i])
         return out
 
     def last_stats(self):
