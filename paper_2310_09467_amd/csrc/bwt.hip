@@ -13,8 +13,15 @@
 //
 // Sorting is a least-significant-digit radix sort (8-bit digits) on 64-bit
 // keys with 32-bit values: per-tile digit counts, one exclusive scan over
-// the digit-major count table, then a stable scatter that ranks equal digits
-// inside each wavefront with ballot matching.
+// the digit-major count table, then a stable scatter.  The scatter ranks
+// equal digits inside each wavefront with ballot matching, sorts the tile by
+// digit in LDS, and writes each digit's run with consecutive threads.
+//
+// Every count (elements, blocks, unresolved rotations) is read from device
+// memory and every kernel loops over its work with a capped grid, so the
+// whole sort can be enqueued without reading anything back: a caller either
+// reads the unresolved count after each round to stop early, or enqueues a
+// fixed number of rounds (after which the count must be zero).
 #include <cstdio>
 #include <cstdlib>
 
@@ -24,85 +31,125 @@ namespace pcbz {
 namespace {
 
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;
+constexpr uint32_t kGridCap = 2048;  // workgroups of the grid-stride kernels
 
 __device__ __forceinline__ uint32_t dev_n(const uint32_t *d_n, uint32_t n_max) {
   if (!d_n) return n_max;
-  uint32_t n = *d_n;
+  const uint32_t n = *d_n;
   return n < n_max ? n : n_max;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, const uint32_t *d_n, uint32_t n_max,
-                                                        int shift, uint32_t *counts, uint32_t stride) {
+                                                        int shift, uint32_t *counts, uint32_t *d_count_n) {
+  constexpr uint32_t TILE = kRsThreads * ITEMS;
   __shared__ uint32_t h[kRsThreads / kWave][256];
-  const int w = threadIdx.x / kWave;
-  for (int i = threadIdx.x; i < (kRsThreads / kWave) * 256; i += kRsThreads) (&h[0][0])[i] = 0;
-  __syncthreads();
   const uint32_t n = dev_n(d_n, n_max);
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
-  if (base < n) {
-#pragma unroll 4
-    for (int it = 0; it < kRsItems; it++) {
-      uint64_t j = base + (uint64_t)it * kRsThreads + threadIdx.x;
+  const uint32_t nt = (n + TILE - 1) / TILE;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d_count_n = 256u * nt;
+  const int w = threadIdx.x / kWave;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    for (int i = threadIdx.x; i < (kRsThreads / kWave) * 256; i += kRsThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)tile * TILE;
+#pragma unroll 8
+    for (int it = 0; it < ITEMS; it++) {
+      const uint64_t j = base + (uint64_t)it * kRsThreads + threadIdx.x;
       if (j < n) atomicAdd(&h[w][(uint32_t)(keys[j] >> shift) & 255u], 1u);
     }
+    __syncthreads();
+    const uint32_t d = threadIdx.x;
+    uint32_t c = 0;
+    for (int k = 0; k < kRsThreads / kWave; k++) c += h[k][d];
+    counts[(size_t)d * nt + tile] = c;
+    __syncthreads();
   }
-  __syncthreads();
-  uint32_t d = threadIdx.x;
-  uint32_t c = 0;
-  for (int k = 0; k < kRsThreads / kWave; k++) c += h[k][d];
-  counts[(size_t)d * stride + blockIdx.x] = c;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
                                                            uint64_t *keys_out, uint32_t *vals_out,
                                                            const uint32_t *d_n, uint32_t n_max, int shift,
-                                                           const uint32_t *offsets, uint32_t stride) {
-  __shared__ uint32_t base_d[256];
+                                                           const uint32_t *offsets) {
+  constexpr uint32_t TILE = kRsThreads * ITEMS;
+  __shared__ uint64_t skey[TILE];
+  __shared__ uint32_t sval[TILE];
+  __shared__ uint32_t gbase[256];   // global position of each digit's run in this tile
+  __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
+  __shared__ uint32_t run[256];     // running fill of each digit's run
   __shared__ uint32_t wcnt[kRsThreads / kWave][256];
+  __shared__ uint32_t wsum[kRsThreads / kWave];
   const uint32_t n = dev_n(d_n, n_max);
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
-  if (base >= n) return;
+  const uint32_t nt = (n + TILE - 1) / TILE;
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
-  base_d[threadIdx.x] = offsets[(size_t)threadIdx.x * stride + blockIdx.x];
-  for (int k = 0; k < kRsThreads / kWave; k++) wcnt[k][threadIdx.x] = 0;
-  __syncthreads();
   const uint64_t lt = lanemask_lt();
-  for (int it = 0; it < kRsItems; it++) {
-    const uint64_t j = base + (uint64_t)it * kRsThreads + threadIdx.x;
-    const bool valid = j < n;
-    uint64_t key = 0;
-    uint32_t val = 0, d = 0;
-    if (valid) {
-      key = keys_in[j];
-      val = vals_in[j];
-      d = (uint32_t)(key >> shift) & 255u;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint64_t base = (uint64_t)tile * TILE;
+    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - base);
+    // tile-local digit counts follow from the scanned table: the next entry of
+    // the digit-major scan is the successor of (digit, tile)
+    const uint32_t d0 = threadIdx.x;
+    const size_t at = (size_t)d0 * nt + tile;
+    const uint32_t here = offsets[at];
+    const uint32_t next = (d0 == 255 && tile == nt - 1) ? n : offsets[at + 1];
+    const uint32_t cnt = next - here;
+    gbase[d0] = here;
+    // exclusive scan of the 256 counts (one per thread)
+    uint32_t incl = cnt;
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+      const uint32_t t = __shfl_up(incl, dd);
+      if (lane >= dd) incl += t;
     }
-    const uint64_t act = ballot64(valid);
-    const uint64_t peers = match_any8(d, act);
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    if (lane == kWave - 1) wsum[w] = incl;
+    for (int k = 0; k < kRsThreads / kWave; k++) wcnt[k][d0] = 0;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base_d[d] + rank;
-      for (int k = 0; k < w; k++) pos += wcnt[k][d];
-      keys_out[pos] = key;
-      vals_out[pos] = val;
-    }
+    uint32_t before = 0;
+    for (int k = 0; k < w; k++) before += wsum[k];
+    lstart[d0] = before + incl - cnt;
+    run[d0] = before + incl - cnt;
     __syncthreads();
-    {
-      const uint32_t dd = threadIdx.x;
-      uint32_t add = 0;
-      for (int k = 0; k < kRsThreads / kWave; k++) {
-        add += wcnt[k][dd];
-        wcnt[k][dd] = 0;
+    // stable local ranks, ITEMS rows of 256 elements in index order
+    for (int it = 0; it < ITEMS; it++) {
+      const uint32_t li = (uint32_t)it * kRsThreads + threadIdx.x;
+      const bool valid = li < tn;
+      uint64_t key = 0;
+      uint32_t val = 0, d = 0;
+      if (valid) {
+        key = keys_in[base + li];
+        val = vals_in[base + li];
+        d = (uint32_t)(key >> shift) & 255u;
       }
-      base_d[dd] += add;
+      const uint64_t peers = match_any8(d, ballot64(valid));
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = run[d] + rank;
+        for (int k = 0; k < w; k++) pos += wcnt[k][d];
+        skey[pos] = key;
+        sval[pos] = val;
+      }
+      __syncthreads();
+      {
+        uint32_t add = 0;
+        for (int k = 0; k < kRsThreads / kWave; k++) {
+          add += wcnt[k][d0];
+          wcnt[k][d0] = 0;
+        }
+        run[d0] += add;
+      }
+      __syncthreads();
+    }
+    // each digit's run is contiguous in LDS and in the output
+    for (uint32_t i = threadIdx.x; i < tn; i += kRsThreads) {
+      const uint64_t key = skey[i];
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      const uint32_t gp = gbase[d] + (i - lstart[d]);
+      keys_out[gp] = key;
+      vals_out[gp] = sval[i];
     }
     __syncthreads();
-    (void)lane;
   }
 }
 
@@ -111,10 +158,11 @@ __device__ __forceinline__ uint32_t block_of(const uint32_t *blk_start, uint32_t
   return upper_index(blk_start, nb, g);
 }
 
-__global__ void k_bwt_init(const uint8_t *rle, uint32_t N, const uint32_t *blk_start, uint32_t nb, uint64_t *keys,
-                           uint32_t *vals, uint32_t *slot) {
-  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < N; gi += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t g = (uint32_t)gi;
+__global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start, const uint32_t *d_nb,
+                           uint64_t *keys, uint32_t *vals, uint32_t *slot, uint32_t *d_u) {
+  const uint32_t N = *d_N, nb = *d_nb;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d_u = N;
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
     const uint32_t k = block_of(blk_start, nb, g);
     const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
     uint32_t v = 0;
@@ -127,19 +175,18 @@ __global__ void k_bwt_init(const uint8_t *rle, uint32_t N, const uint32_t *blk_s
 
 // Group-start markers (the slot of each group's first element), for a
 // max-scan that yields every element's new rank.
-__global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, uint32_t U, uint32_t *mark) {
-  for (uint64_t ki = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ki < U; ki += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = (uint32_t)ki;
+__global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const uint32_t *d_u, uint32_t *mark) {
+  const uint32_t U = *d_u;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x)
     mark[k] = (k == 0 || keys[k] != keys[k - 1]) ? slot[k] : 0u;
-  }
 }
 
 // Writes ranks and suffix-array entries; flags elements that stay unresolved.
 __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
-                             const uint32_t *newrank, uint32_t U, const uint32_t *blk_start, uint32_t nb,
-                             uint32_t compared, uint32_t *rank, uint32_t *sa, uint32_t *unres) {
-  for (uint64_t ki = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ki < U; ki += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = (uint32_t)ki;
+                             const uint32_t *newrank, const uint32_t *d_u, const uint32_t *blk_start,
+                             const uint32_t *d_nb, uint32_t compared, uint32_t *rank, uint32_t *sa, uint32_t *unres) {
+  const uint32_t U = *d_u, nb = *d_nb;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     const uint32_t g = vals[k];
     rank[g] = newrank[k];
     sa[slot[k]] = g;
@@ -152,9 +199,9 @@ __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const u
 }
 
 __global__ void k_bwt_compact(const uint32_t *vals, const uint32_t *slot, const uint32_t *unres,
-                              const uint32_t *pos, uint32_t U, uint32_t *vals2, uint32_t *slot2) {
-  for (uint64_t ki = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ki < U; ki += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t k = (uint32_t)ki;
+                              const uint32_t *pos, const uint32_t *d_u, uint32_t *vals2, uint32_t *slot2) {
+  const uint32_t U = *d_u;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     if (unres[k]) {
       vals2[pos[k]] = vals[k];
       slot2[pos[k]] = slot[k];
@@ -162,21 +209,22 @@ __global__ void k_bwt_compact(const uint32_t *vals, const uint32_t *slot, const 
   }
 }
 
-__global__ void k_bwt_keys(const uint32_t *vals, uint32_t U, const uint32_t *rank, const uint32_t *blk_start,
-                           uint32_t nb, uint32_t h, int bits, uint64_t *keys) {
-  for (uint64_t ki = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ki < U; ki += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t g = vals[ki];
+__global__ void k_bwt_keys(const uint32_t *vals, const uint32_t *d_u, const uint32_t *rank, const uint32_t *blk_start,
+                           const uint32_t *d_nb, uint32_t h, int bits, uint64_t *keys) {
+  const uint32_t U = *d_u, nb = *d_nb;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
+    const uint32_t g = vals[k];
     const uint32_t b = block_of(blk_start, nb, g);
     const uint32_t s = blk_start[b], m = blk_start[b + 1] - s;
     const uint32_t g2 = s + (uint32_t)(((uint64_t)(g - s) + h) % m);
-    keys[ki] = ((uint64_t)rank[g] << bits) | rank[g2];
+    keys[k] = ((uint64_t)rank[g] << bits) | rank[g2];
   }
 }
 
-__global__ void k_bwt_emit(const uint32_t *sa, const uint8_t *rle, uint32_t N, const uint32_t *blk_start, uint32_t nb,
-                           uint8_t *L, BlockCode *codes) {
-  for (uint64_t ji = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; ji < N; ji += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t j = (uint32_t)ji;
+__global__ void k_bwt_emit(const uint32_t *sa, const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start,
+                           const uint32_t *d_nb, uint8_t *L, BlockCode *codes) {
+  const uint32_t N = *d_N, nb = *d_nb;
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
     const uint32_t g = sa[j];
     const uint32_t b = block_of(blk_start, nb, j);
     const uint32_t s = blk_start[b], e = blk_start[b + 1];
@@ -194,78 +242,99 @@ int bits_for(uint64_t maxval) {
 uint32_t grid_for(uint64_t n) {
   uint64_t g = (n + 255) / 256;
   if (g < 1) g = 1;
-  if (g > 16384) g = 16384;
+  if (g > kGridCap) g = kGridCap;
   return (uint32_t)g;
 }
 
-}  // namespace
-
-size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + kRsTile - 1) / kRsTile + 1); }
-
-// Sorts (keys[0], vals[0]) by the low `bits` bits of the key; returns the
-// buffer index holding the result.
-int radix_sort(uint64_t *keys[2], uint32_t *vals[2], uint32_t n, int bits, uint32_t *counts, void *scan_tmp,
-               hipStream_t s) {
+template <int ITEMS>
+int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits,
+                 uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+  constexpr uint32_t TILE = kRsThreads * ITEMS;
   int cur = 0;
-  if (n <= 1 || bits <= 0) return cur;
-  const uint32_t ntiles = (n + kRsTile - 1) / kRsTile;
+  if (n_max <= 1 || bits <= 0) return cur;
+  const uint32_t ntiles = (n_max + TILE - 1) / TILE;
+  const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
   for (int shift = 0; shift < bits; shift += 8) {
-    PCBZ_LAUNCH(k_rs_hist, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], nullptr, n, shift, counts, ntiles);
-    scan_exclusive_u32(counts, counts, nullptr, 256u * ntiles, scan_tmp, nullptr, s);
-    PCBZ_LAUNCH(k_rs_scatter, dim3(ntiles), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                       vals[cur ^ 1], nullptr, n, shift, counts, ntiles);
+    PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, shift, counts,
+                d_count_n);
+    scan_exclusive_u32(counts, counts, d_count_n, 256u * ntiles, scan_tmp, nullptr, s);
+    PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+                vals[cur ^ 1], d_n, n_max, shift, counts);
     // a scatter pass reads and writes every 8-byte key and 4-byte value once
-    trace_bytes("k_rs_scatter", 24ull * n);
+    trace_bytes("k_rs_scatter<ITEMS>", 24ull * n_max);
     cur ^= 1;
   }
   return cur;
 }
 
-// Eager prefix doubling: reads the unresolved count back after each round.
-int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_start, BwtWork w, uint32_t *sa,
-            uint8_t *L, BlockCode *codes, uint32_t *pinned_u, hipStream_t s) {
-  if (N == 0) return 0;
+}  // namespace
+
+size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + 2047) / 2048 + 1); }
+
+// Sorts (keys[0], vals[0]) by the low `bits` bits of the key (n read from
+// d_n); returns the buffer index holding the result.
+int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
+               uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+  if (items <= 8) return radix_sort_t<8>(keys, vals, d_n, n_max, bits, counts, d_count_n, scan_tmp, s);
+  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, counts, d_count_n, scan_tmp, s);
+}
+
+// Prefix doubling over every block.  With `pinned_u` the unresolved count is
+// read back after each round and the loop stops when it reaches zero (at most
+// max_rounds); without it exactly max_rounds rounds are enqueued and the
+// final unresolved count is left in *d_left.  Returns the rounds enqueued.
+int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
+            const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
+            int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s) {
+  if (n_max == 0) return 0;
   uint64_t *keys[2] = {w.key[0], w.key[1]};
   uint32_t *vals[2] = {w.val[0], w.val[1]};
   uint32_t *slot = w.slot, *slot2 = w.slot2;
-  PCBZ_LAUNCH(k_bwt_init, dim3(grid_for(N)), dim3(256), 0, s, rle, N, blk_start, nb, keys[0], vals[0], slot);
-  int cur = radix_sort(keys, vals, N, 32 + bits_for(nb - 1), w.counts, w.scan_tmp, s);
-  const int rbits = bits_for(N - 1);
-  uint32_t U = N;
+  uint32_t *du[2] = {w.d_u, w.d_u + 1};
+  const uint32_t g = grid_for(n_max);
+  PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, keys[0], vals[0], slot, du[0]);
+  int cur = radix_sort(keys, vals, du[0], n_max, 32 + bits_for(nb_max > 0 ? nb_max - 1 : 0), items, w.counts,
+                       w.d_count_n, w.scan_tmp, s);
+  const int rbits = bits_for(n_max - 1);
+  int u = 0;  // which count slot holds the current unresolved count
   uint32_t compared = 4;
   int rounds = 0;
+  uint32_t n_cur = n_max;  // bound on the unresolved count (exact when read back)
   for (;;) {
+    const uint32_t gc = grid_for(n_cur);
     // new ranks: max-scan of group-start slots
-    PCBZ_LAUNCH(k_bwt_heads, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], slot, U, w.flag);
-    scan_inclusive_max_u32(w.flag, w.flag, nullptr, U, w.scan_tmp, s);
-    PCBZ_LAUNCH(k_bwt_update, dim3(grid_for(U)), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, U,
-                       blk_start, nb, compared, w.rank, sa, w.flag2);
-    scan_exclusive_u32(w.flag2, w.flag, nullptr, U, w.scan_tmp, w.d_u, s);
-    PCBZ_LAUNCH(k_bwt_compact, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, U,
-                       vals[cur ^ 1], slot2);
-    hipMemcpyAsync(pinned_u, w.d_u, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    U = *pinned_u;
+    PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag);
+    scan_inclusive_max_u32(w.flag, w.flag, du[u], n_cur, w.scan_tmp, s);
+    PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
+                compared, w.rank, sa, w.flag2);
+    scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
+    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, du[u], vals[cur ^ 1],
+                slot2);
+    u ^= 1;
     rounds++;
-    if (getenv("PCBZ_DEBUG_BWT")) fprintf(stderr, "pcbz bwt: N=%u round %d compared=%u unresolved=%u\n", N, rounds, compared, U);
-    if (U == 0) break;
-    if (rounds > 40 || compared >= (1u << 31)) return -1;  // doubling must finish once 2h reaches the block length
-    // compact list is now in (vals[cur^1], slot2)
+    if (pinned_u) {
+      hipMemcpyAsync(pinned_u, du[u], sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+      hipStreamSynchronize(s);
+      if (getenv("PCBZ_DEBUG_BWT"))
+        fprintf(stderr, "pcbz bwt: round %d compared=%u unresolved=%u\n", rounds, compared, *pinned_u);
+      n_cur = *pinned_u;
+      if (n_cur == 0) break;
+    }
+    if (rounds >= max_rounds || compared >= (1u << 30)) break;
+    // the compact list is now in (vals[cur^1], slot2)
     cur ^= 1;
     uint32_t *t = slot;
     slot = slot2;
     slot2 = t;
-    const uint32_t h = compared;
-    PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(U)), dim3(256), 0, s, vals[cur], U, w.rank, blk_start, nb, h, rbits,
-                       keys[cur]);
-    // sort keys[cur]/vals[cur]; radix_sort sorts buffer 0, so arrange the pair
+    PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(n_cur)), dim3(256), 0, s, vals[cur], du[u], w.rank, blk_start, d_nb,
+                compared, rbits, keys[cur]);
     uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
     uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
-    int r = radix_sort(kk, vv, U, 2 * rbits, w.counts, w.scan_tmp, s);
-    if (r == 1) cur ^= 1;
-    compared = compared * 2;
+    if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, w.counts, w.d_count_n, w.scan_tmp, s) == 1) cur ^= 1;
+    compared *= 2;
   }
-  PCBZ_LAUNCH(k_bwt_emit, dim3(grid_for(N)), dim3(256), 0, s, sa, rle, N, blk_start, nb, L, codes);
+  if (d_left) copy_u32(d_left, du[u], s);
+  PCBZ_LAUNCH(k_bwt_emit, dim3(g), dim3(256), 0, s, sa, rle, d_N, blk_start, d_nb, L, codes);
   return rounds;
 }
 

@@ -387,6 +387,20 @@ void launch_choose2(const BandDesc *bands, uint32_t n_bands, const int32_t *task
                      forced, choice, entropy, score_out);
 }
 
+namespace {
+// Per-band forced ids from each frame's caller array (0xFF: judge the band).
+__global__ void k_gather_forced(const FrameOut *frames, uint8_t *forced) {
+  const FrameOut F = frames[blockIdx.x];
+  for (uint32_t k = threadIdx.x; k < F.n_bands; k += blockDim.x)
+    forced[F.band_base + k] = F.forced ? F.forced[k] : (uint8_t)0xFFu;
+}
+}  // namespace
+
+void launch_gather_forced(const FrameOut *frames, uint32_t n_frames, uint8_t *forced, hipStream_t s) {
+  if (!n_frames) return;
+  PCBZ_LAUNCH(k_gather_forced, dim3(n_frames), dim3(256), 0, s, frames, forced);
+}
+
 void launch_validate_forced(const BandDesc *bands, uint32_t n_bands, uint8_t *forced, uint32_t *err,
                             hipStream_t s) {
   if (!n_bands) return;

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const ui
 
 }  // namespace
 
-void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
+void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
                  uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
                  uint32_t *d_n_sym, hipStream_t s) {
   fill_u32(w.used, 0, (size_t)max_blocks * 8, s);
@@ -296,10 +296,10 @@ void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const 
   PCBZ_LAUNCH(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.inlist, w.idx);
   PCBZ_LAUNCH(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);
-  scan_inclusive_max_u32(w.zs, w.zs, nullptr, N, w.scan_tmp, s);
+  scan_inclusive_max_u32(w.zs, w.zs, d_N, N, w.scan_tmp, s);
   PCBZ_LAUNCH(k_rle2_len, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, cb, w.d_n_chunks, blk_start, d_nb,
                      w.len);
-  scan_exclusive_u32(w.len, w.off, nullptr, N, w.scan_tmp, d_n_sym, s);
+  scan_exclusive_u32(w.len, w.off, d_N, N, w.scan_tmp, d_n_sym, s);
   PCBZ_LAUNCH(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks,
                      blk_start, d_nb, codes, sym, freq);
 }

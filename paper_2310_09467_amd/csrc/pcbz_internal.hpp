@@ -167,7 +167,8 @@ struct CandBufs {
 
 // Per-frame output description for the container writer.
 struct FrameOut {
-  uint8_t *out;  // caller's device output buffer
+  uint8_t *out;           // caller's device output buffer
+  const uint8_t *forced;  // caller's forced ids (device, n_bands) or nullptr
   uint64_t cap;  // its capacity in bytes
   uint32_t h, w, pitch, level;
   uint32_t n_bands;
@@ -183,6 +184,7 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, 
 void scan_inclusive_max_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
                             hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);  // one word, device to device, as a kernel
 
 // judge.hip
 size_t remap_lds_bytes(uint32_t pitch, uint32_t lens_per_wg);
@@ -199,6 +201,7 @@ void launch_gather2(const uint32_t *band_start, uint32_t n_bands, CandBufs cb, c
                     uint8_t *chosen, uint64_t total, hipStream_t s);
 void launch_validate_forced(const BandDesc *bands, uint32_t n_bands, uint8_t *forced, uint32_t *err,
                             hipStream_t s);
+void launch_gather_forced(const FrameOut *frames, uint32_t n_frames, uint8_t *forced, hipStream_t s);
 
 // rle1.hip
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
@@ -218,15 +221,19 @@ struct BwtWork {
   uint32_t *slot;
   uint32_t *slot2;
   uint32_t *rank;
-  uint32_t *flag;    // [N+1]
-  uint32_t *flag2;   // [N+1]
-  uint32_t *counts;  // radix tile counts
-  uint32_t *d_u;     // unresolved count (device)
+  uint32_t *flag;       // [N+1]
+  uint32_t *flag2;      // [N+1]
+  uint32_t *counts;     // radix tile counts
+  uint32_t *d_u;        // [2] unresolved counts (device)
+  uint32_t *d_count_n;  // size of the current count table (device)
   void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max);
-int run_bwt(const uint8_t *rle, uint32_t N, uint32_t nb, const uint32_t *blk_start, BwtWork w, uint32_t *sa,
-            uint8_t *L, BlockCode *codes, uint32_t *pinned_u, hipStream_t s);
+int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
+               uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
+int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
+            const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
+            int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
 struct MtfWork {
@@ -243,7 +250,7 @@ struct MtfWork {
   uint32_t *d_n_chunks;
   void *scan_tmp;
 };
-void launch_mtf2(const uint8_t *L, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
+void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
                  uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
                  uint32_t *d_n_sym, hipStream_t s);
 

@@ -66,18 +66,19 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *in, const u
                                                      uint32_t *aggs) {
   __shared__ uint32_t sh_wave[kThreads / kWave];
   const uint32_t n = get_n(d_n, n_max);
-  const uint64_t base = (uint64_t)blockIdx.x * kTile;
-  uint32_t acc = Op::id;
-  if (base < n) {
+  const uint32_t ntiles = (n + kTile - 1) / kTile;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t base = (uint64_t)tile * kTile;
+    uint32_t acc = Op::id;
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
       uint64_t j = base + (uint64_t)i * kThreads + threadIdx.x;
       if (j < n) acc = Op::f(acc, in[j]);
     }
+    uint32_t inc, exc, total;
+    block_scan<Op>(acc, sh_wave, inc, exc, total);
+    if (threadIdx.x == 0) aggs[tile] = total;
   }
-  uint32_t inc, exc, total;
-  block_scan<Op>(acc, sh_wave, inc, exc, total);
-  if (threadIdx.x == 0) aggs[blockIdx.x] = total;
 }
 
 // Exclusive scan of the tile aggregates in place (one workgroup of 1024).
@@ -103,42 +104,47 @@ __global__ __launch_bounds__(1024) void k_scan_aggs(uint32_t *aggs, const uint32
 template <typename Op, bool kInclusive>
 __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t *in, uint32_t *out, const uint32_t *d_n,
                                                         uint32_t n_max, const uint32_t *aggs) {
-  __shared__ uint32_t tile[kPad];
+  __shared__ uint32_t tile_buf[kPad];
   __shared__ uint32_t sh_wave[kThreads / kWave];
   const uint32_t n = get_n(d_n, n_max);
-  const uint64_t base = (uint64_t)blockIdx.x * kTile;
-  if (base >= n) return;
+  const uint32_t ntiles = (n + kTile - 1) / kTile;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t base = (uint64_t)tile * kTile;
 #pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    int j = i * kThreads + threadIdx.x;
-    uint64_t g = base + j;
-    tile[padi(j)] = g < n ? in[g] : Op::id;
-  }
-  __syncthreads();
-  uint32_t v[kItems];
-  uint32_t acc = Op::id;
+    for (int i = 0; i < kItems; i++) {
+      int j = i * kThreads + threadIdx.x;
+      uint64_t g = base + j;
+      tile_buf[padi(j)] = g < n ? in[g] : Op::id;
+    }
+    __syncthreads();
+    uint32_t v[kItems];
+    uint32_t acc = Op::id;
 #pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    v[i] = tile[padi(threadIdx.x * kItems + i)];
-    acc = Op::f(acc, v[i]);
-  }
-  uint32_t inc, exc, total;
-  block_scan<Op>(acc, sh_wave, inc, exc, total);
-  uint32_t run = Op::f(aggs[blockIdx.x], exc);
+    for (int i = 0; i < kItems; i++) {
+      v[i] = tile_buf[padi(threadIdx.x * kItems + i)];
+      acc = Op::f(acc, v[i]);
+    }
+    uint32_t inc, exc, total;
+    block_scan<Op>(acc, sh_wave, inc, exc, total);
+    uint32_t run = Op::f(aggs[tile], exc);
 #pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    uint32_t nv = Op::f(run, v[i]);
-    tile[padi(threadIdx.x * kItems + i)] = kInclusive ? nv : run;
-    run = nv;
-  }
-  __syncthreads();
+    for (int i = 0; i < kItems; i++) {
+      uint32_t nv = Op::f(run, v[i]);
+      tile_buf[padi(threadIdx.x * kItems + i)] = kInclusive ? nv : run;
+      run = nv;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < kItems; i++) {
-    int j = i * kThreads + threadIdx.x;
-    uint64_t g = base + j;
-    if (g < n) out[g] = tile[padi(j)];
+    for (int i = 0; i < kItems; i++) {
+      int j = i * kThreads + threadIdx.x;
+      uint64_t g = base + j;
+      if (g < n) out[g] = tile_buf[padi(j)];
+    }
+    __syncthreads();
   }
 }
+
+__global__ void k_copy1(uint32_t *dst, const uint32_t *src) { *dst = *src; }
 
 __global__ void k_fill(uint32_t *p, uint32_t v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
@@ -151,11 +157,12 @@ void run_scan(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n
     if (d_total) fill_u32(d_total, 0, 1, s);
     return;
   }
-  uint32_t ntiles = (n_max + kTile - 1) / kTile;
+  const uint32_t ntiles = (n_max + kTile - 1) / kTile;
+  const uint32_t grid = ntiles < 2048 ? ntiles : 2048;  // persistent grid; tiles come from the device count
   uint32_t *aggs = (uint32_t *)tmp;
-  PCBZ_LAUNCH((k_reduce<Op>), dim3(ntiles), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
+  PCBZ_LAUNCH((k_reduce<Op>), dim3(grid), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
   PCBZ_LAUNCH((k_scan_aggs<Op>), dim3(1), dim3(1024), 0, s, aggs, d_n, n_max, d_total);
-  PCBZ_LAUNCH((k_downsweep<Op, kInclusive>), dim3(ntiles), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
+  PCBZ_LAUNCH((k_downsweep<Op, kInclusive>), dim3(grid), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
 }
 
 }  // namespace
@@ -170,6 +177,10 @@ void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, 
 void scan_inclusive_max_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
                             hipStream_t s) {
   run_scan<OpMax, true>(in, out, d_n, n_max, tmp, nullptr, s);
+}
+
+void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
+  PCBZ_LAUNCH(k_copy1, dim3(1), dim3(1), 0, s, dst, src);
 }
 
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {

@@ -44,6 +44,14 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+        # torch's wheel carries its own HIP runtime with the same soname as the
+        # one libpcbz links; loading torch first makes the process use a single
+        # runtime, so torch's device memory and stream handles are the
+        # library's too.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, u32, sz, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_int
         pp = ctypes.POINTER(Params)

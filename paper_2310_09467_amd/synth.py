@@ -133,8 +133,10 @@ class VesselScene:
             parts.append((int(rng.integers(0, n_tubes)), rng.uniform(0, 1), rng.uniform(2, 10)))
         self.seed = seed
         self.particle_peak = particle_peak
-        # Static light field: point-sample each tube along its arc and across its width.
-        lam = np.full((H, W), background, np.float64)
+        # Static light field: point-sample each tube along its arc and across its
+        # width; the summed tube field is then scaled so that its 99.9th
+        # percentile adds `tube_photons` over the background.
+        lam = np.zeros((H, W), np.float64)
         self.paths = []
         for ctrl, kc, radius in tubes:
             dense = _natural_cubic(np.concatenate([ctrl, kc[:, None]], axis=1), 2000)
@@ -156,8 +158,10 @@ class VesselScene:
                 nrm = np.array([-d[1], d[0]]) / (np.hypot(d[0], d[1]) + 1e-12)
                 for o in offs:
                     w = np.exp(-(o * o) / (2 * (r_l / 2 + 1e-9) ** 2))
-                    _add_spots(lam, X + o * nrm[0], Y + o * nrm[1], k, tube_photons * w / 3.0, pitch)
-        self.static = lam
+                    _add_spots(lam, X + o * nrm[0], Y + o * nrm[1], k, w, pitch)
+        lit = lam[lam > 0]
+        scale = tube_photons / np.percentile(lit, 99.9) if lit.size else 0.0
+        self.static = background + lam * scale
         self.particles = parts
 
     def frame(self, i, shape=None, rng=None):
