@@ -122,6 +122,78 @@ int pcbz_trace_enable(pcbz_ctx *ctx, int on, const char *filter);
 int pcbz_trace_read(pcbz_ctx *ctx, char *names, size_t name_stride, double *ms, uint64_t *calls, uint64_t *bytes,
                     uint32_t max, uint32_t *n, int reset);
 
+/* ------------------------------------------------------------------------
+ * Learned arrangement selector.  The paper judges every candidate of every
+ * band (Sec. 2.1.2) and names a cheaper decision criterion as future work
+ * (Sec. 4).  The selector is a small network that predicts, from per-band
+ * features, the arrangement the judgement would choose; bands whose
+ * predicted probability reaches min_conf skip the judgement and build only
+ * the predicted arrangement, the rest are judged as usual.  Output stays a
+ * valid container whose ids may differ from the exhaustive choice.
+ *
+ * Features (pcbz_features): per band, the band's pixels are split into
+ * 64 x 64 cells (cell (i, j) covers rows [i*Hb/64, (i+1)*Hb/64) and columns
+ * [j*W/64, (j+1)*W/64), Hb = band rows); each cell gives log1p(mean),
+ * log1p(population variance), log1p(mean |x - x one lens to the left|)
+ * (pixels of the first lens column excluded from the sum, divided by all
+ * pixels) and log1p(mean |x - prev|) (0 without d_prev); empty cells are 0.
+ * Layout: FP32 [n_bands][64][64][4].
+ *
+ * Network (151,076 FP32 parameters, in this order): conv 3x3 stride 2 pad 1
+ * 4->32 (W1 [32][3][3][4], b1 [32]), ReLU; conv 32->32 (W2 [32][3][3][32],
+ * b2), ReLU; conv 32->32 (W3, b3), ReLU; FC 2048->64 (W4 [64][2048] over the
+ * 8x8x32 map flattened (y, x, c), b4), ReLU; FC 64->4 (W5 [4][64], b5).  The
+ * input is (feature - mean[c]) / std[c] (norm8 = mean[4], std[4]).  Every
+ * layer input is rounded to bfloat16 (round to nearest even) and products
+ * accumulate in FP32 on the matrix cores.
+ *
+ * A selector lives on its context's device; it may be shared by contexts on
+ * that device but not used by two calls at once.  Unset it from every
+ * context (pcbz_set_selector(ctx, NULL, 0)) before pcbz_selector_free.
+ * ------------------------------------------------------------------------ */
+typedef struct pcbz_selector pcbz_selector;
+
+size_t pcbz_selector_num_params(void);
+/* params: host FP32 array of pcbz_selector_num_params() values or NULL
+ * (zeros); norm8: host mean[4], std[4] or NULL (0 and 1). */
+int pcbz_selector_create(pcbz_ctx *ctx, const float *params, const float *norm8, pcbz_selector **out);
+void pcbz_selector_free(pcbz_selector *sel);
+int pcbz_selector_get_params(const pcbz_selector *sel, float *params, float *norm8);
+int pcbz_selector_set_params(pcbz_selector *sel, const float *params, const float *norm8);
+/* File: "PCBZSEL1", u32 parameter count, norm8, parameters (FP32 LE).
+ * Load returns PCBZ_EDATA for a bad file. */
+int pcbz_selector_save(const pcbz_selector *sel, const char *path);
+int pcbz_selector_load(pcbz_ctx *ctx, const char *path, pcbz_selector **out);
+
+/* Features of every band of one frame into d_feat (device, n_bands*16384
+ * floats).  Synchronises `stream`. */
+int pcbz_features(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                  float *d_feat, void *stream);
+/* Logits d_logits[n][4] (device) for n feature maps (device). */
+int pcbz_selector_forward(pcbz_selector *sel, const float *d_feat, uint32_t n, float *d_logits, void *stream);
+/* Softmax cross-entropy with per-class weights (class_w4, host, NULL =
+ * ones), averaged as sum w[y_i] * loss_i / sum w[y_i], over n <= 4096
+ * samples with labels d_label[n] (device, 0..3).  Writes the parameter
+ * gradient (device, num_params floats, may be NULL) and the loss (host, may
+ * be NULL). */
+int pcbz_selector_gradients(pcbz_selector *sel, const float *d_feat, const uint8_t *d_label, uint32_t n,
+                            const float *class_w4, float *d_grad, float *loss, void *stream);
+/* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay)
+ * on the gradient of the batch. */
+int pcbz_selector_train_step(pcbz_selector *sel, const float *d_feat, const uint8_t *d_label, uint32_t n,
+                             const float *class_w4, float lr, float weight_decay, float *loss, void *stream);
+/* Plain GEMM on the selector's matrix-core kernel, for checking it:
+ * C[M][N] (FP32) = A[M][K] x B[K][N], A and B row-major bfloat16 bits. */
+int pcbz_gemm_bf16(int M, int N, int K, const uint16_t *d_a, const uint16_t *d_b, float *d_c, void *stream);
+
+/* Makes pcbz_compress / pcbz_compress_batch consult `sel` (NULL: judge every
+ * band).  min_conf > 1 judges every band; 0 trusts every prediction.  Bands
+ * of frames with a caller-forced array keep the caller's ids. */
+int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf);
+/* Bands seen by the selector in the last compress call and how many of
+ * them were judged (fell below min_conf). */
+int pcbz_selector_stats(const pcbz_ctx *ctx, uint32_t *n_bands, uint32_t *n_judged);
+
 #ifdef __cplusplus
 }
 #endif

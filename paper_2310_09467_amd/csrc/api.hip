@@ -142,6 +142,10 @@ struct pcbz_ctx {
   std::vector<pcbz::TuneRec> tune;
   std::string tune_path;
   int eager_items = 8;
+  // learned arrangement selector (optional): confident bands skip the judge
+  pcbz_selector *sel = nullptr;
+  float min_conf = 1.f;
+  uint32_t last_sel_bands = 0, last_sel_fallback = 0;
 };
 
 namespace {
@@ -234,6 +238,8 @@ struct Plan {
   uint64_t ntot = 0;
   uint32_t slots = 0, segs = 0, pitch_max = 1, nt_max = 1, band_n_max = 0, lens_per_wg = 1, remap_chunks = 1;
   bool any_forced = false;
+  bool selector = false;  // the selector decides bands before the judge
+  bool use_forced() const { return any_forced || selector; }
 };
 
 int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, Plan &P) {
@@ -318,7 +324,7 @@ int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, 
   if (tl < 1) return fail(ctx, PCBZ_EINVAL, "pitch %u too large", pm);
   P.lens_per_wg = tl;
   P.remap_chunks = (P.nt_max + tl - 1) / tl;
-  (void)judge_only;
+  P.selector = !judge_only && ctx->sel != nullptr && !P.bands.empty();
   return PCBZ_OK;
 }
 
@@ -356,6 +362,7 @@ struct Work {
   uint32_t *prefix, *sym_bits, *sym_off, *blk_sym_start, *word_start, *band_len;
   uint64_t *frame_len;
   void *scan_tmp;
+  float *feat, *logits;  // selector features [band][64][64][4] and logits [band][4]
   // sizes
   uint32_t max_blocks, n_rle_max, max_chunks, max_sym, max_groups, max_words;
 };
@@ -378,6 +385,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.seg_first = A.get<uint16_t>((size_t)P.segs * 256);
   w.seg_last = A.get<uint16_t>((size_t)P.segs * 256);
   w.score = A.get<unsigned long long>(P.tasks.size() + 1);
+  w.feat = P.selector ? A.get<float>((size_t)nbands * kFeatCells * kFeatChan) : nullptr;
+  w.logits = P.selector ? A.get<float>((size_t)nbands * 4) : nullptr;
   if (!compress) return A.off;
   const uint64_t N = P.ntot;
   w.chosen = A.get<uint8_t>(N + 16);
@@ -593,13 +602,14 @@ int ensure_small(pcbz_ctx *ctx) {
 
 // Judge stages shared by pcbz_judge and the compress path.
 void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
-  launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb,
-                P.any_forced ? w.forced : nullptr, 0xFu, s);
+  const uint8_t *forced = P.use_forced() ? w.forced : nullptr;
+  launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
+                0xFu, s);
   if (!P.tasks.empty()) {
     fill_u32(w.hist, 0, (size_t)P.tasks.size() * 65536, s);
     fill_u32((uint32_t *)w.score, 0, P.tasks.size() * 2, s);
     launch_judge2(w.tasks, (uint32_t)P.tasks.size(), w.tile_task, w.tile_local, (uint32_t)P.tile_task.size(), w.cb,
-                  w.seg_first, w.seg_last, w.hist, ctx->d_tq, w.score, s);
+                  w.seg_first, w.seg_last, w.hist, ctx->d_tq, w.score, forced, s);
   }
 }
 
@@ -618,12 +628,19 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   const uint32_t N = (uint32_t)P.ntot;
   const bool eager = tu.rounds == 0;
   fill_u32(w.ctr, 0, 64, s);
-  if (P.any_forced) {
+  if (P.use_forced()) {
     launch_gather_forced(w.frames, (uint32_t)P.frames.size(), w.forced, s);
     launch_validate_forced(w.bands, nbands, w.forced, w.ctr, s);
   }
+  if (P.selector) {
+    // learned selector: confident bands get their id here and skip the judge
+    launch_features(w.bands, nbands, w.feat, s);
+    int st = selector_forward(ctx->sel, w.feat, nbands, w.logits, s);
+    if (st) return fail(ctx, st, "selector forward failed");
+    launch_select(w.logits, nbands, w.bands, ctx->min_conf, w.forced, w.ctr + 14, s);
+  }
   enqueue_judge(ctx, P, w, s);
-  launch_choose2(w.bands, nbands, w.task_of, w.score, w.tasks, P.any_forced ? w.forced : nullptr, w.choice, nullptr,
+  launch_choose2(w.bands, nbands, w.task_of, w.score, w.tasks, P.use_forced() ? w.forced : nullptr, w.choice, nullptr,
                  nullptr, s);
   launch_gather2(w.band_start, nbands, w.cb, w.choice, w.chosen, P.ntot, s);
   // first run-length stage, block cuts, CRCs
@@ -699,6 +716,8 @@ int prepare(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, Plan &P, Work &w) {
   if ((st = ensure_arena(ctx, need))) return st;
   if ((st = ensure_tables(ctx, P.band_n_max))) return st;
   if ((st = ensure_small(ctx))) return st;
+  if (P.selector && (st = selector_prepare(ctx->sel, (uint32_t)P.bands.size())))
+    return fail(ctx, st, "selector workspace allocation failed");
   Arena A{ctx->arena};
   layout(A, P, true, w);
   return PCBZ_OK;
@@ -735,17 +754,24 @@ int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, 
   ctx->last_blocks = ctr[1];
   ctx->last_rounds = (uint32_t)rounds;
   ctx->last_graph = 0;
+  ctx->last_sel_bands = P.selector ? (uint32_t)P.bands.size() : 0;
+  ctx->last_sel_fallback = P.selector ? ctr[14] : 0;
   return check_results(ctx, fin, lens, ctr);
 }
 
 // Shape signature of a batch: everything that fixes the captured launch
 // sequence (geometry, level, candidates, and which frames have prev/forced).
-std::string shape_key(const std::vector<FrameIn> &fin) {
+std::string shape_key(pcbz_ctx *ctx, const std::vector<FrameIn> &fin) {
   std::string k;
   char buf[96];
   for (const FrameIn &F : fin) {
     snprintf(buf, sizeof buf, "%ux%u/%u/%u/%x/%d%d;", F.p.h, F.p.w, F.p.pitch, F.p.level, F.p.cand_mask,
              F.prev ? 1 : 0, F.forced ? 1 : 0);
+    k += buf;
+  }
+  if (ctx->sel) {
+    snprintf(buf, sizeof buf, "sel%p/%a/%llu", (void *)ctx->sel, (double)ctx->min_conf,
+             (unsigned long long)selector_gen(ctx->sel));
     k += buf;
   }
   return k;
@@ -813,7 +839,7 @@ int launch_graph(pcbz_ctx *ctx, GraphEntry *g, hipStream_t s, float *ms) {
 // replay ends with unresolved rotations (data needing more rounds than the
 // tuned budget), the call is redone eagerly and the budget raised.
 int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, std::vector<size_t> &lens) {
-  const std::string key = shape_key(fin);
+  const std::string key = shape_key(ctx, fin);
   TuneRec *rec = nullptr;
   for (TuneRec &r : ctx->tune)
     if (r.key == key) rec = &r;
@@ -874,6 +900,8 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
   ctx->last_blocks = ctr[1];
   ctx->last_rounds = (uint32_t)tu.rounds;
   ctx->last_graph = 1;
+  ctx->last_sel_bands = P.selector ? (uint32_t)P.bands.size() : 0;
+  ctx->last_sel_fallback = P.selector ? ctr[14] : 0;
   if (ctr[9] != 0) {
     // more rounds needed than the budget: redo eagerly and remember
     st = run_compress(ctx, fin, s, lens, {});
@@ -886,6 +914,8 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
 }
 
 }  // namespace
+
+int pcbz::context_device(const pcbz_ctx *ctx) { return ctx->device; }
 
 extern "C" {
 
@@ -1074,6 +1104,56 @@ int pcbz_trace_read(pcbz_ctx *c, char *names, size_t name_stride, double *ms, ui
     pcbz::g_tracer.calls.clear();
     pcbz::g_tracer.bytes.clear();
   }
+  return PCBZ_OK;
+}
+
+int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf) {
+  if (!ctx) return PCBZ_EINVAL;
+  if (!(min_conf >= 0.f)) return fail(ctx, PCBZ_EINVAL, "min_conf must be >= 0");
+  ctx->sel = sel;
+  ctx->min_conf = min_conf;
+  return PCBZ_OK;
+}
+
+int pcbz_selector_stats(const pcbz_ctx *ctx, uint32_t *n_bands, uint32_t *n_judged) {
+  if (!ctx) return PCBZ_EINVAL;
+  if (n_bands) *n_bands = ctx->last_sel_bands;
+  if (n_judged) *n_judged = ctx->last_sel_fallback;
+  return PCBZ_OK;
+}
+
+int pcbz_features(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                  float *d_feat, void *stream) {
+  if (!ctx || !prm || !d_frame || !d_feat) return fail(ctx, PCBZ_EINVAL, "null argument");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  int st = check_params(prm);
+  if (st) return fail(ctx, st, "invalid parameters");
+  uint32_t R, nb;
+  plan_rows(prm, &R, &nb);
+  std::vector<BandDesc> bands(nb);
+  const uint32_t ns = prm->h / prm->pitch;
+  for (uint32_t k = 0; k < nb; k++) {
+    BandDesc B{};
+    B.frame = d_frame;
+    B.prev = d_prev;
+    B.W = prm->w;
+    B.pitch = prm->pitch;
+    B.Nt = prm->w / prm->pitch;
+    B.Rb = std::min(R, ns - k * R);
+    B.y0 = k * R * prm->pitch;
+    B.band_in_frame = k;
+    B.cand_mask = prm->cand_mask;
+    B.level = prm->level;
+    B.n = 2u * B.Rb * prm->pitch * prm->w;
+    bands[k] = B;
+  }
+  if ((st = ensure_arena(ctx, nb * sizeof(BandDesc) + 256))) return st;
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  HIPCHK(ctx, hipMemcpy(ctx->arena, bands.data(), nb * sizeof(BandDesc), hipMemcpyHostToDevice));
+  launch_features((const BandDesc *)ctx->arena, nb, d_feat, s);
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  HIPCHK(ctx, hipGetLastError());
   return PCBZ_OK;
 }
 

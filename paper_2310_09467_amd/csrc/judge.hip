@@ -111,12 +111,13 @@ __global__ __launch_bounds__(256) void k_remap(const BandDesc *bands, const RowI
 // ---------------------------------------------------------------- pair histogram
 __global__ __launch_bounds__(1024) void k_judge_pairs(const JudgeTask *tasks, const uint32_t *tile_task,
                                                       const uint32_t *tile_local, CandBufs cb, uint16_t *seg_first,
-                                                      uint16_t *seg_last, uint32_t *hist_g) {
+                                                      uint16_t *seg_last, uint32_t *hist_g, const uint8_t *forced) {
   __shared__ uint32_t hist[32768];  // 65536 16-bit bins
   __shared__ uint16_t lastp[kJWaves][256];
   __shared__ uint16_t firstp[kJWaves][256];
   const uint32_t ti = tile_task[blockIdx.x];
   const JudgeTask T = tasks[ti];
+  if (forced && forced[T.band] != 0xFFu) return;  // band already decided (uniform per workgroup)
   const uint8_t *x = cb.p[T.cand] + T.x_off;
   const int lane = lane_id();
   const int w = threadIdx.x / kWave;
@@ -200,10 +201,12 @@ __global__ __launch_bounds__(1024) void k_judge_pairs(const JudgeTask *tasks, co
 // value; pairs are counted in a 16-bit LDS histogram (at most 256 per tile
 // boundary plus 255 bucket boundaries per bin) and flushed once.
 __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, const uint16_t *tile_first,
-                                                     const uint16_t *tile_last, uint32_t *hist_g) {
+                                                     const uint16_t *tile_last, uint32_t *hist_g,
+                                                     const uint8_t *forced) {
   __shared__ uint32_t lh[32768];
   __shared__ uint16_t fe[256], le[256];
   const JudgeTask T = tasks[blockIdx.x];
+  if (forced && forced[T.band] != 0xFFu) return;
   const uint32_t c = threadIdx.x;
   const uint32_t ntile = (T.n + kJTile - 1) / kJTile;
   uint32_t *H = hist_g + (size_t)blockIdx.x * 65536;
@@ -259,8 +262,10 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
 
 // S[task] += sum Tq(P[t]) over 1024 bins per workgroup; clears the bins.
 __global__ __launch_bounds__(256) void k_judge_score(uint32_t *hist_g, const int64_t *tq,
-                                                     unsigned long long *score) {
+                                                     unsigned long long *score, const JudgeTask *tasks,
+                                                     const uint8_t *forced) {
   __shared__ unsigned long long part[256 / kWave];
+  if (forced && forced[tasks[blockIdx.y].band] != 0xFFu) return;  // its bins were never touched
   uint32_t *H = hist_g + (size_t)blockIdx.y * 65536 + (size_t)blockIdx.x * 1024;
   unsigned long long acc = 0;
   for (int i = threadIdx.x; i < 1024; i += 256) {
@@ -371,12 +376,12 @@ void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, 
 
 void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *tile_task, const uint32_t *tile_local,
                    uint32_t n_tiles, CandBufs cb, uint16_t *seg_first, uint16_t *seg_last, uint32_t *hist,
-                   const int64_t *tq, unsigned long long *score, hipStream_t s) {
+                   const int64_t *tq, unsigned long long *score, const uint8_t *forced, hipStream_t s) {
   if (!n_tasks) return;
   PCBZ_LAUNCH(k_judge_pairs, dim3(n_tiles), dim3(1024), 0, s, tasks, tile_task, tile_local, cb, seg_first,
-                     seg_last, hist);
-  PCBZ_LAUNCH(k_judge_fixup, dim3(n_tasks), dim3(256), 0, s, tasks, seg_first, seg_last, hist);
-  PCBZ_LAUNCH(k_judge_score, dim3(64, n_tasks), dim3(256), 0, s, hist, tq, score);
+                     seg_last, hist, forced);
+  PCBZ_LAUNCH(k_judge_fixup, dim3(n_tasks), dim3(256), 0, s, tasks, seg_first, seg_last, hist, forced);
+  PCBZ_LAUNCH(k_judge_score, dim3(64, n_tasks), dim3(256), 0, s, hist, tq, score, tasks, forced);
 }
 
 void launch_choose2(const BandDesc *bands, uint32_t n_bands, const int32_t *task_of,

@@ -191,9 +191,10 @@ size_t remap_lds_bytes(uint32_t pitch, uint32_t lens_per_wg);
 void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, uint32_t max_chunks,
                    uint32_t lens_per_wg, uint32_t pitch_max, CandBufs cb, const uint8_t *forced,
                    uint32_t write_mask, hipStream_t s);
+// forced (may be nullptr): tasks of bands whose id is not 0xFF are skipped.
 void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *tile_task, const uint32_t *tile_local,
                    uint32_t n_tiles, CandBufs cb, uint16_t *seg_first, uint16_t *seg_last, uint32_t *hist,
-                   const int64_t *tq, unsigned long long *score, hipStream_t s);
+                   const int64_t *tq, unsigned long long *score, const uint8_t *forced, hipStream_t s);
 void launch_choose2(const BandDesc *bands, uint32_t n_bands, const int32_t *task_of,
                     const unsigned long long *score, const JudgeTask *tasks, const uint8_t *forced, uint8_t *choice,
                     double *entropy, int64_t *score_out, hipStream_t s);
@@ -268,4 +269,24 @@ void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *bl
                   uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words,
                   uint32_t max_words, hipStream_t s);
 
+// ---------------------------------------------------------------- learned selector
+}  // namespace pcbz
+struct pcbz_selector;
+struct pcbz_ctx;
+namespace pcbz {
+constexpr uint32_t kFeatCells = 4096;  // 64 x 64 cells per band
+constexpr uint32_t kFeatChan = 4;
+// Per-band features [n_bands][64][64][4] (FP32) from the raw frames.
+void launch_features(const BandDesc *bands, uint32_t n_bands, float *feat, hipStream_t s);
+// Allocates the selector's workspace for batches of up to n samples (not
+// capturable: call before a graph capture).
+int selector_prepare(pcbz_selector *S, uint32_t n);
+// Workspace generation (changes whenever a buffer a captured graph uses moves).
+uint64_t selector_gen(const pcbz_selector *S);
+int context_device(const pcbz_ctx *ctx);
+int selector_forward(pcbz_selector *S, const float *feat, uint32_t n, float *logits, hipStream_t s);
+// Bands with forced == 0xFF take the network's argmax over their enabled
+// candidates if its softmax probability is >= min_conf, else stay 0xFF (judged).
+void launch_select(const float *logits, uint32_t n_bands, const BandDesc *bands, float min_conf, uint8_t *forced,
+                   uint32_t *n_fallback, hipStream_t s);
 }  // namespace pcbz

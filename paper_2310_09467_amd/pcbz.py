@@ -21,7 +21,10 @@ _NAMES = {EINVAL: "EINVAL", ENOSPC: "ENOSPC", EDATA: "EDATA", ENEEDPREV: "ENEEDP
 
 EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_judge", "pcbz_compress",
            "pcbz_compress_batch", "pcbz_peek", "pcbz_decompress", "pcbz_last_stats", "pcbz_trace_enable",
-           "pcbz_trace_read")
+           "pcbz_trace_read", "pcbz_selector_num_params", "pcbz_selector_create", "pcbz_selector_free",
+           "pcbz_selector_get_params", "pcbz_selector_set_params", "pcbz_selector_save", "pcbz_selector_load",
+           "pcbz_features", "pcbz_selector_forward", "pcbz_selector_gradients", "pcbz_selector_train_step",
+           "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats")
 
 
 class PcbzError(RuntimeError):
@@ -68,6 +71,20 @@ def load():
             "pcbz_last_stats": (i32, [vp, vp, vp, vp, vp]),
             "pcbz_trace_enable": (i32, [vp, i32, ctypes.c_char_p]),
             "pcbz_trace_read": (i32, [vp, vp, sz, vp, vp, vp, u32, vp, i32]),
+            "pcbz_selector_num_params": (sz, []),
+            "pcbz_selector_create": (i32, [vp, vp, vp, ctypes.POINTER(vp)]),
+            "pcbz_selector_free": (None, [vp]),
+            "pcbz_selector_get_params": (i32, [vp, vp, vp]),
+            "pcbz_selector_set_params": (i32, [vp, vp, vp]),
+            "pcbz_selector_save": (i32, [vp, ctypes.c_char_p]),
+            "pcbz_selector_load": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(vp)]),
+            "pcbz_features": (i32, [vp, pp, vp, vp, vp, vp]),
+            "pcbz_selector_forward": (i32, [vp, vp, u32, vp, vp]),
+            "pcbz_selector_gradients": (i32, [vp, vp, vp, u32, vp, vp, vp, vp]),
+            "pcbz_selector_train_step": (i32, [vp, vp, vp, u32, vp, ctypes.c_float, ctypes.c_float, vp, vp]),
+            "pcbz_gemm_bf16": (i32, [i32, i32, i32, vp, vp, vp, vp]),
+            "pcbz_set_selector": (i32, [vp, vp, ctypes.c_float]),
+            "pcbz_selector_stats": (i32, [vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -263,11 +280,161 @@ class Context:
             out[nm] = (ms[i], calls[i], nbytes[i])
         return out
 
+    def features(self, frame, prev=None, pitch=15, level=9, cand_mask=0x7):
+        """Per-band selector features: device float32 tensor [n_bands, 64, 64, 4]."""
+        torch = _torch()
+        f = to_device(frame)
+        pv = None if prev is None else to_device(prev)
+        h, w = f.shape
+        nb, _ = plan(h, w, pitch, level, cand_mask)
+        out = torch.empty((nb, 64, 64, 4), dtype=torch.float32, device=f.device)
+        p = Params(h, w, pitch, level, cand_mask)
+        st = load().pcbz_features(self._h, ctypes.byref(p), _ptr(f), _ptr(pv), _ptr(out), _stream())
+        if st:
+            self._err(st, "features")
+        return out
+
+    def set_selector(self, sel, min_conf=0.9):
+        """Compress calls consult `sel` (None: judge every band)."""
+        st = load().pcbz_set_selector(self._h, None if sel is None else sel._h, float(min_conf))
+        if st:
+            self._err(st, "set_selector")
+        self._sel = sel  # keeps the selector alive while it is set
+
+    def selector_stats(self):
+        """(bands seen by the selector, bands judged) of the last compress call."""
+        n, j = ctypes.c_uint32(), ctypes.c_uint32()
+        load().pcbz_selector_stats(self._h, ctypes.byref(n), ctypes.byref(j))
+        return n.value, j.value
+
     def last_stats(self):
         r, q = ctypes.c_uint64(), ctypes.c_uint64()
         nb, rounds = ctypes.c_uint32(), ctypes.c_uint32()
         load().pcbz_last_stats(self._h, ctypes.byref(r), ctypes.byref(q), ctypes.byref(nb), ctypes.byref(rounds))
         return dict(raw_bytes=r.value, rle_bytes=q.value, blocks=nb.value, bwt_rounds=rounds.value)
+
+
+def selector_num_params():
+    return int(load().pcbz_selector_num_params())
+
+
+class Selector:
+    """Learned arrangement selector (network parameters on the device)."""
+
+    def __init__(self, ctx, params=None, norm=None, _handle=None):
+        self.ctx = ctx
+        if _handle is not None:
+            self._h = _handle
+            return
+        h = ctypes.c_void_p()
+        pa = None if params is None else np.ascontiguousarray(params, np.float32)
+        if pa is not None and pa.size != selector_num_params():
+            raise ValueError(f"expected {selector_num_params()} parameters, got {pa.size}")
+        nm = None if norm is None else np.ascontiguousarray(norm, np.float32).reshape(8)
+        st = load().pcbz_selector_create(ctx._h, None if pa is None else pa.ctypes.data_as(ctypes.c_void_p),
+                                         None if nm is None else nm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+        if st:
+            raise PcbzError(st, "selector_create")
+        self._h = h
+
+    @classmethod
+    def load_file(cls, ctx, path):
+        h = ctypes.c_void_p()
+        st = load().pcbz_selector_load(ctx._h, str(path).encode(), ctypes.byref(h))
+        if st:
+            raise PcbzError(st, f"selector_load {path}")
+        return cls(ctx, _handle=h)
+
+    def save(self, path):
+        st = load().pcbz_selector_save(self._h, str(path).encode())
+        if st:
+            raise PcbzError(st, f"selector_save {path}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pcbz_selector_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        """(parameters float32[num_params], norm float32[8]) on the host."""
+        p = np.empty(selector_num_params(), np.float32)
+        nm = np.empty(8, np.float32)
+        st = load().pcbz_selector_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p),
+                                             nm.ctypes.data_as(ctypes.c_void_p))
+        if st:
+            raise PcbzError(st, "selector_get_params")
+        return p, nm
+
+    def set_params(self, params, norm=None):
+        pa = np.ascontiguousarray(params, np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, np.float32).reshape(8)
+        st = load().pcbz_selector_set_params(self._h, pa.ctypes.data_as(ctypes.c_void_p),
+                                             None if nm is None else nm.ctypes.data_as(ctypes.c_void_p))
+        if st:
+            raise PcbzError(st, "selector_set_params")
+
+    def forward(self, feat):
+        """feat: device float32 [n, 64, 64, 4] -> device float32 logits [n, 4]."""
+        torch = _torch()
+        feat = feat.contiguous()
+        n = feat.shape[0]
+        out = torch.empty((n, 4), dtype=torch.float32, device=feat.device)
+        st = load().pcbz_selector_forward(self._h, _ptr(feat), n, _ptr(out), _stream())
+        if st:
+            raise PcbzError(st, "selector_forward")
+        return out
+
+    @staticmethod
+    def _cw(class_w):
+        if class_w is None:
+            return None
+        return (ctypes.c_float * 4)(*[float(x) for x in class_w])
+
+    def gradients(self, feat, labels, class_w=None):
+        """Returns (device float32 gradient [num_params], loss)."""
+        torch = _torch()
+        feat = feat.contiguous()
+        lab = labels.to(torch.uint8).contiguous()
+        g = torch.empty(selector_num_params(), dtype=torch.float32, device=feat.device)
+        loss = ctypes.c_float()
+        st = load().pcbz_selector_gradients(self._h, _ptr(feat), _ptr(lab), feat.shape[0], self._cw(class_w), _ptr(g),
+                                            ctypes.byref(loss), _stream())
+        if st:
+            raise PcbzError(st, "selector_gradients")
+        return g, loss.value
+
+    def train_step(self, feat, labels, class_w=None, lr=1e-3, weight_decay=1e-4):
+        """One AdamW step; returns the batch loss before the step."""
+        torch = _torch()
+        feat = feat.contiguous()
+        lab = labels.to(torch.uint8).contiguous()
+        loss = ctypes.c_float()
+        st = load().pcbz_selector_train_step(self._h, _ptr(feat), _ptr(lab), feat.shape[0], self._cw(class_w),
+                                             float(lr), float(weight_decay), ctypes.byref(loss), _stream())
+        if st:
+            raise PcbzError(st, "selector_train_step")
+        return loss.value
+
+
+def gemm_bf16(a16, b16):
+    """C = A x B on the selector's matrix-core kernel; a16 [M, K], b16 [K, N] device int16 (bf16 bits)."""
+    torch = _torch()
+    a16, b16 = a16.contiguous(), b16.contiguous()
+    M, K = a16.shape
+    K2, N = b16.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    c = torch.empty((M, N), dtype=torch.float32, device=a16.device)
+    st = load().pcbz_gemm_bf16(M, N, K, _ptr(a16), _ptr(b16), _ptr(c), _stream())
+    if st:
+        raise PcbzError(st, "gemm_bf16")
+    return c
 
 
 def as_uint16(t):

@@ -1,0 +1,229 @@
+"""Trains and evaluates the learned arrangement selector on the GPU.
+
+Labels are the arrangement the entropy judgement (paper Sec. 2.1.2, Eq. 1)
+picks for each band, computed by the library's own judge kernels; features
+come from the library's feature kernel; every forward, backward and AdamW
+step runs in the library's matrix-core kernels.  torch only holds device
+buffers and does the bookkeeping of the data set (shuffling, gathering
+mini-batches, feature statistics).
+
+Data: seeded synthetic bead light fields (the frame model of Sec. 3) of
+2040 x 2040 pixels with 136 x 136 lenses, drawn with a log-uniform peak of
+10..3000 photons, 500..4000 beads and a random depth window; half of the
+frames come with a previous frame (the same beads, slightly moved and
+re-exposed), which enables the temporal candidate.  Frames are coded at
+level 9, like the benchmark workload.
+
+Evaluation on held-out frames: top-1 agreement with the judgement, and for
+each confidence threshold the share of bands still judged and the regret,
+the relative growth of the total compressed size against judging every
+band.  The threshold picked is the smallest whose regret stays within the
+budget (0.5 % by default).
+
+    python -m paper_2310_09467_amd.selector_train --out selector.bin --report report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import pcbz, synth
+
+H = W = 2040
+PITCH, LEVEL = 15, 9
+THRESHOLDS = (0.0, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.98, 0.99, 0.999, 1.01)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def draw_frame(seed):
+    """(frame, prev or None) of the training distribution."""
+    rng = np.random.default_rng(seed)
+    peak = float(np.exp(rng.uniform(np.log(10.0), np.log(3000.0))))
+    n = int(rng.integers(500, 4001))
+    centre = float(rng.uniform(-0.4, 0.4))
+    half = float(rng.uniform(0.05, 0.5))
+    frame, pos = synth.beads_frame(H, W, n, peak, seed=seed * 7 + 1, depth_window=(centre, half))
+    if rng.uniform() < 0.5:
+        return frame, None
+    moved = pos.copy()
+    moved[:, :2] += rng.normal(0.0, 0.05, size=(len(pos), 2))
+    prev, _ = synth.beads_frame(H, W, n, peak, seed=seed * 7 + 2, positions=moved)
+    return frame, prev
+
+
+class Dataset:
+    """Features (device) and judged labels of every band of a set of frames."""
+
+    def __init__(self, ctx, seeds):
+        import torch
+
+        feats, labels, self.frames = [], [], []
+        for i, sd in enumerate(seeds):
+            frame, prev = draw_frame(sd)
+            mask = 0xF if prev is not None else 0x7
+            feats.append(ctx.features(frame, prev, PITCH, LEVEL, mask))
+            labels.append(ctx.judge(frame, prev, PITCH, LEVEL, mask)[0].to(torch.int64))
+            self.frames.append((frame, prev, mask))
+            if (i + 1) % 16 == 0:
+                log(f"  {i + 1}/{len(seeds)} frames")
+        self.feat = torch.cat(feats)
+        self.label = torch.cat(labels)
+
+    def counts(self):
+        return np.bincount(self.label.cpu().numpy(), minlength=4)
+
+
+def he_params(seed):
+    """He-normal weights (fan-in), zero biases, in the library's parameter order."""
+    shapes = ((32, 3, 3, 4), (32,), (32, 3, 3, 32), (32,), (32, 3, 3, 32), (32,), (64, 2048), (64,), (4, 64), (4,))
+    rng = np.random.default_rng(seed)
+    parts = []
+    for s in shapes:
+        if len(s) == 1:
+            parts.append(np.zeros(s))
+        else:
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / np.prod(s[1:])), size=s))
+    theta = np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+    assert theta.size == pcbz.selector_num_params()
+    return theta
+
+
+def fit(ctx, data, epochs=30, batch=256, lr=1e-3, weight_decay=1e-4, seed=0):
+    """AdamW on class-weighted cross-entropy; returns (selector, loss history)."""
+    import torch
+
+    f = data.feat
+    mean = f.mean(dim=(0, 1, 2)).cpu().numpy()
+    std = f.std(dim=(0, 1, 2)).cpu().numpy() + 1e-3
+    norm = np.concatenate([mean, std]).astype(np.float32)
+    sel = pcbz.Selector(ctx, he_params(seed), norm)
+    cnt = data.counts().astype(np.float64)
+    present = cnt > 0
+    cw = np.ones(4)
+    cw[present] = cnt[present].sum() / (present.sum() * cnt[present])
+    cw = np.clip(cw, 0.25, 4.0)
+    g = torch.Generator().manual_seed(seed)
+    n = f.shape[0]
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(f.device)
+        tot = 0.0
+        for i in range(0, n, batch):
+            idx = perm[i:i + batch]
+            tot += sel.train_step(f[idx], data.label[idx], cw, lr, weight_decay) * len(idx)
+        hist.append(tot / n)
+        if ep % 5 == 0 or ep == epochs - 1:
+            log(f"  epoch {ep}: loss {hist[-1]:.4f}")
+    return sel, hist, cw
+
+
+def evaluate(ctx, sel, data, thresholds=THRESHOLDS):
+    """Agreement, per-threshold judged share and size regret on `data`."""
+    logits = sel.forward(data.feat)
+    pred = logits.argmax(dim=1)
+    agree = float((pred == data.label).float().mean())
+    exhaustive = 0
+    for frame, prev, mask in data.frames:
+        exhaustive += len(ctx.compress(frame, prev, PITCH, LEVEL, mask))
+    rows = []
+    try:
+        for tau in thresholds:
+            ctx.set_selector(sel, tau)
+            total, judged, bands = 0, 0, 0
+            for frame, prev, mask in data.frames:
+                total += len(ctx.compress(frame, prev, PITCH, LEVEL, mask))
+                nb, nj = ctx.selector_stats()
+                bands += nb
+                judged += nj
+            rows.append({"min_conf": tau, "judged_frac": judged / max(bands, 1),
+                         "regret": total / exhaustive - 1.0, "bytes": total})
+    finally:
+        ctx.set_selector(None)
+    return {"agreement": agree, "exhaustive_bytes": exhaustive, "thresholds": rows}
+
+
+def pick_threshold(rows, budget):
+    ok = [r for r in rows if r["regret"] <= budget]
+    return min(ok, key=lambda r: r["min_conf"]) if ok else rows[-1]
+
+
+def throughput(ctx, sel, frames, tau, reps=3):
+    """Input MB/s of single-frame compress calls without and with the selector."""
+    import torch
+
+    dev = [(pcbz.to_device(f), None if p is None else pcbz.to_device(p), m) for f, p, m in frames]
+    nb, bound = pcbz.plan(H, W, PITCH, LEVEL, 0xF)
+    out = torch.empty(bound, dtype=torch.uint8, device="cuda")
+
+    def run():
+        for f, p, m in dev:
+            ctx.compress_into(f, p, pcbz.Params(H, W, PITCH, LEVEL, m), out)
+
+    res = {}
+    for name, s in (("judge_all", None), ("selector", sel)):
+        ctx.set_selector(s, tau)
+        run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        res[name] = 2.0 * H * W * len(dev) * reps / (time.perf_counter() - t) / 1e6
+    ctx.set_selector(None)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-frames", type=int, default=96)
+    ap.add_argument("--test-frames", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--budget", type=float, default=0.005, help="regret budget for the threshold")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None, help="write the trained selector here")
+    ap.add_argument("--report", default=None, help="write the evaluation report (JSON) here")
+    args = ap.parse_args()
+
+    ctx = pcbz.Context(0)
+    t0 = time.perf_counter()
+    log("training frames")
+    train_set = Dataset(ctx, [1000 + args.seed * 100000 + i for i in range(args.train_frames)])
+    log("held-out frames")
+    test_set = Dataset(ctx, [5000000 + args.seed * 100000 + i for i in range(args.test_frames)])
+    t1 = time.perf_counter()
+    log("labels (train):", train_set.counts().tolist(), "(test):", test_set.counts().tolist())
+    sel, hist, cw = fit(ctx, train_set, args.epochs, args.batch, args.lr, seed=args.seed)
+    t2 = time.perf_counter()
+    ev = evaluate(ctx, sel, test_set)
+    tr = evaluate(ctx, sel, train_set, thresholds=(0.0,))
+    pick = pick_threshold(ev["thresholds"], args.budget)
+    tp = throughput(ctx, sel, test_set.frames[:8], pick["min_conf"])
+    rep = {
+        "train_bands": int(train_set.feat.shape[0]), "test_bands": int(test_set.feat.shape[0]),
+        "train_labels": train_set.counts().tolist(), "test_labels": test_set.counts().tolist(),
+        "class_weights": [float(x) for x in cw], "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+        "loss_first": hist[0], "loss_last": hist[-1],
+        "train_agreement": tr["agreement"], "test_agreement": ev["agreement"],
+        "thresholds": ev["thresholds"], "budget": args.budget, "picked": pick, "throughput_mb_s": tp,
+        "seconds": {"data": round(t1 - t0, 1), "train": round(t2 - t1, 1)},
+    }
+    if args.out:
+        sel.save(args.out)
+    out = json.dumps(rep, indent=1)
+    if args.report:
+        with open(args.report, "w") as fh:
+            fh.write(out + "\n")
+    print(out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+"""GPU parity of the learned arrangement selector against oracle/selector.py:
+the matrix-core GEMM, the band features, the network's logits and gradients,
+one AdamW step, and the compress path with the selector (lossless, equal to
+compressing with the predicted ids forced, equal to exhaustive judging when
+every band falls back)."""
+import numpy as np
+import pytest
+
+from oracle import selector as OS
+from paper_2310_09467_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_09467_amd import pcbz
+
+    return torch, pcbz, pcbz.Context(0)
+
+
+def _bf16_bits(torch, x):
+    """float64 array (already bf16-representable) -> device int16 tensor of its bf16 bits."""
+    a = np.asarray(x, np.float32).view(np.uint32) >> 16
+    return torch.from_numpy(a.astype(np.uint16).view(np.int16)).cuda()
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 16), (17, 33, 48), (100, 70, 300), (64, 64, 16),
+                                   (5, 130, 2049), (257, 3, 77)])
+def test_gemm_bf16_lane_layout(env, M, N, K):
+    torch, pcbz, _ = env
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    a = OS.bf16(rng.normal(size=(M, K)))
+    b = OS.bf16(rng.normal(size=(K, N)))
+    c = pcbz.gemm_bf16(_bf16_bits(torch, a), _bf16_bits(torch, b)).cpu().numpy()
+    ref = a @ b
+    # FP32 accumulation of K exact bf16 products
+    tol = 2e-6 * np.sqrt(K) * (np.abs(a) @ np.abs(b)) + 1e-30
+    assert np.all(np.abs(c - ref) <= tol), np.max(np.abs(c - ref) / tol)
+
+
+def _frames():
+    f1 = synth.config1_frame(11)
+    f0 = synth.config1_frame(12)
+    big, _ = synth.beads_frame(450, 300, 40, 300.0, seed=13)
+    return [(f1, None, 1), (f1, f0, 1), (big, None, 2)]
+
+
+def test_features_match_oracle(env):
+    torch, pcbz, ctx = env
+    for frame, prev, level in _frames():
+        got = ctx.features(frame, prev, 15, level, 0xF if prev is not None else 0x7).cpu().numpy()
+        ref = OS.features(frame, prev, 15, level)
+        assert got.shape == ref.shape
+        # FP64 sums of integers on both sides; only the final FP32 rounding may differ
+        np.testing.assert_allclose(got, ref, rtol=2e-7, atol=1e-7)
+
+
+def _setup(env, seed=0, n=6):
+    torch, pcbz, ctx = env
+    rng = np.random.default_rng(seed)
+    theta = OS.init_params(seed)
+    theta[OS.NUM_PARAMS - 4:] = rng.normal(0, 0.1, 4)
+    norm = np.array([5.0, 8.0, 2.0, 0.5, 1.5, 3.0, 1.0, 1.0], np.float32)
+    feats = []
+    for frame, prev, level in _frames():
+        feats.append(OS.features(frame, prev, 15, level))
+    feat = np.concatenate(feats)[:n].astype(np.float32)
+    sel = pcbz.Selector(ctx, theta.astype(np.float32), norm)
+    return torch, pcbz, ctx, sel, theta, norm.astype(np.float64), feat
+
+
+def test_forward_matches_oracle(env):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 1)
+    got = sel.forward(torch.from_numpy(feat).cuda()).cpu().numpy()
+    ref, _ = OS.forward(theta, norm, feat.astype(np.float64))
+    # bf16 rounding of FP32 vs FP64 intermediates may flip single roundings
+    scale = np.abs(ref).max() + 1e-6
+    assert np.max(np.abs(got - ref)) <= 2e-2 * scale, (got, ref)
+
+
+def test_forward_batch_invariant(env):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 2)
+    f = torch.from_numpy(feat).cuda()
+    whole = sel.forward(f).cpu().numpy()
+    for i in range(len(feat)):
+        one = sel.forward(f[i:i + 1]).cpu().numpy()
+        np.testing.assert_array_equal(one[0], whole[i])
+
+
+def test_gradients_match_oracle(env):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 3)
+    labels = np.array([0, 1, 2, 1, 0, 2][:len(feat)])
+    cw = [1.0, 2.0, 0.5, 1.0]
+    g, loss = sel.gradients(torch.from_numpy(feat).cuda(), torch.from_numpy(labels).cuda(), cw)
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref = OS.loss_and_grad(theta, norm, feat.astype(np.float64), labels, cw)
+    assert abs(loss - ref_loss) <= 1e-2 * abs(ref_loss) + 1e-4
+    G, R = OS.unpack(g), OS.unpack(ref)
+    for name, _ in OS.LAYOUT:
+        num = np.linalg.norm(G[name] - R[name])
+        den = np.linalg.norm(R[name]) + 1e-12
+        assert num / den <= 3e-2, (name, num / den)
+
+
+def test_train_step_matches_oracle_adamw(env):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 4)
+    labels = np.array([2, 0, 1, 1, 0, 2][:len(feat)])
+    lr, wd = 1e-3, 1e-2
+    sel.train_step(torch.from_numpy(feat).cuda(), torch.from_numpy(labels).cuda(), None, lr, wd)
+    got, _ = sel.params()
+    _, gref = OS.loss_and_grad(theta, norm, feat.astype(np.float64), labels)
+    ref, _, _ = OS.adamw(theta, np.zeros_like(theta), np.zeros_like(theta), gref, 1, lr, wd)
+    # the first AdamW step moves each parameter by about lr * sign(g): check the
+    # step direction where the oracle's gradient is clearly nonzero
+    step_got = got - theta * (1 - lr * wd)
+    step_ref = ref - theta * (1 - lr * wd)
+    big = np.abs(gref) > 1e-3 * np.abs(gref).max()
+    agree = np.mean(np.sign(step_got[big]) == np.sign(step_ref[big]))
+    assert agree >= 0.99, agree
+    assert np.max(np.abs(step_got)) <= lr * 1.0001
+
+
+def test_save_load_roundtrip(env, tmp_path):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 5)
+    path = tmp_path / "sel.bin"
+    sel.save(path)
+    s2 = pcbz.Selector.load_file(ctx, path)
+    p1, n1 = sel.params()
+    p2, n2 = s2.params()
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(n1, n2)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"PCBZSEL0" + bytes(64))
+    with pytest.raises(pcbz.PcbzError):
+        pcbz.Selector.load_file(ctx, bad)
+
+
+def test_compress_with_selector(env):
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 6)
+    frames = _frames()
+    try:
+        for frame, prev, level in frames:
+            mask = 0xF if prev is not None else 0x7
+            plain = ctx.compress(frame, prev, 15, level, mask)
+            # every band falls back: exhaustive bytes
+            ctx.set_selector(sel, 2.0)
+            blob = ctx.compress(frame, prev, 15, level, mask)
+            nb, judged = ctx.selector_stats()
+            assert blob == plain and judged == nb > 0
+            # every band trusted: the predicted ids, lossless
+            ctx.set_selector(sel, 0.0)
+            blob, ids = ctx.compress(frame, prev, 15, level, mask, return_choice=True)
+            nb, judged = ctx.selector_stats()
+            assert judged == 0
+            logits = sel.forward(ctx.features(frame, prev, 15, level, mask)).cpu().numpy()
+            pred = OS.predict(logits, mask, 0.0)
+            np.testing.assert_array_equal(ids, pred)
+            ctx.set_selector(None)
+            assert blob == ctx.compress(frame, prev, 15, level, mask, forced=ids)
+            out = pcbz.as_uint16(ctx.decompress(blob, prev))
+            np.testing.assert_array_equal(out, frame)
+    finally:
+        ctx.set_selector(None)
+
+
+def test_selector_in_batch_graph(env):
+    """Captured batch replays with the selector equal the eager forced result."""
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 7)
+    frames = [f for f, _, _ in _frames()]
+    params = [(15, 1, 0x7), (15, 1, 0x7), (15, 2, 0x7)]
+    try:
+        ctx.set_selector(sel, 0.6)
+        first = ctx.compress_batch(frames, None, params)
+        for _ in range(3):
+            again = ctx.compress_batch(frames, None, params)
+            assert again == first
+        ctx.set_selector(None)
+        for blob, frame, (p, lv, m) in zip(first, frames, params):
+            # expected ids: the prediction where it is confident, the judgement elsewhere
+            logits = sel.forward(ctx.features(frame, None, p, lv, m)).cpu().numpy()
+            pred = OS.predict(logits, m, 0.6)
+            judged = ctx.judge(frame, None, p, lv, m)[0].cpu().numpy()
+            ids = np.where(pred == 0xFF, judged, pred).astype(np.uint8)
+            assert blob == ctx.compress(frame, None, p, lv, m, forced=ids)
+            out = pcbz.as_uint16(ctx.decompress(blob))
+            np.testing.assert_array_equal(out, frame)
+    finally:
+        ctx.set_selector(None)
