@@ -194,6 +194,66 @@ int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf);
  * them were judged (fell below min_conf). */
 int pcbz_selector_stats(const pcbz_ctx *ctx, uint32_t *n_bands, uint32_t *n_judged);
 
+/* on = 0 makes pcbz_compress_batch run eagerly instead of capturing and
+ * replaying a graph per batch shape (useful when shapes rarely repeat).
+ * Output bytes are the same either way. */
+int pcbz_set_graphs(pcbz_ctx *ctx, int on);
+
+/* ------------------------------------------------------------------------
+ * Serving loop.  Frames arrive from cameras over time (pcbz_server_submit,
+ * host memory that must stay valid until the frame's result is polled).
+ * Admission, first in first out, gives a frame its device blocks (frame and
+ * output) from a pool holding an eighth of hbm_budget; a frame waits on the
+ * host while the pool is full.  n_workers worker threads, each with its own
+ * context and stream (and its own copy of `sel`, if given, used with
+ * min_conf), repeatedly take every admitted frame (up to max_batch_bytes of
+ * input; 0 = derived from the budget) and compress them in one
+ * pcbz_compress_batch call, so batches of different workers overlap on the
+ * device and frames that arrive meanwhile join the next batch.  The rest of
+ * the budget is split between the workers' workspaces; a batch that does not
+ * fit is split.  hbm_budget must be at least 64 MiB.
+ *
+ * Temporal candidate: when a frame's cand_mask has bit 3, the previous frame
+ * of the same camera and shape (kept on the device as camera state) is its
+ * previous frame; the first frame of a camera and shape is coded without the
+ * temporal candidate.  The result names the previous frame's tag.
+ *
+ * Each container equals what pcbz_compress gives for that frame alone with
+ * the same previous frame (and the same selector and min_conf).
+ * ------------------------------------------------------------------------ */
+typedef struct pcbz_server pcbz_server;
+
+typedef struct {
+  uint64_t tag;        /* the submit tag */
+  uint64_t prev_tag;   /* tag of the previous frame used, UINT64_MAX if none */
+  uint32_t camera;
+  int32_t status;      /* pcbz_status of the frame */
+  const uint8_t *data; /* container bytes, valid until the next pcbz_server_poll */
+  size_t len;
+  double latency_ms;   /* submit -> container in host memory */
+  double submit_ms;    /* submit time on the server's steady clock */
+} pcbz_server_result;
+
+typedef struct {
+  uint64_t submitted, completed, pending, admitted, in_flight;
+  uint64_t batches, batched_frames;
+  uint64_t pool_bytes, pool_used, pool_peak; /* device pool for frames, outputs and camera state */
+  double busy_ms;    /* time with at least one batch running */
+  double overlap_ms; /* time with two or more batches running at once */
+} pcbz_server_info;
+
+int pcbz_server_create(int hip_device, size_t hbm_budget, uint32_t n_workers, size_t max_batch_bytes,
+                       const pcbz_selector *sel, float min_conf, pcbz_server **out);
+/* Returns PCBZ_ENOMEM if the frame can never fit the pool. */
+int pcbz_server_submit(pcbz_server *srv, const pcbz_params *prm, const uint16_t *host_frame, uint32_t camera,
+                       uint64_t tag);
+/* Up to max finished results; waits up to timeout_ms (-1: until one is
+ * ready, 0: no wait).  *n receives the count. */
+int pcbz_server_poll(pcbz_server *srv, pcbz_server_result *res, uint32_t max, uint32_t *n, int timeout_ms);
+int pcbz_server_stats(const pcbz_server *srv, pcbz_server_info *st);
+/* Finishes admitted work, drops frames never admitted, frees everything. */
+void pcbz_server_destroy(pcbz_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

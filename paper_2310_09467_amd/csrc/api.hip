@@ -145,6 +145,7 @@ struct pcbz_ctx {
   // learned arrangement selector (optional): confident bands skip the judge
   pcbz_selector *sel = nullptr;
   float min_conf = 1.f;
+  bool use_graphs = true;  // pcbz_compress_batch replays captured graphs
   uint32_t last_sel_bands = 0, last_sel_fallback = 0;
 };
 
@@ -1035,8 +1036,8 @@ int pcbz_compress_batch(pcbz_ctx *ctx, uint32_t n, const pcbz_params *prm, const
     fin[i] = FrameIn{prm[i], d_frames[i], d_prevs ? d_prevs[i] : nullptr, d_forced ? d_forced[i] : nullptr, d_outs[i],
                      caps[i]};
   std::vector<size_t> out;
-  int st = getenv("PCBZ_NO_GRAPH") ? run_compress(ctx, fin, (hipStream_t)stream, out, {})
-                                     : run_compress_graph(ctx, fin, (hipStream_t)stream, out);
+  int st = (!ctx->use_graphs || getenv("PCBZ_NO_GRAPH")) ? run_compress(ctx, fin, (hipStream_t)stream, out, {})
+                                                       : run_compress_graph(ctx, fin, (hipStream_t)stream, out);
   for (uint32_t i = 0; i < n && i < out.size(); i++) lens[i] = out[i];
   return st;
 }
@@ -1112,6 +1113,12 @@ int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf) {
   if (!(min_conf >= 0.f)) return fail(ctx, PCBZ_EINVAL, "min_conf must be >= 0");
   ctx->sel = sel;
   ctx->min_conf = min_conf;
+  return PCBZ_OK;
+}
+
+int pcbz_set_graphs(pcbz_ctx *ctx, int on) {
+  if (!ctx) return PCBZ_EINVAL;
+  ctx->use_graphs = on != 0;
   return PCBZ_OK;
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_
            "pcbz_trace_read", "pcbz_selector_num_params", "pcbz_selector_create", "pcbz_selector_free",
            "pcbz_selector_get_params", "pcbz_selector_set_params", "pcbz_selector_save", "pcbz_selector_load",
            "pcbz_features", "pcbz_selector_forward", "pcbz_selector_gradients", "pcbz_selector_train_step",
-           "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats")
+           "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats", "pcbz_set_graphs", "pcbz_server_create",
+           "pcbz_server_submit", "pcbz_server_poll", "pcbz_server_stats", "pcbz_server_destroy")
 
 
 class PcbzError(RuntimeError):
@@ -36,6 +37,19 @@ class PcbzError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("h", ctypes.c_uint32), ("w", ctypes.c_uint32), ("pitch", ctypes.c_uint32),
                 ("level", ctypes.c_uint32), ("cand_mask", ctypes.c_uint32)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("prev_tag", ctypes.c_uint64), ("camera", ctypes.c_uint32),
+                ("status", ctypes.c_int32), ("data", ctypes.c_void_p), ("len", ctypes.c_size_t),
+                ("latency_ms", ctypes.c_double), ("submit_ms", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "pending", "admitted", "in_flight",
+                                               "batches", "batched_frames", "pool_bytes", "pool_used",
+                                               "pool_peak")] + [("busy_ms", ctypes.c_double),
+                                                                ("overlap_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -85,6 +99,12 @@ def load():
             "pcbz_gemm_bf16": (i32, [i32, i32, i32, vp, vp, vp, vp]),
             "pcbz_set_selector": (i32, [vp, vp, ctypes.c_float]),
             "pcbz_selector_stats": (i32, [vp, vp, vp]),
+            "pcbz_set_graphs": (i32, [vp, i32]),
+            "pcbz_server_create": (i32, [i32, sz, u32, sz, vp, ctypes.c_float, ctypes.POINTER(vp)]),
+            "pcbz_server_submit": (i32, [vp, pp, vp, u32, ctypes.c_uint64]),
+            "pcbz_server_poll": (i32, [vp, ctypes.POINTER(ServerResult), u32, vp, i32]),
+            "pcbz_server_stats": (i32, [vp, ctypes.POINTER(ServerInfo)]),
+            "pcbz_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -301,6 +321,12 @@ class Context:
             self._err(st, "set_selector")
         self._sel = sel  # keeps the selector alive while it is set
 
+    def set_graphs(self, on=True):
+        """pcbz_compress_batch: replay captured graphs (True) or run eagerly."""
+        st = load().pcbz_set_graphs(self._h, 1 if on else 0)
+        if st:
+            self._err(st, "set_graphs")
+
     def selector_stats(self):
         """(bands seen by the selector, bands judged) of the last compress call."""
         n, j = ctypes.c_uint32(), ctypes.c_uint32()
@@ -420,6 +446,73 @@ class Selector:
         if st:
             raise PcbzError(st, "selector_train_step")
         return loss.value
+
+
+class Server:
+    """Serving loop: submit host frames as they arrive, poll finished containers.
+
+    Host frames must stay alive (and unchanged) until their result is polled;
+    pinned host memory makes the uploads asynchronous.
+    """
+
+    def __init__(self, device=0, hbm_budget=32 << 30, workers=2, max_batch_bytes=0, selector=None,
+                 min_conf=1.01):
+        h = ctypes.c_void_p()
+        st = load().pcbz_server_create(device, int(hbm_budget), int(workers), int(max_batch_bytes),
+                                       None if selector is None else selector._h, float(min_conf),
+                                       ctypes.byref(h))
+        if st:
+            raise PcbzError(st, "server_create")
+        self._h = h
+        self._keep = {}  # tag -> host frame, alive until polled
+
+    def submit(self, frame, tag, camera=0, pitch=15, level=9, cand_mask=0x7):
+        """frame: host uint16 array or tensor (pinned for asynchronous upload)."""
+        if hasattr(frame, "data_ptr"):
+            ptr, (h, w) = frame.data_ptr(), tuple(frame.shape)
+        else:
+            frame = np.ascontiguousarray(frame, np.uint16)
+            ptr, (h, w) = frame.ctypes.data, frame.shape
+        p = Params(h, w, pitch, level, cand_mask)
+        self._keep[int(tag)] = frame
+        st = load().pcbz_server_submit(self._h, ctypes.byref(p), ctypes.c_void_p(ptr), int(camera), int(tag))
+        if st:
+            self._keep.pop(int(tag), None)
+            raise PcbzError(st, f"server_submit tag {tag}")
+
+    def poll(self, max_results=256, timeout_ms=0):
+        """List of dicts (tag, prev_tag, camera, status, data bytes, latency_ms, submit_ms)."""
+        res = (ServerResult * max_results)()
+        n = ctypes.c_uint32()
+        st = load().pcbz_server_poll(self._h, res, max_results, ctypes.byref(n), int(timeout_ms))
+        if st:
+            raise PcbzError(st, "server_poll")
+        out = []
+        for i in range(n.value):
+            r = res[i]
+            data = ctypes.string_at(r.data, r.len) if r.len else b""
+            self._keep.pop(int(r.tag), None)
+            out.append(dict(tag=r.tag, prev_tag=None if r.prev_tag == 2 ** 64 - 1 else r.prev_tag,
+                            camera=r.camera, status=r.status, data=data, latency_ms=r.latency_ms,
+                            submit_ms=r.submit_ms))
+        return out
+
+    def stats(self):
+        info = ServerInfo()
+        load().pcbz_server_stats(self._h, ctypes.byref(info))
+        return {n: getattr(info, n) for n, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pcbz_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gemm_bf16(a16, b16):
