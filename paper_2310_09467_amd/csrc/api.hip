@@ -363,6 +363,7 @@ struct Work {
   uint32_t *prefix, *sym_bits, *sym_off, *blk_sym_start, *word_start, *band_len;
   uint64_t *frame_len;
   void *scan_tmp;
+  size_t scan_n;  // elements the scan state is sized for
   float *feat, *logits;  // selector features [band][64][64][4] and logits [band][4]
   // sizes
   uint32_t max_blocks, n_rle_max, max_chunks, max_sym, max_groups, max_words;
@@ -456,6 +457,7 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.max_words = (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)w.max_sym * 9 / 8 + (uint64_t)S * 20600) / 4 + S);
   size_t scan_n = std::max<size_t>((size_t)w.max_sym + 2, radix_counts_words((uint32_t)nr));
   w.scan_tmp = A.get<uint8_t>(scan_tmp_bytes(scan_n));
+  w.scan_n = scan_n;
   w.bw.scan_tmp = w.scan_tmp;
   w.mw.scan_tmp = w.scan_tmp;
   return A.off;

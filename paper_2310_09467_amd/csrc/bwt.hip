@@ -12,8 +12,9 @@
 // index, which the stable sort preserved from the initial index order).
 //
 // Sorting is a least-significant-digit radix sort (8-bit digits) on 64-bit
-// keys with 32-bit values: per-tile digit counts, one exclusive scan over
-// the digit-major count table, then a stable scatter.  The scatter ranks
+// keys with 32-bit values: per-tile digit counts, an exclusive scan of each
+// digit's row of counts (one workgroup per digit, which also yields the
+// digit totals), then a stable scatter.  The scatter ranks
 // equal digits inside each wavefront with ballot matching, sorts the tile by
 // digit in LDS, and writes each digit's run with consecutive threads.
 //
@@ -66,11 +67,56 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
   }
 }
 
+// Exclusive scan of one digit's row of per-tile counts, in place; the row
+// total goes to totals[digit].  One workgroup per digit.
+template <int ITEMS>
+__global__ __launch_bounds__(kRsThreads) void k_rs_rowscan(uint32_t *counts, const uint32_t *d_n, uint32_t n_max,
+                                                           uint32_t *totals) {
+  constexpr uint32_t TILE = kRsThreads * ITEMS;
+  constexpr uint32_t kPer = 16;  // consecutive row entries per thread
+  __shared__ uint32_t wsum[kRsThreads / kWave];
+  const uint32_t n = dev_n(d_n, n_max);
+  const uint32_t nt = (n + TILE - 1) / TILE;
+  uint32_t *row = counts + (size_t)blockIdx.x * nt;
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nt; c0 += kRsThreads * kPer) {
+    const uint32_t b = c0 + threadIdx.x * kPer;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) {
+      v[i] = b + i < nt ? row[b + i] : 0u;
+      sum += v[i];
+    }
+    uint32_t incl = sum;
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+      const uint32_t t = __shfl_up(incl, dd);
+      if (lane >= dd) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = carry, chunk = 0;
+    for (int k = 0; k < kRsThreads / kWave; k++) {
+      if (k < w) before += wsum[k];
+      chunk += wsum[k];
+    }
+    uint32_t run = before + incl - sum;
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) {
+      if (b + i < nt) row[b + i] = run;
+      run += v[i];
+    }
+    carry += chunk;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
                                                            uint64_t *keys_out, uint32_t *vals_out,
                                                            const uint32_t *d_n, uint32_t n_max, int shift,
-                                                           const uint32_t *offsets) {
+                                                           const uint32_t *offsets, const uint32_t *totals) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   __shared__ uint64_t skey[TILE];
   __shared__ uint32_t sval[TILE];
@@ -84,15 +130,31 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
+  const uint32_t d0 = threadIdx.x;
+  // first output position of each digit: exclusive scan of the digit totals
+  uint32_t dbase;
+  {
+    const uint32_t tot = totals[d0];
+    uint32_t incl = tot;
+    for (int dd = 1; dd < kWave; dd <<= 1) {
+      const uint32_t t = __shfl_up(incl, dd);
+      if (lane >= dd) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    dbase = incl - tot;
+    for (int k = 0; k < w; k++) dbase += wsum[k];
+    __syncthreads();
+  }
+  const uint32_t dend = dbase + totals[d0];
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const uint64_t base = (uint64_t)tile * TILE;
     const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - base);
-    // tile-local digit counts follow from the scanned table: the next entry of
-    // the digit-major scan is the successor of (digit, tile)
-    const uint32_t d0 = threadIdx.x;
+    // tile-local digit counts follow from the row-scanned table: the next
+    // entry of the digit's row is the successor of (digit, tile)
     const size_t at = (size_t)d0 * nt + tile;
-    const uint32_t here = offsets[at];
-    const uint32_t next = (d0 == 255 && tile == nt - 1) ? n : offsets[at + 1];
+    const uint32_t here = dbase + offsets[at];
+    const uint32_t next = tile == nt - 1 ? dend : dbase + offsets[at + 1];
     const uint32_t cnt = next - here;
     gbase[d0] = here;
     // exclusive scan of the 256 counts (one per thread)
@@ -253,13 +315,15 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
   int cur = 0;
   if (n_max <= 1 || bits <= 0) return cur;
   const uint32_t ntiles = (n_max + TILE - 1) / TILE;
+  uint32_t *totals = counts + radix_counts_words(n_max) - 256;  // after the largest count table
+  (void)scan_tmp;
   const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
   for (int shift = 0; shift < bits; shift += 8) {
     PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, shift, counts,
                 d_count_n);
-    scan_exclusive_u32(counts, counts, d_count_n, 256u * ntiles, scan_tmp, nullptr, s);
+    PCBZ_LAUNCH(k_rs_rowscan<ITEMS>, dim3(256), dim3(kRsThreads), 0, s, counts, d_n, n_max, totals);
     PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
-                vals[cur ^ 1], d_n, n_max, shift, counts);
+                vals[cur ^ 1], d_n, n_max, shift, counts, totals);
     // a scatter pass reads and writes every 8-byte key and 4-byte value once
     trace_bytes("k_rs_scatter<ITEMS>", 24ull * n_max);
     cur ^= 1;

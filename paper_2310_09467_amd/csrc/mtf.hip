@@ -7,9 +7,10 @@
 // order.  So (1) every chunk computes that partial list, (2) one wavefront per
 // block chains the partial lists to get each chunk's incoming list, and
 // (3) every chunk replays move-to-front from its incoming list.  The replay
-// keeps the 256-entry list in one wavefront's registers (four entries per
-// lane); a ballot finds the symbol and a one-byte shift across lanes moves it
-// to the front.
+// keeps the list in one wavefront's registers as ranks (the position of every
+// symbol, four symbols per lane): a step reads the rank r of its symbol from
+// the owning lane, every rank below r grows by one and the symbol's rank
+// becomes 0.
 //
 // Zero runs: a run of r zero indices becomes the bijective base-2 digits of
 // r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
@@ -162,45 +163,49 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
   }
 }
 
+// New rank of a symbol at rank x when the symbol at rank r moves to the
+// front (x, r <= 255): x + 1 if x < r, 0 if x == r, else x.
+__device__ __forceinline__ uint32_t mtf_step(uint32_t x, uint32_t r) {
+  const uint32_t y = x + ((x - r) >> 31);
+  return y & (((((x ^ r) - 1u) >> 31)) - 1u);
+}
+
 __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
                                                 const uint32_t *d_n_chunks, const uint32_t *blk_start,
                                                 const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
                                                 uint8_t *idx) {
+  __shared__ uint8_t rk[256];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
   uint32_t b, p0, p1, bs, be;
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  const int lane = lane_id();
+  const uint32_t lane = (uint32_t)lane_id();
   const uint8_t *sq = seq + b * 256;
   const uint8_t *il = inlist + (size_t)c * 256;
-  uint32_t w = (uint32_t)il[4 * lane] | ((uint32_t)il[4 * lane + 1] << 8) | ((uint32_t)il[4 * lane + 2] << 16) |
-               ((uint32_t)il[4 * lane + 3] << 24);
+  // the list as ranks: lane l holds the positions of symbols l, l+64, l+128, l+192
+  for (uint32_t e = lane; e < 256; e += 64) rk[il[e]] = (uint8_t)e;
+  __syncthreads();
+  uint32_t R0 = rk[lane], R1 = rk[lane + 64], R2 = rk[lane + 128], R3 = rk[lane + 192];
   for (uint32_t base = p0; base < p1; base += 64) {
     const uint32_t p = base + lane;
     const uint32_t vl = p < p1 ? sq[L[p]] : 0u;
     const uint32_t steps = min(64u, p1 - base);
     uint32_t mine = 0;
     for (uint32_t k = 0; k < steps; k++) {
-      const uint32_t v = wave_read(vl, (int)k);
-      const uint32_t x = w ^ (v * 0x01010101u);
-      const uint32_t hz = (x - 0x01010101u) & ~x & 0x80808080u;
-      const uint64_t bal = ballot64(hz != 0);
-      const int ln = __ffsll((unsigned long long)bal) - 1;
-      const uint32_t hzl = wave_read(hz, ln);
-      const uint32_t pos = 4u * ln + (__ffs(hzl) - 1) / 8;
-      if ((uint32_t)lane == k) mine = pos;
-      if (pos != 0) {
-        uint32_t up = __shfl_up(w, 1) >> 24;
-        if (lane == 0) up = v;
-        const uint32_t shifted = (w << 8) | up;
-        const int kk = (int)pos - 4 * lane;
-        if (kk >= 3)
-          w = shifted;
-        else if (kk >= 0) {
-          const uint32_t mask = (1u << (8 * (kk + 1))) - 1u;
-          w = (shifted & mask) | (w & ~mask);
-        }
-      }
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
+      const uint32_t sl = v & 63u, j = v >> 6;
+      const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
+      const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)R1, (int)sl);
+      const uint32_t a2 = (uint32_t)__builtin_amdgcn_readlane((int)R2, (int)sl);
+      const uint32_t a3 = (uint32_t)__builtin_amdgcn_readlane((int)R3, (int)sl);
+      const uint32_t r = j == 0 ? a0 : j == 1 ? a1 : j == 2 ? a2 : a3;  // the move-to-front index
+      // symbols in front of v move back by one and v (the only rank equal
+      // to r) moves to the front; branch-free on ranks <= 255
+      R0 = mtf_step(R0, r);
+      R1 = mtf_step(R1, r);
+      R2 = mtf_step(R2, r);
+      R3 = mtf_step(R3, r);
+      mine = lane == k ? r : mine;
     }
     if (p < p1) idx[p] = (uint8_t)mine;
   }

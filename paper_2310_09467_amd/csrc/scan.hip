@@ -1,11 +1,13 @@
 // scan.hip -- device-wide prefix scans (sum and max over uint32) and fills.
 //
-// Three phases: per-tile reduction, a single-workgroup scan of the tile
-// aggregates, then a per-tile rescan that applies the carry.  A tile is
-// 256 threads x 16 items, staged through LDS so that global accesses stay
-// coalesced while each thread scans 16 consecutive items.  Sums wrap mod
-// 2^32, so differences of prefix values inside any segment whose own total
-// stays below 2^32 are exact.
+// Two launches: per-tile reductions, then a per-tile rescan from a carry
+// that each workgroup sums from the aggregates itself.  A tile is 256 threads x
+// 16 items, staged through LDS so that global accesses stay coalesced while
+// each thread scans 16 consecutive items.  (A single pass with decoupled
+// look-back measured slower here: device-scope status polls across the XCDs
+// cost about a microsecond each.)  Sums wrap mod 2^32, so differences of
+// prefix values inside any segment whose own total stays below 2^32 are
+// exact.
 #include "pcbz_internal.hpp"
 
 namespace pcbz {
@@ -15,6 +17,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTile = kThreads * kItems;
 constexpr int kPad = kTile + kTile / 32;
+constexpr uint32_t kStateWords = 16;  // reserved words in front of the tile aggregates
 
 struct OpSum {
   static __device__ __forceinline__ uint32_t f(uint32_t a, uint32_t b) { return a + b; }
@@ -61,6 +64,7 @@ __device__ void block_scan(uint32_t v, uint32_t *sh_wave, uint32_t &incl, uint32
   total = t;
 }
 
+// Phase 1: per-tile reductions over a capped grid.
 template <typename Op>
 __global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *in, const uint32_t *d_n, uint32_t n_max,
                                                      uint32_t *aggs) {
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *in, const u
     uint32_t acc = Op::id;
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-      uint64_t j = base + (uint64_t)i * kThreads + threadIdx.x;
+      const uint64_t j = base + (uint64_t)i * kThreads + threadIdx.x;
       if (j < n) acc = Op::f(acc, in[j]);
     }
     uint32_t inc, exc, total;
@@ -81,39 +85,30 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *in, const u
   }
 }
 
-// Exclusive scan of the tile aggregates in place (one workgroup of 1024).
-template <typename Op>
-__global__ __launch_bounds__(1024) void k_scan_aggs(uint32_t *aggs, const uint32_t *d_n, uint32_t n_max,
-                                                    uint32_t *d_total) {
-  __shared__ uint32_t sh_wave[1024 / kWave];
-  const uint32_t n = get_n(d_n, n_max);
-  const uint32_t ntiles = (n + kTile - 1) / kTile;
-  uint32_t carry = Op::id;
-  for (uint32_t base = 0; base < ntiles; base += 1024) {
-    uint32_t j = base + threadIdx.x;
-    uint32_t v = j < ntiles ? aggs[j] : Op::id;
-    uint32_t inc, own_excl, total;
-    block_scan<Op>(v, sh_wave, inc, own_excl, total);
-    if (j < ntiles) aggs[j] = Op::f(carry, own_excl);
-    carry = Op::f(carry, total);
-    __syncthreads();
-  }
-  if (d_total && threadIdx.x == 0) *d_total = carry;
-}
-
+// Phase 2: each workgroup reduces the aggregates in front of its tile
+// itself (a few KB from L2; later tiles of the same workgroup extend the
+// sum), then rescans its items from that carry.
 template <typename Op, bool kInclusive>
 __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t *in, uint32_t *out, const uint32_t *d_n,
-                                                        uint32_t n_max, const uint32_t *aggs) {
+                                                        uint32_t n_max, const uint32_t *aggs, uint32_t *d_total) {
   __shared__ uint32_t tile_buf[kPad];
   __shared__ uint32_t sh_wave[kThreads / kWave];
   const uint32_t n = get_n(d_n, n_max);
   const uint32_t ntiles = (n + kTile - 1) / kTile;
+  if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0 && d_total) *d_total = Op::id;
+  uint32_t carry = Op::id, counted = 0;  // carry = Op over aggs[0, counted)
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    uint32_t part = Op::id;
+    for (uint32_t j = counted + threadIdx.x; j < tile; j += kThreads) part = Op::f(part, aggs[j]);
+    uint32_t inc, exc, total;
+    block_scan<Op>(part, sh_wave, inc, exc, total);
+    carry = Op::f(carry, total);
+    counted = tile;
     const uint64_t base = (uint64_t)tile * kTile;
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-      int j = i * kThreads + threadIdx.x;
-      uint64_t g = base + j;
+      const int j = i * kThreads + threadIdx.x;
+      const uint64_t g = base + j;
       tile_buf[padi(j)] = g < n ? in[g] : Op::id;
     }
     __syncthreads();
@@ -124,22 +119,22 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t *in, uint
       v[i] = tile_buf[padi(threadIdx.x * kItems + i)];
       acc = Op::f(acc, v[i]);
     }
-    uint32_t inc, exc, total;
     block_scan<Op>(acc, sh_wave, inc, exc, total);
-    uint32_t run = Op::f(aggs[tile], exc);
+    uint32_t run = Op::f(carry, exc);
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-      uint32_t nv = Op::f(run, v[i]);
+      const uint32_t nv = Op::f(run, v[i]);
       tile_buf[padi(threadIdx.x * kItems + i)] = kInclusive ? nv : run;
       run = nv;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kItems; i++) {
-      int j = i * kThreads + threadIdx.x;
-      uint64_t g = base + j;
+      const int j = i * kThreads + threadIdx.x;
+      const uint64_t g = base + j;
       if (g < n) out[g] = tile_buf[padi(j)];
     }
+    if (tile == ntiles - 1 && d_total && threadIdx.x == 0) *d_total = Op::f(carry, total);
     __syncthreads();
   }
 }
@@ -159,15 +154,17 @@ void run_scan(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n
   }
   const uint32_t ntiles = (n_max + kTile - 1) / kTile;
   const uint32_t grid = ntiles < 2048 ? ntiles : 2048;  // persistent grid; tiles come from the device count
-  uint32_t *aggs = (uint32_t *)tmp;
+  uint32_t *aggs = (uint32_t *)tmp + kStateWords;
   PCBZ_LAUNCH((k_reduce<Op>), dim3(grid), dim3(kThreads), 0, s, in, d_n, n_max, aggs);
-  PCBZ_LAUNCH((k_scan_aggs<Op>), dim3(1), dim3(1024), 0, s, aggs, d_n, n_max, d_total);
-  PCBZ_LAUNCH((k_downsweep<Op, kInclusive>), dim3(grid), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs);
+  PCBZ_LAUNCH((k_downsweep<Op, kInclusive>), dim3(grid), dim3(kThreads), 0, s, in, out, d_n, n_max, aggs, d_total);
 }
 
 }  // namespace
 
-size_t scan_tmp_bytes(size_t n_max) { return ((n_max + kTile - 1) / kTile + 64) * sizeof(uint32_t); }
+size_t scan_tmp_bytes(size_t n_max) {
+  return (kStateWords + (n_max + kTile - 1) / kTile + 1) * sizeof(uint32_t);
+}
+
 
 void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
                         uint32_t *d_total, hipStream_t s) {
