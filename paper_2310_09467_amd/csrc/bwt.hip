@@ -243,7 +243,8 @@ __global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const ui
     mark[k] = (k == 0 || keys[k] != keys[k - 1]) ? slot[k] : 0u;
 }
 
-// Writes ranks and suffix-array entries; flags elements that stay unresolved.
+// Writes ranks, and suffix-array entries of the elements that are now in a
+// group of one (or whose block is fully compared); flags the others.
 __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
                              const uint32_t *newrank, const uint32_t *d_u, const uint32_t *blk_start,
                              const uint32_t *d_nb, uint32_t compared, uint32_t *rank, uint32_t *sa, uint32_t *unres) {
@@ -251,12 +252,13 @@ __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const u
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     const uint32_t g = vals[k];
     rank[g] = newrank[k];
-    sa[slot[k]] = g;
     const bool first = (k == 0) || keys[k] != keys[k - 1];
     const bool last = (k + 1 == U) || keys[k + 1] != keys[k];
     const uint32_t b = block_of(blk_start, nb, g);
     const uint32_t m = blk_start[b + 1] - blk_start[b];
-    unres[k] = (first && last) || m <= compared ? 0u : 1u;
+    const bool done = (first && last) || m <= compared;
+    if (done) sa[slot[k]] = g;  // final position; unresolved ones are written in a later round
+    unres[k] = done ? 0u : 1u;
   }
 }
 

@@ -6,11 +6,9 @@
 // occurrence (most recent first) move to the front, the rest keep their
 // order.  So (1) every chunk computes that partial list, (2) one wavefront per
 // block chains the partial lists to get each chunk's incoming list, and
-// (3) every chunk replays move-to-front from its incoming list.  The replay
-// keeps the list in one wavefront's registers as ranks (the position of every
-// symbol, four symbols per lane): a step reads the rank r of its symbol from
-// the owning lane, every rank below r grows by one and the symbol's rank
-// becomes 0.
+// (3) every chunk replays move-to-front from its incoming list, with the
+// same rule one level down: each lane of the chunk's wavefront replays a
+// 64-position slice from the list the wavefront chained for it.
 //
 // Zero runs: a run of r zero indices becomes the bijective base-2 digits of
 // r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
@@ -163,52 +161,110 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
   }
 }
 
-// New rank of a symbol at rank x when the symbol at rank r moves to the
-// front (x, r <= 255): x + 1 if x < r, 0 if x == r, else x.
-__device__ __forceinline__ uint32_t mtf_step(uint32_t x, uint32_t r) {
-  const uint32_t y = x + ((x - r) >> 31);
-  return y & (((((x ^ r) - 1u) >> 31)) - 1u);
-}
+// Replay of one 4096-position chunk by one wavefront: lane j owns the 64
+// positions [64j, 64j + 64) of the chunk.
+//   1. every lane lists the distinct symbols of its slice in order of last
+//      occurrence (its partial list);
+//   2. the wavefront chains the partial lists from the chunk's incoming list
+//      to get the list entering every slice (256 entries, four per lane);
+//   3. every lane replays move-to-front over its slice on its own copy of
+//      that list in LDS: one pass over the list words finds the symbol and
+//      shifts the entries in front of it by one byte.
+constexpr uint32_t kSlice = 64;          // positions per lane
+constexpr uint32_t kRowWords = 65;       // list row stride in words (bank spread)
 
 __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
                                                 const uint32_t *d_n_chunks, const uint32_t *blk_start,
                                                 const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
                                                 uint8_t *idx) {
-  __shared__ uint8_t rk[256];
+  __shared__ uint8_t sym[kChunk];               // symbols of the chunk, later its indices
+  __shared__ uint8_t part[kWave][kSlice];       // partial lists
+  __shared__ uint32_t plen[kWave];
+  __shared__ uint32_t seen[kWave][9];           // per-lane symbol bitmaps (padded)
+  __shared__ uint32_t rows[kWave * kRowWords];  // per-lane incoming lists
+  __shared__ uint32_t cur[2][64];               // chain lists (256 bytes each)
+  __shared__ uint8_t flag[256];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
   uint32_t b, p0, p1, bs, be;
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t m = p1 - p0;
   const uint8_t *sq = seq + b * 256;
-  const uint8_t *il = inlist + (size_t)c * 256;
-  // the list as ranks: lane l holds the positions of symbols l, l+64, l+128, l+192
-  for (uint32_t e = lane; e < 256; e += 64) rk[il[e]] = (uint8_t)e;
+  for (uint32_t i = lane; i < kChunk; i += kWave) sym[i] = i < m ? sq[L[p0 + i]] : (uint8_t)0;
+  for (uint32_t k = 0; k < 9; k++) seen[lane][k] = 0;
+  flag[lane] = 0;
+  flag[lane + 64] = 0;
+  flag[lane + 128] = 0;
+  flag[lane + 192] = 0;
+  cur[0][lane] = ((const uint32_t *)(inlist + (size_t)c * 256))[lane];
   __syncthreads();
-  uint32_t R0 = rk[lane], R1 = rk[lane + 64], R2 = rk[lane + 128], R3 = rk[lane + 192];
-  for (uint32_t base = p0; base < p1; base += 64) {
-    const uint32_t p = base + lane;
-    const uint32_t vl = p < p1 ? sq[L[p]] : 0u;
-    const uint32_t steps = min(64u, p1 - base);
-    uint32_t mine = 0;
-    for (uint32_t k = 0; k < steps; k++) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
-      const uint32_t sl = v & 63u, j = v >> 6;
-      const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
-      const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)R1, (int)sl);
-      const uint32_t a2 = (uint32_t)__builtin_amdgcn_readlane((int)R2, (int)sl);
-      const uint32_t a3 = (uint32_t)__builtin_amdgcn_readlane((int)R3, (int)sl);
-      const uint32_t r = j == 0 ? a0 : j == 1 ? a1 : j == 2 ? a2 : a3;  // the move-to-front index
-      // symbols in front of v move back by one and v (the only rank equal
-      // to r) moves to the front; branch-free on ranks <= 255
-      R0 = mtf_step(R0, r);
-      R1 = mtf_step(R1, r);
-      R2 = mtf_step(R2, r);
-      R3 = mtf_step(R3, r);
-      mine = lane == k ? r : mine;
-    }
-    if (p < p1) idx[p] = (uint8_t)mine;
+  // 1. partial list of this lane's slice (most recent first)
+  const uint32_t s0 = lane * kSlice;
+  const uint32_t len = s0 < m ? min(kSlice, m - s0) : 0u;
+  uint32_t np = 0;
+  for (uint32_t t = len; t-- > 0;) {
+    const uint32_t v = sym[s0 + t];
+    const uint32_t bit = 1u << (v & 31u);
+    const uint32_t old = atomicOr(&seen[lane][v >> 5], bit);
+    if (!(old & bit)) part[lane][np++] = (uint8_t)v;
   }
+  plen[lane] = np;
+  __syncthreads();
+  // 2. chain: list entering slice j+1 = partial list j, then the list entering
+  //    slice j without those symbols (order kept)
+  int cb = 0;
+  for (uint32_t j = 0; j < kWave; j++) {
+    const uint32_t w4 = cur[cb][lane];
+    rows[j * kRowWords + lane] = w4;  // lane j's incoming list
+    const uint32_t pl = plen[j];
+    if (lane < pl) flag[part[j][lane]] = 1;
+    __syncthreads();
+    uint32_t keep = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) keep |= (flag[(w4 >> (8 * q)) & 255u] ? 0u : 1u) << q;
+    const uint32_t kn = (uint32_t)__popc(keep);
+    uint32_t pos = kn;  // inclusive prefix of kept entries over lanes
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = __shfl_up(pos, d);
+      if ((int)lane >= d) pos += o;
+    }
+    pos = pl + pos - kn;
+    uint8_t *nxt = (uint8_t *)cur[cb ^ 1];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+      if ((keep >> q) & 1u) nxt[pos++] = (uint8_t)(w4 >> (8 * q));
+    if (lane < pl) {
+      nxt[lane] = part[j][lane];
+      flag[part[j][lane]] = 0;
+    }
+    __syncthreads();
+    cb ^= 1;
+  }
+  // 3. replay this lane's slice on its own list
+  uint32_t *row = rows + lane * kRowWords;
+  for (uint32_t t = 0; t < len; t++) {
+    const uint32_t v = sym[s0 + t];
+    const uint32_t pat = v * 0x01010101u;
+    uint32_t carry = v;
+    for (uint32_t k = 0; k < 64; k++) {  // the list holds every byte value: found by word 63
+      const uint32_t w = row[k];
+      const uint32_t x = w ^ pat;
+      const uint32_t hz = (x - 0x01010101u) & ~x & 0x80808080u;
+      const uint32_t sh = (w << 8) | carry;
+      if (hz) {
+        const uint32_t bpos = (uint32_t)(__ffs(hz) - 1) >> 3;
+        const uint32_t mk = bpos == 3 ? 0xFFFFFFFFu : ((1u << (8 * (bpos + 1))) - 1u);
+        row[k] = (sh & mk) | (w & ~mk);
+        sym[s0 + t] = (uint8_t)(4 * k + bpos);
+        break;
+      }
+      row[k] = sh;
+      carry = w >> 24;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = lane; i < m; i += kWave) idx[p0 + i] = sym[i];
 }
 
 // zero-run start markers: a position starts a segment if it begins the block

@@ -9,9 +9,10 @@
 // for a one-block stream) and zero padding to a byte.
 //
 // A workgroup per block builds the header bits in LDS.  Selector MTF indices
-// come from per-table last-occurrence scans: a selector seen before sits
-// behind every table used since its last use; one never seen sits behind all
-// seen tables and the unseen tables with smaller index.  Symbol bit lengths
+// come from per-table last-use scans over the workgroup's threads: a
+// selector seen before sits behind every table used since its last use; one
+// never seen sits behind all seen tables and the unseen tables with smaller
+// index.  Symbol bit lengths
 // are scanned into bit offsets, and a writer thread owns each 32-bit word of
 // a stream, assembling it from the header bits, the symbols that overlap it
 // (found by binary search) and the trailer.
@@ -71,15 +72,12 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
   __shared__ uint32_t w[kPrefixWords];
   __shared__ uint32_t shu[256];
   __shared__ int shi[256];
-  __shared__ int carry_last[kMaxGroups];
-  __shared__ int tile_last[kMaxGroups];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
   const BlockDesc B = blocks[b];
   const BlockCode C = codes[b];
   const uint32_t G = C.n_groups, nsel = C.n_sel, alpha = C.alpha;
   for (int i = threadIdx.x; i < (int)kPrefixWords; i += 256) w[i] = 0;
-  if (threadIdx.x < kMaxGroups) carry_last[threadIdx.x] = -1;
   __syncthreads();
   const uint32_t *u = used + b * 8;
   uint32_t nranges = 0;
@@ -109,52 +107,73 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
   }
   o = 137 + 16 + 16 * nranges + 18;
   __syncthreads();
-  // selectors: staged in LDS by the whole workgroup, then one wavefront walks
-  // them 64 per step; the last use of each table before a lane comes from a
-  // ballot inside the step or from the carried last use
+  // selectors: staged in LDS; each thread takes a contiguous slice.  The
+  // last use of every table before a slice is an exclusive max-scan of the
+  // slices' own last uses; with it each thread computes its selectors' MTF
+  // indices, the bit offset of its slice is a scan of the slices' bit
+  // counts, and each thread writes its slice's unary codes.
   __shared__ uint8_t ssel[kMaxSelectors];
   stage_to_lds(ssel, sel + C.sel_start, min(nsel, kMaxSelectors));
   __syncthreads();
-  if (threadIdx.x < kWave) {
-    const int lane = lane_id();
-    const uint64_t lt = lanemask_lt();
-    int carry[kMaxGroups];
-    for (int g = 0; g < kMaxGroups; g++) carry[g] = -1;
-    uint32_t pos = o;
-    for (uint32_t t0 = 0; t0 < nsel; t0 += kWave) {
-      const uint32_t j = t0 + lane;
-      const int s = j < nsel ? (int)ssel[j] : -1;
-      int last[kMaxGroups];
-      for (uint32_t g = 0; g < G; g++) {
-        const uint64_t bal = ballot64(s == (int)g);
-        const uint64_t before = bal & lt;
-        last[g] = before ? (int)(t0 + 63 - __clzll(before)) : carry[g];
-        if (bal) carry[g] = (int)(t0 + 63 - __clzll(bal));
-      }
-      uint32_t idx = 0;
-      if (s >= 0) {
-        const int ls = last[s];
-        for (uint32_t g = 0; g < G; g++) {
-          if ((int)g == s) continue;
-          if (ls >= 0)
-            idx += last[g] > ls ? 1u : 0u;
-          else
-            idx += (last[g] >= 0 || (int)g < s) ? 1u : 0u;
-        }
-      }
-      const uint32_t nbits = s >= 0 ? idx + 1 : 0;
-      uint32_t incl = nbits;
-      for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t t = __shfl_up(incl, d);
-        if (lane >= d) incl += t;
-      }
-      if (s >= 0 && idx > 0) put_bits(w, pos + incl - nbits, idx, (1u << idx) - 1u);  // idx ones; the zero is there
-      pos += wave_read(incl, kWave - 1);
+  {
+    const uint32_t K = (nsel + 255u) / 256u;
+    const uint32_t j0 = min(nsel, threadIdx.x * K), j1 = min(nsel, j0 + K);
+    int ll[kMaxGroups];
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; g++) ll[g] = -1;
+    for (uint32_t j = j0; j < j1; j++) {
+      const int sj = ssel[j];
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) ll[g] = sj == g ? (int)j : ll[g];
     }
-    if (lane == 0) shu[0] = pos;
+    int carry[kMaxGroups];
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; g++) carry[g] = block_excl_max(ll[g], shi);
+    // MTF index of selector value sv given the last uses before it
+    auto mtf_index = [&](const int *last, int sv) {
+      uint32_t idx = 0;
+      const int ls = last[sv];
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) {
+        if (g == sv || g >= (int)G) continue;
+        if (ls >= 0)
+          idx += last[g] > ls ? 1u : 0u;
+        else
+          idx += (last[g] >= 0 || g < sv) ? 1u : 0u;
+      }
+      return idx;
+    };
+    int last[kMaxGroups];
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; g++) last[g] = carry[g];
+    uint32_t bits = 0;
+    for (uint32_t j = j0; j < j1; j++) {
+      const int sj = ssel[j];
+      int lcopy[kMaxGroups];
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) lcopy[g] = last[g];
+      bits += mtf_index(lcopy, sj) + 1u;
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) last[g] = sj == g ? (int)j : last[g];
+    }
+    uint32_t tot;
+    const uint32_t base = block_excl_sum<uint32_t>(bits, shu, tot);
+    uint32_t pos = o + base;
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; g++) last[g] = carry[g];
+    for (uint32_t j = j0; j < j1; j++) {
+      const int sj = ssel[j];
+      int lcopy[kMaxGroups];
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) lcopy[g] = last[g];
+      const uint32_t idx = mtf_index(lcopy, sj);
+      if (idx > 0) put_bits(w, pos, idx, (1u << idx) - 1u);  // idx ones; the zero is already there
+      pos += idx + 1u;
+#pragma unroll
+      for (int g = 0; g < kMaxGroups; g++) last[g] = sj == g ? (int)j : last[g];
+    }
+    o += tot;
   }
-  __syncthreads();
-  o = shu[0];
   __syncthreads();
   // code lengths, per table: 5-bit start, then per symbol +1 ("10") / -1 ("11") steps and "0"
   for (uint32_t g = 0; g < G; g++) {
