@@ -12,6 +12,12 @@ Reported next to the throughput: compression ratio and its ratio to plain
 `bzip2 -9` on the raster bytes, per-frame latency percentiles, the roofline
 fraction of the dominant kernel (HIP events on the library's stream), and
 the CPU oracle timed on the host on one frame (a reported baseline).
+
+Also in the same line (not the headline value): the three frames as one
+batch through the captured-graph path, the learned selector (single calls
+and batched; its size regret against judging every band), and a short
+serving run of simulated cameras (p50/p99 latency, throughput, and how many
+served containers equal the one-frame call).
 """
 from __future__ import annotations
 
@@ -44,6 +50,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="k_rs_scatter<ITEMS>")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving leg length (0: skip)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched / selector / serving legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -110,6 +118,7 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": args.roofline_kernel,
                     "launches": calls, "avg_launch_us": round(per_launch_s * 1e6, 2),
                     "bytes_per_launch": int(per_launch_bytes)}
+    extras = {} if args.no_extras else run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args)
     cpu = None
     parity = None
     if not args.no_cpu_baseline and rank == 0:
@@ -148,8 +157,89 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     if rank == 0:
         print(json.dumps(out), flush=True)
+
+
+def timed(fn, reps):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
+    """Batched, selector and serving legs on the same frames."""
+    raw = 2 * H * W * len(frames)
+    res = {}
+    log("batched leg")
+    bprm = [prm] * len(frames)
+    blens = ctx.compress_batch_into(dev, None, bprm, outs)  # tunes and captures once
+    t = timed(lambda: ctx.compress_batch_into(dev, None, bprm, outs), 5)
+    blens = ctx.compress_batch_into(dev, None, bprm, outs)
+    batch_blobs = [outs[i][: blens[i]].cpu().numpy().tobytes() for i in range(len(frames))]
+    res["batched"] = {"value": round(raw / t / 1e6, 2), "unit": "MB/s", "frames": len(frames),
+                      "equal_to_single_calls": batch_blobs == blobs}
+    from paper_2310_09467_amd import cameras
+
+    path = cameras.DEFAULT_SELECTOR
+    if os.path.exists(path):
+        log("selector leg")
+        sel = pcbz.Selector.load_file(ctx, path)
+        tau = 0.9
+        rep_path = path.replace(".bin", "_report.json")
+        if os.path.exists(rep_path):
+            with open(rep_path) as fh:
+                tau = float(json.load(fh)["picked"]["min_conf"])
+        lens = [0] * len(frames)
+
+        def single():
+            for i in range(len(frames)):
+                lens[i] = ctx.compress_into(dev[i], None, prm, outs[i])
+
+        ctx.set_selector(sel, tau)
+        t_sel = timed(single, 5)
+        judged = ctx.selector_stats()
+        sel_bytes = sum(lens)
+        t_bsel = timed(lambda: ctx.compress_batch_into(dev, None, bprm, outs), 5)
+        ctx.set_selector(None)
+        t_plain = timed(single, 5)
+        exh = sum(len(b) for b in blobs)
+        res["selector"] = {"min_conf": tau, "single_mb_s": round(raw / t_sel / 1e6, 2),
+                           "batched_mb_s": round(raw / t_bsel / 1e6, 2),
+                           "plain_single_mb_s": round(raw / t_plain / 1e6, 2),
+                           "regret": round(sel_bytes / exh - 1.0, 6),
+                           "bands_judged_last_frame": list(judged)}
+    if args.serve_seconds > 0:
+        log("serving leg")
+        seqs = cameras.render_sequences()
+        pool = cameras.pools(seqs)
+        events = cameras.schedule(4, 50.0, args.serve_seconds)
+        sel = pcbz.Selector.load_file(ctx, path) if os.path.exists(path) else None
+        srv = pcbz.Server(0, 32 << 30, 2, 0, sel, 0.9)
+        warm = [(0.0, 1000 + c, si) for c in range(2) for si in range(len(cameras.SIZES))]
+        cameras.run(srv, pool, warm, temporal=False, tag0=1 << 40)
+        results, src, t0 = cameras.run(srv, pool, events, True)
+        summ = cameras.summarize(results, events, src, pool, t0)
+        st = srv.stats()
+        srv.close()
+        ver = cameras.verify(results, src, pool, seqs, 24, sel, 0.9)
+        res["serving"] = {"cameras": 4, "rate_per_camera": 50.0, "seconds": args.serve_seconds, "frames": summ["frames"],
+                          "throughput_mb_s": round(summ["throughput_mb_s"], 2),
+                          "offered_mb_s": round(summ["offered_mb_s"], 2),
+                          "latency_ms": {k: round(v, 3) for k, v in summ["latency_ms"].items()},
+                          "ratio": round(summ["ratio"], 4), "hbm_budget_gb": 32,
+                          "pool_peak_mb": round(st["pool_peak"] / 1e6, 1),
+                          "overlap_frac": round(st["overlap_ms"] / max(st["busy_ms"], 1e-9), 3),
+                          "mean_batch": round(st["batched_frames"] / max(st["batches"], 1), 2),
+                          "equal_alone": f"{ver['equal_alone']}/{ver['checked']}"}
+    return res
 
 
 if __name__ == "__main__":

@@ -719,8 +719,6 @@ int prepare(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, Plan &P, Work &w) {
   if ((st = ensure_arena(ctx, need))) return st;
   if ((st = ensure_tables(ctx, P.band_n_max))) return st;
   if ((st = ensure_small(ctx))) return st;
-  if (P.selector && (st = selector_prepare(ctx->sel, (uint32_t)P.bands.size())))
-    return fail(ctx, st, "selector workspace allocation failed");
   Arena A{ctx->arena};
   layout(A, P, true, w);
   return PCBZ_OK;

@@ -235,38 +235,149 @@ __global__ void k_norm_input(const float *f, long n, const float *mean, const fl
 }
 
 // ---------------------------------------------------------------- features
-// One thread per (band, cell); cells split the band's Hb x W pixels 64 x 64.
-__global__ void k_features(const BandDesc *bands, uint32_t n_bands, float *feat) {
-  const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t b = blockIdx.y;
-  if (b >= n_bands || cell >= 4096) return;
+// One workgroup per (cell row, band).  Threads walk pixel columns (coalesced
+// row reads) and sum each column's pixels of the cell row exactly in
+// integers, then add the column sums into the column's cell in LDS; 64
+// threads finish the cells.  The integer sums equal the double sums of the
+// definition, so the results are the same.
+__global__ __launch_bounds__(256) void k_features(const BandDesc *bands, uint32_t n_bands, float *feat) {
+  __shared__ unsigned long long s_sum[64], s_sq[64], s_dx[64], s_dt[64];
+  const uint32_t ci = blockIdx.x, b = blockIdx.y;
+  if (b >= n_bands) return;
   const BandDesc B = bands[b];
   const uint32_t Hb = B.Rb * B.pitch, W = B.W, p = B.pitch;
-  const uint32_t ci = cell / 64, cj = cell % 64;
-  const uint32_t y0 = ci * Hb / 64, y1 = (ci + 1) * Hb / 64, x0 = cj * W / 64, x1 = (cj + 1) * W / 64;
-  double s = 0, s2 = 0, sd = 0, st = 0;
-  const uint32_t cnt = (y1 - y0) * (x1 - x0);
-  for (uint32_t y = y0; y < y1; y++) {
-    const uint16_t *row = B.frame + (size_t)(B.y0 + y) * W;
-    const uint16_t *prow = B.prev ? B.prev + (size_t)(B.y0 + y) * W : nullptr;
-    for (uint32_t x = x0; x < x1; x++) {
-      const double v = row[x];
-      s += v;
-      s2 += v * v;
-      if (x >= p) sd += fabs(v - (double)row[x - p]);
-      if (prow) st += fabs(v - (double)prow[x]);
+  const uint32_t y0 = ci * Hb / 64, y1 = (ci + 1) * Hb / 64;
+  if (threadIdx.x < 64) {
+    s_sum[threadIdx.x] = 0;
+    s_sq[threadIdx.x] = 0;
+    s_dx[threadIdx.x] = 0;
+    s_dt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (uint32_t x = threadIdx.x; x < W; x += blockDim.x) {
+    unsigned long long sum = 0, sq = 0, dx = 0, dt = 0;
+    for (uint32_t y = y0; y < y1; y++) {
+      const size_t o = (size_t)(B.y0 + y) * W + x;
+      const uint32_t v = B.frame[o];
+      sum += v;
+      sq += (unsigned long long)v * v;
+      if (x >= p) dx += (uint32_t)abs((int)v - (int)B.frame[o - p]);
+      if (B.prev) dt += (uint32_t)abs((int)v - (int)B.prev[o]);
+    }
+    if (y1 > y0) {
+      // cell j covers columns [j*W/64, (j+1)*W/64)
+      const uint32_t j = min(63u, (uint32_t)(((uint64_t)x * 64 + 63) / W));
+      atomicAdd(&s_sum[j], sum);
+      atomicAdd(&s_sq[j], sq);
+      atomicAdd(&s_dx[j], dx);
+      atomicAdd(&s_dt[j], dt);
     }
   }
-  float *o = feat + ((size_t)b * 4096 + cell) * 4;
-  if (cnt == 0) {
-    o[0] = o[1] = o[2] = o[3] = 0.f;
-    return;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const uint32_t cj = threadIdx.x;
+    const uint32_t x0 = cj * W / 64, x1 = (cj + 1) * W / 64;
+    const uint32_t cnt = (y1 - y0) * (x1 - x0);
+    float *o = feat + ((size_t)b * 4096 + ci * 64 + cj) * 4;
+    if (cnt == 0) {
+      o[0] = o[1] = o[2] = o[3] = 0.f;
+    } else {
+      const double mean = (double)s_sum[cj] / cnt, var = fmax((double)s_sq[cj] / cnt - mean * mean, 0.0);
+      o[0] = (float)log1p(mean);
+      o[1] = (float)log1p(var);
+      o[2] = (float)log1p((double)s_dx[cj] / cnt);
+      o[3] = (float)log1p((double)s_dt[cj] / cnt);
+    }
   }
-  const double mean = s / cnt, var = fmax(s2 / cnt - mean * mean, 0.0);
-  o[0] = (float)log1p(mean);
-  o[1] = (float)log1p(var);
-  o[2] = (float)log1p(sd / cnt);
-  o[3] = (float)log1p(st / cnt);
+}
+
+// ---------------------------------------------------------------- fused inference
+// The whole network for one band per workgroup (four wavefronts), with every
+// activation in LDS.  Convolutions are tiles of 16 output pixels x 16
+// channels on the matrix cores; a lane's A operand is four consecutive
+// channels of one input pixel (one 8-byte LDS read) and its B operand four
+// consecutive weights of one output channel.  The fully connected layers
+// use the same instruction with the sample in row 0.  K is walked in steps
+// of 16 in the same order as the layer-by-layer path, so both give the same
+// logits.
+template <int H, int C>
+__device__ __forceinline__ void conv_tile_layer(const uint16_t *X, const uint16_t *Wt, const float *bias,
+                                                uint16_t *Y) {
+  constexpr int Ho = H / 2, M = Ho * Ho, K = 9 * C, KS = (K + 15) / 16;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int r = lane & 15, q = lane >> 4;
+  for (int mt = w; mt < M / 16; mt += 4) {
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    const int m = mt * 16 + r, oy = m / Ho, ox = m % Ho;
+    for (int ks = 0; ks < KS; ks++) {
+      const int k0 = ks * 16 + 4 * q;  // this lane's first k
+      bf16x4 a = {0, 0, 0, 0}, b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+      if (k0 < K) {
+        const int pos = k0 / C, c0 = k0 % C, ky = pos / 3, kx = pos % 3;
+        const int iy = 2 * oy - 1 + ky, ix = 2 * ox - 1 + kx;
+        if (iy >= 0 && iy < H && ix >= 0 && ix < H) a = *(const bf16x4 *)(X + (iy * H + ix) * C + c0);
+        b0 = *(const bf16x4 *)(Wt + (size_t)r * K + k0);
+        b1 = *(const bf16x4 *)(Wt + (size_t)(16 + r) * K + k0);
+      }
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int mo = mt * 16 + 4 * q + j;
+      Y[mo * 32 + r] = f2bf(fmaxf(acc0[j] + bias[r], 0.f));
+      Y[mo * 32 + 16 + r] = f2bf(fmaxf(acc1[j] + bias[16 + r], 0.f));
+    }
+  }
+}
+
+// out = W x (+ bias, ReLU to bf16 or plain FP32) for one sample: x has K
+// entries, W is [N][K]; wavefront w computes outputs [16w, 16w + 16).
+template <int K, int N>
+__device__ __forceinline__ void fc_layer(const uint16_t *x, const uint16_t *Wt, const float *bias, uint16_t *out16,
+                                         float *out32) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int r = lane & 15, q = lane >> 4;
+  if (w * 16 >= N) return;
+  const int n = w * 16 + r;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 4 * q; k0 < K; k0 += 16) {
+    bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+    if (r == 0) a = *(const bf16x4 *)(x + k0);
+    if (n < N) b = *(const bf16x4 *)(Wt + (size_t)n * K + k0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  // row 0 of the result sits in lanes 0..15, element 0
+  if (q == 0 && n < N) {
+    const float v = acc[0] + bias[n];
+    if (out16) out16[n] = f2bf(fmaxf(v, 0.f));
+    if (out32) out32[n] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sel_infer(const float *feat, const float *norm, const uint16_t *p16,
+                                                   const float *p, long oW1, long oB1, long oW2, long oB2, long oW3,
+                                                   long oB3, long oW4, long oB4, long oW5, long oB5,
+                                                   float *logits) {
+  __shared__ __align__(16) uint16_t bufA[64 * 64 * 4];    // x0, then x2
+  __shared__ __align__(16) uint16_t bufB[32 * 32 * 32];   // x1, then x3
+  __shared__ __align__(16) uint16_t x4[64];
+  const size_t sample = blockIdx.x;
+  const float *f = feat + sample * 16384;
+  for (int i = threadIdx.x; i < 16384; i += 256) {
+    const int c = i & 3;
+    bufA[i] = f2bf((f[i] - norm[c]) / norm[4 + c]);
+  }
+  __syncthreads();
+  conv_tile_layer<64, 4>(bufA, p16 + oW1, p + oB1, bufB);
+  __syncthreads();
+  conv_tile_layer<32, 32>(bufB, p16 + oW2, p + oB2, bufA);
+  __syncthreads();
+  conv_tile_layer<16, 32>(bufA, p16 + oW3, p + oB3, bufB);
+  __syncthreads();
+  fc_layer<2048, 64>(bufB, p16 + oW4, p + oB4, x4, nullptr);
+  __syncthreads();
+  fc_layer<64, 4>(x4, p16 + oW5, p + oB5, nullptr, logits + sample * 4);
 }
 
 // Confident bands get the network's choice; the rest (p_max < min_conf) are
@@ -497,30 +608,18 @@ int upload_params(pcbz_selector *S, const float *host) {
 
 }  // namespace
 
-int selector_prepare(pcbz_selector *S, uint32_t n) {
-  (void)hipSetDevice(S->device);
-  return ensure_work(S, std::min<uint32_t>(std::max<uint32_t>(n, 1), 256));
-}
-
 uint64_t selector_gen(const pcbz_selector *S) { return S->gen; }
 
 int selector_forward(pcbz_selector *S, const float *feat, uint32_t n, float *logits, hipStream_t s) {
-  const uint32_t chunk = 256;
-  int st = ensure_work(S, std::min(n, chunk));
-  if (st) return st;
-  for (uint32_t i = 0; i < n; i += chunk) {
-    const uint32_t k = std::min(chunk, n - i);
-    forward(S, feat + (size_t)i * 4096 * 4, k, s);
-    if (hipMemcpyAsync(logits + (size_t)i * 4, S->w.logits, (size_t)k * 4 * sizeof(float), hipMemcpyDeviceToDevice,
-                       s) != hipSuccess)
-      return PCBZ_EDEVICE;
-  }
+  if (!n) return PCBZ_OK;
+  PCBZ_LAUNCH(k_sel_infer, dim3(n), dim3(256), 0, s, feat, S->d_norm, S->p16, S->p, kW1, kB1, kW2, kB2, kW3, kB3,
+              kW4, kB4, kW5, kB5, logits);
   return PCBZ_OK;
 }
 
 void launch_features(const BandDesc *bands, uint32_t n_bands, float *feat, hipStream_t s) {
   if (!n_bands) return;
-  PCBZ_LAUNCH(k_features, dim3(16, n_bands), dim3(256), 0, s, bands, n_bands, feat);
+  PCBZ_LAUNCH(k_features, dim3(64, n_bands), dim3(256), 0, s, bands, n_bands, feat);
 }
 
 void launch_select(const float *logits, uint32_t n_bands, const BandDesc *bands, float min_conf, uint8_t *forced,

@@ -6,9 +6,8 @@
 // occurrence (most recent first) move to the front, the rest keep their
 // order.  So (1) every chunk computes that partial list, (2) one wavefront per
 // block chains the partial lists to get each chunk's incoming list, and
-// (3) every chunk replays move-to-front from its incoming list, with the
-// same rule one level down: each lane of the chunk's wavefront replays a
-// 64-position slice from the list the wavefront chained for it.
+// (3) every chunk replays move-to-front from its incoming list (ranks in
+// registers, see k_mtf_run).
 //
 // Zero runs: a run of r zero indices becomes the bijective base-2 digits of
 // r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
@@ -161,110 +160,62 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
   }
 }
 
-// Replay of one 4096-position chunk by one wavefront: lane j owns the 64
-// positions [64j, 64j + 64) of the chunk.
-//   1. every lane lists the distinct symbols of its slice in order of last
-//      occurrence (its partial list);
-//   2. the wavefront chains the partial lists from the chunk's incoming list
-//      to get the list entering every slice (256 entries, four per lane);
-//   3. every lane replays move-to-front over its slice on its own copy of
-//      that list in LDS: one pass over the list words finds the symbol and
-//      shifts the entries in front of it by one byte.
-constexpr uint32_t kSlice = 64;          // positions per lane
-constexpr uint32_t kRowWords = 65;       // list row stride in words (bank spread)
+// Replay of one chunk by one wavefront.  The list is held as ranks (the
+// position of each symbol), 16 bits per symbol, two symbols per register and
+// two registers per lane: lane l holds the ranks of symbols l and l + 64
+// (R0 low / high half) and l + 128 and l + 192 (R1).  A step reads the rank
+// r of its symbol from the owning lane (uniform), then every lane updates
+// both halves of both registers with packed 16-bit arithmetic: ranks below r
+// grow by one, the rank equal to r (the symbol itself; ranks are distinct)
+// becomes 0.  No lane diverges and no data moves between lanes.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+// ranks x (two halves, each <= 255) after the symbol at rank r moves to front
+__device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r2) {
+  const u16x2 xv = as_u16x2(x), rv = as_u16x2(r2);
+  const u16x2 lt = (u16x2)((xv - rv) >> (u16x2)15);                       // 1 where x < r
+  const u16x2 ne = (u16x2)(((xv ^ rv) + (u16x2)0x7FFF) >> (u16x2)15);      // 1 where x != r
+  return as_u32((xv + lt) * ne);
+}
 
 __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
                                                 const uint32_t *d_n_chunks, const uint32_t *blk_start,
                                                 const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
                                                 uint8_t *idx) {
-  __shared__ uint8_t sym[kChunk];               // symbols of the chunk, later its indices
-  __shared__ uint8_t part[kWave][kSlice];       // partial lists
-  __shared__ uint32_t plen[kWave];
-  __shared__ uint32_t seen[kWave][9];           // per-lane symbol bitmaps (padded)
-  __shared__ uint32_t rows[kWave * kRowWords];  // per-lane incoming lists
-  __shared__ uint32_t cur[2][64];               // chain lists (256 bytes each)
-  __shared__ uint8_t flag[256];
+  __shared__ uint8_t rk[256];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
   uint32_t b, p0, p1, bs, be;
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   const uint32_t lane = (uint32_t)lane_id();
-  const uint32_t m = p1 - p0;
   const uint8_t *sq = seq + b * 256;
-  for (uint32_t i = lane; i < kChunk; i += kWave) sym[i] = i < m ? sq[L[p0 + i]] : (uint8_t)0;
-  for (uint32_t k = 0; k < 9; k++) seen[lane][k] = 0;
-  flag[lane] = 0;
-  flag[lane + 64] = 0;
-  flag[lane + 128] = 0;
-  flag[lane + 192] = 0;
-  cur[0][lane] = ((const uint32_t *)(inlist + (size_t)c * 256))[lane];
+  const uint8_t *il = inlist + (size_t)c * 256;
+  for (uint32_t e = lane; e < 256; e += 64) rk[il[e]] = (uint8_t)e;
   __syncthreads();
-  // 1. partial list of this lane's slice (most recent first)
-  const uint32_t s0 = lane * kSlice;
-  const uint32_t len = s0 < m ? min(kSlice, m - s0) : 0u;
-  uint32_t np = 0;
-  for (uint32_t t = len; t-- > 0;) {
-    const uint32_t v = sym[s0 + t];
-    const uint32_t bit = 1u << (v & 31u);
-    const uint32_t old = atomicOr(&seen[lane][v >> 5], bit);
-    if (!(old & bit)) part[lane][np++] = (uint8_t)v;
-  }
-  plen[lane] = np;
-  __syncthreads();
-  // 2. chain: list entering slice j+1 = partial list j, then the list entering
-  //    slice j without those symbols (order kept)
-  int cb = 0;
-  for (uint32_t j = 0; j < kWave; j++) {
-    const uint32_t w4 = cur[cb][lane];
-    rows[j * kRowWords + lane] = w4;  // lane j's incoming list
-    const uint32_t pl = plen[j];
-    if (lane < pl) flag[part[j][lane]] = 1;
-    __syncthreads();
-    uint32_t keep = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) keep |= (flag[(w4 >> (8 * q)) & 255u] ? 0u : 1u) << q;
-    const uint32_t kn = (uint32_t)__popc(keep);
-    uint32_t pos = kn;  // inclusive prefix of kept entries over lanes
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = __shfl_up(pos, d);
-      if ((int)lane >= d) pos += o;
+  uint32_t R0 = (uint32_t)rk[lane] | ((uint32_t)rk[lane + 64] << 16);
+  uint32_t R1 = (uint32_t)rk[lane + 128] | ((uint32_t)rk[lane + 192] << 16);
+  for (uint32_t base = p0; base < p1; base += 64) {
+    const uint32_t p = base + lane;
+    const uint32_t vl = p < p1 ? sq[L[p]] : 0u;
+    const uint32_t steps = min(64u, p1 - base);
+    uint32_t mine = 0;
+    for (uint32_t k = 0; k < steps; k++) {
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
+      const uint32_t sl = v & 63u;
+      const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
+      const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)R1, (int)sl);
+      const uint32_t word = (v & 128u) ? a1 : a0;
+      const uint32_t r = (v & 64u) ? (word >> 16) : (word & 0xFFFFu);  // the move-to-front index
+      const uint32_t r2 = r * 0x10001u;
+      R0 = mtf_ranks(R0, r2);
+      R1 = mtf_ranks(R1, r2);
+      mine = lane == k ? r : mine;
     }
-    pos = pl + pos - kn;
-    uint8_t *nxt = (uint8_t *)cur[cb ^ 1];
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-      if ((keep >> q) & 1u) nxt[pos++] = (uint8_t)(w4 >> (8 * q));
-    if (lane < pl) {
-      nxt[lane] = part[j][lane];
-      flag[part[j][lane]] = 0;
-    }
-    __syncthreads();
-    cb ^= 1;
+    if (p < p1) idx[p] = (uint8_t)mine;
   }
-  // 3. replay this lane's slice on its own list
-  uint32_t *row = rows + lane * kRowWords;
-  for (uint32_t t = 0; t < len; t++) {
-    const uint32_t v = sym[s0 + t];
-    const uint32_t pat = v * 0x01010101u;
-    uint32_t carry = v;
-    for (uint32_t k = 0; k < 64; k++) {  // the list holds every byte value: found by word 63
-      const uint32_t w = row[k];
-      const uint32_t x = w ^ pat;
-      const uint32_t hz = (x - 0x01010101u) & ~x & 0x80808080u;
-      const uint32_t sh = (w << 8) | carry;
-      if (hz) {
-        const uint32_t bpos = (uint32_t)(__ffs(hz) - 1) >> 3;
-        const uint32_t mk = bpos == 3 ? 0xFFFFFFFFu : ((1u << (8 * (bpos + 1))) - 1u);
-        row[k] = (sh & mk) | (w & ~mk);
-        sym[s0 + t] = (uint8_t)(4 * k + bpos);
-        break;
-      }
-      row[k] = sh;
-      carry = w >> 24;
-    }
-  }
-  __syncthreads();
-  for (uint32_t i = lane; i < m; i += kWave) idx[p0 + i] = sym[i];
 }
 
 // zero-run start markers: a position starts a segment if it begins the block

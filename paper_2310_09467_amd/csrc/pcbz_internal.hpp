@@ -278,12 +278,10 @@ constexpr uint32_t kFeatCells = 4096;  // 64 x 64 cells per band
 constexpr uint32_t kFeatChan = 4;
 // Per-band features [n_bands][64][64][4] (FP32) from the raw frames.
 void launch_features(const BandDesc *bands, uint32_t n_bands, float *feat, hipStream_t s);
-// Allocates the selector's workspace for batches of up to n samples (not
-// capturable: call before a graph capture).
-int selector_prepare(pcbz_selector *S, uint32_t n);
-// Workspace generation (changes whenever a buffer a captured graph uses moves).
+// Generation of the selector's device buffers (changes whenever one moves).
 uint64_t selector_gen(const pcbz_selector *S);
 int context_device(const pcbz_ctx *ctx);
+// Logits of n feature maps: one fused inference kernel (capturable).
 int selector_forward(pcbz_selector *S, const float *feat, uint32_t n, float *logits, hipStream_t s);
 // Bands with forced == 0xFF take the network's argmax over their enabled
 // candidates if its softmax probability is >= min_conf, else stay 0xFF (judged).

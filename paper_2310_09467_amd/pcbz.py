@@ -263,6 +263,21 @@ class Context:
             self._err(st, "compress_batch")
         return [outs[i][: lens[i]].cpu().numpy().tobytes() for i in range(n)]
 
+    def compress_batch_into(self, dev_frames, dev_prevs, params, outs):
+        """Device-level batch call: device int16 frames (and prevs or None),
+        Params list, device uint8 output tensors.  Returns the lengths."""
+        n = len(dev_frames)
+        prm = (Params * n)(*params)
+        VP = ctypes.c_void_p * n
+        caps = (ctypes.c_size_t * n)(*[o.numel() for o in outs])
+        lens = (ctypes.c_size_t * n)()
+        d_prevs = None if dev_prevs is None else VP(*[0 if p is None else p.data_ptr() for p in dev_prevs])
+        st = load().pcbz_compress_batch(self._h, n, prm, VP(*[f.data_ptr() for f in dev_frames]), d_prevs, None,
+                                        VP(*[o.data_ptr() for o in outs]), caps, lens, _stream())
+        if st:
+            self._err(st, "compress_batch")
+        return list(lens)
+
     def decompress(self, blob, prev=None):
         """Decodes a container (host bytes) into a device int16 tensor (uint16 bits)."""
         torch = _torch()

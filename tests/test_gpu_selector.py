@@ -190,3 +190,16 @@ def test_selector_in_batch_graph(env):
             np.testing.assert_array_equal(out, frame)
     finally:
         ctx.set_selector(None)
+
+
+def test_fused_inference_matches_layer_path(env):
+    """The fused inference kernel and the layer-by-layer training forward give
+    the same logits (same k order on the matrix cores): the loss the training
+    path reports equals the loss of the fused logits."""
+    torch, pcbz, ctx, sel, theta, norm, feat = _setup(env, 8)
+    labels = np.array([3, 1, 0, 2, 1, 0][:len(feat)])
+    f = torch.from_numpy(feat).cuda()
+    logits = sel.forward(f).cpu().numpy().astype(np.float64)
+    _, loss = sel.gradients(f, torch.from_numpy(labels).cuda())
+    ref, _ = OS.softmax_ce(logits, labels)
+    assert abs(loss - ref) <= 2e-6 * abs(ref) + 1e-7, (loss, ref)
