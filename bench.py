@@ -52,7 +52,12 @@ def main():
     ap.add_argument("--roofline-kernel", default="k_rs_scatter<ITEMS>")
     ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving leg length (0: skip)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / selector / serving legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain device-to-device copies of 256 MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the path shards by camera / frame across GPUs, see the design notes)", file=sys.stderr)
@@ -114,10 +119,12 @@ def main():
         # once (24 B per element of the suffix-sort working set).
         per_launch_bytes = nbytes / calls
         achieved = per_launch_bytes / per_launch_s / 1e9 if per_launch_s > 0 else 0.0
+        traffic = measured_traffic(args.roofline_kernel)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": args.roofline_kernel,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": args.roofline_kernel,
                     "launches": calls, "avg_launch_us": round(per_launch_s * 1e6, 2),
-                    "bytes_per_launch": int(per_launch_bytes)}
+                    "bytes_per_launch": int(per_launch_bytes),
+                    "traffic_over_algorithmic": None if traffic is None else round(traffic / per_launch_bytes, 3)}
     extras = {} if args.no_extras else run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args)
     cpu = None
     parity = None
@@ -160,6 +167,41 @@ def main():
     out.update(extras)
     if rank == 0:
         print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when there is
+    none or the kernel's source changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md")):
+        m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("kernel") != kernel:
+            continue
+        src = os.path.join(ROOT, rec["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+            return None
+        return int(rec["traffic_bytes_per_launch"])
+    return None
+
+
+def calibrate_copy(nbytes=256 << 20, reps=4):
+    """Plain device copies of a known size: the HBM counters of the copy kernel
+    give the factor between counter units and bytes."""
+    import torch
+
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": reps}), flush=True)
 
 
 def timed(fn, reps):

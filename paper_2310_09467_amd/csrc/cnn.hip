@@ -341,6 +341,7 @@ __device__ __forceinline__ void fc_layer(const uint16_t *x, const uint16_t *Wt, 
   if (w * 16 >= N) return;
   const int n = w * 16 + r;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
   for (int k0 = 4 * q; k0 < K; k0 += 16) {
     bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
     if (r == 0) a = *(const bf16x4 *)(x + k0);
@@ -362,18 +363,24 @@ __global__ __launch_bounds__(256) void k_sel_infer(const float *feat, const floa
   __shared__ __align__(16) uint16_t bufA[64 * 64 * 4];    // x0, then x2
   __shared__ __align__(16) uint16_t bufB[32 * 32 * 32];   // x1, then x3
   __shared__ __align__(16) uint16_t x4[64];
+  __shared__ __align__(16) uint32_t sW[32 * 288 / 2];     // one conv layer's weights
   const size_t sample = blockIdx.x;
   const float *f = feat + sample * 16384;
   for (int i = threadIdx.x; i < 16384; i += 256) {
     const int c = i & 3;
     bufA[i] = f2bf((f[i] - norm[c]) / norm[4 + c]);
   }
+  stage_to_lds(sW, (const uint32_t *)(p16 + oW1), 32 * 36 / 2);
   __syncthreads();
-  conv_tile_layer<64, 4>(bufA, p16 + oW1, p + oB1, bufB);
+  conv_tile_layer<64, 4>(bufA, (const uint16_t *)sW, p + oB1, bufB);
   __syncthreads();
-  conv_tile_layer<32, 32>(bufB, p16 + oW2, p + oB2, bufA);
+  stage_to_lds(sW, (const uint32_t *)(p16 + oW2), 32 * 288 / 2);
   __syncthreads();
-  conv_tile_layer<16, 32>(bufA, p16 + oW3, p + oB3, bufB);
+  conv_tile_layer<32, 32>(bufB, (const uint16_t *)sW, p + oB2, bufA);
+  __syncthreads();
+  stage_to_lds(sW, (const uint32_t *)(p16 + oW3), 32 * 288 / 2);
+  __syncthreads();
+  conv_tile_layer<16, 32>(bufA, (const uint16_t *)sW, p + oB3, bufB);
   __syncthreads();
   fc_layer<2048, 64>(bufB, p16 + oW4, p + oB4, x4, nullptr);
   __syncthreads();

@@ -186,20 +186,30 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
                                                 const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
                                                 uint8_t *idx) {
   __shared__ uint8_t rk[256];
+  __shared__ uint8_t smap[256];
+  __shared__ uint8_t ssym[kChunk];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
   uint32_t b, p0, p1, bs, be;
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   const uint32_t lane = (uint32_t)lane_id();
-  const uint8_t *sq = seq + b * 256;
   const uint8_t *il = inlist + (size_t)c * 256;
-  for (uint32_t e = lane; e < 256; e += 64) rk[il[e]] = (uint8_t)e;
+  for (uint32_t e = lane; e < 256; e += 64) {
+    rk[il[e]] = (uint8_t)e;
+    smap[e] = seq[b * 256 + e];
+  }
+  // the chunk's bytes, staged up front (many loads in flight) so that the
+  // replay never waits on global memory
+  const uint32_t m = p1 - p0;
+  stage_to_lds(ssym, L + p0, m);
+  __syncthreads();
+  for (uint32_t i = lane; i < m; i += 64) ssym[i] = smap[ssym[i]];
   __syncthreads();
   uint32_t R0 = (uint32_t)rk[lane] | ((uint32_t)rk[lane + 64] << 16);
   uint32_t R1 = (uint32_t)rk[lane + 128] | ((uint32_t)rk[lane + 192] << 16);
   for (uint32_t base = p0; base < p1; base += 64) {
     const uint32_t p = base + lane;
-    const uint32_t vl = p < p1 ? sq[L[p]] : 0u;
+    const uint32_t vl = p < p1 ? (uint32_t)ssym[p - p0] : 0u;
     const uint32_t steps = min(64u, p1 - base);
     uint32_t mine = 0;
     for (uint32_t k = 0; k < steps; k++) {
