@@ -271,7 +271,7 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
         summ = cameras.summarize(results, events, src, pool, t0)
         st = srv.stats()
         srv.close()
-        ver = cameras.verify(results, src, pool, seqs, 24, sel, 0.9)
+        ver = cameras.verify(results, src, pool, seqs, 48, sel, 0.9)
         res["serving"] = {"cameras": 4, "rate_per_camera": 50.0, "seconds": args.serve_seconds, "frames": summ["frames"],
                           "throughput_mb_s": round(summ["throughput_mb_s"], 2),
                           "offered_mb_s": round(summ["offered_mb_s"], 2),
@@ -280,7 +280,8 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
                           "pool_peak_mb": round(st["pool_peak"] / 1e6, 1),
                           "overlap_frac": round(st["overlap_ms"] / max(st["busy_ms"], 1e-9), 3),
                           "mean_batch": round(st["batched_frames"] / max(st["batches"], 1), 2),
-                          "equal_alone": f"{ver['equal_alone']}/{ver['checked']}"}
+                          "equal_alone": f"{ver['equal_alone']}/{ver['checked']}",
+                          "selector_regret_checked": round(ver["regret"], 6)}
     return res
 
 

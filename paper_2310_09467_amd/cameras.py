@@ -30,7 +30,7 @@ from . import pcbz, synth
 SIZES = ((1020, 1020), (2040, 2040), (2040, 1020))
 PITCH, LEVEL = 15, 9
 _HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_SELECTOR = os.path.join(_HERE, "weights", "selector_lfm_beads.bin")
+DEFAULT_SELECTOR = os.path.join(_HERE, "weights", "selector_lfm.bin")
 
 
 def log(*a):

@@ -203,3 +203,37 @@ def test_fused_inference_matches_layer_path(env):
     _, loss = sel.gradients(f, torch.from_numpy(labels).cuda())
     ref, _ = OS.softmax_ce(logits, labels)
     assert abs(loss - ref) <= 2e-6 * abs(ref) + 1e-7, (loss, ref)
+
+
+def test_trained_selector_gain(env):
+    """The committed trained selector on the three 2040x2040 bead frames:
+    most bands skip the judgement, the size regret stays within 0.5 %, and
+    the output stays lossless."""
+    import json
+    import os
+
+    torch, pcbz, ctx = env
+    from paper_2310_09467_amd import cameras
+
+    path = cameras.DEFAULT_SELECTOR
+    tau = json.load(open(path.replace(".bin", "_report.json")))["picked"]["min_conf"]
+    sel = pcbz.Selector.load_file(ctx, path)
+    total_sel = total_exh = bands = judged = 0
+    try:
+        for peak in (20.0, 100.0, 1000.0):
+            f = synth.config2_frame(peak)
+            exh = ctx.compress(f, None, 15, 9, 0x7)
+            ctx.set_selector(sel, tau)
+            blob = ctx.compress(f, None, 15, 9, 0x7)
+            nb, nj = ctx.selector_stats()
+            ctx.set_selector(None)
+            bands += nb
+            judged += nj
+            total_sel += len(blob)
+            total_exh += len(exh)
+            np.testing.assert_array_equal(pcbz.as_uint16(ctx.decompress(blob)), f)
+    finally:
+        ctx.set_selector(None)
+    assert judged <= 0.1 * bands, (judged, bands)
+    assert total_sel <= 1.005 * total_exh, (total_sel, total_exh)
+    assert os.path.getsize(path) > 0
