@@ -3,9 +3,10 @@
 // All blocks of a batch are sorted together.  A rotation's rank is the
 // position in the final suffix order where its group (rotations sharing the
 // compared prefix) starts, so ranks of different blocks never collide.
-//   round 0: key = (block, first four bytes of the rotation, cyclic)
+//   round 0: key = (block, first b bytes of the rotation, cyclic), b = 7
+//            (6 above 256 blocks per call, 4 above 65536)
 //   round r: key = (rank[g], rank[start + (g - start + h) mod m]) for the
-//            rotations still in groups of two or more, h = 4 * 2^(r-1)
+//            rotations still in groups of two or more, h = b * 2^(r-1)
 // After each stable sort the group starts give new ranks; groups of one are
 // final, and a block is final once the compared prefix length reaches its
 // length m (equal rotations of a periodic block are then ordered by start
@@ -220,16 +221,22 @@ __device__ __forceinline__ uint32_t block_of(const uint32_t *blk_start, uint32_t
   return upper_index(blk_start, nb, g);
 }
 
+// key = (block, the first `nbytes` bytes of the rotation, cyclic), the block
+// in the bits above 8 * nbytes
 __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start, const uint32_t *d_nb,
-                           uint64_t *keys, uint32_t *vals, uint32_t *slot, uint32_t *d_u) {
+                           int nbytes, uint64_t *keys, uint32_t *vals, uint32_t *slot, uint32_t *d_u) {
   const uint32_t N = *d_N, nb = *d_nb;
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_u = N;
   for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
     const uint32_t k = block_of(blk_start, nb, g);
     const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
-    uint32_t v = 0;
-    for (uint32_t t = 0; t < 4; t++) v = (v << 8) | rle[s + (i + t) % m];
-    keys[g] = ((uint64_t)k << 32) | v;
+    uint64_t v = 0;
+    uint32_t j = i;
+    for (int t = 0; t < nbytes; t++) {
+      v = (v << 8) | rle[s + j];
+      j = j + 1 == m ? 0u : j + 1;
+    }
+    keys[g] = ((uint64_t)k << (8 * nbytes)) | v;
     vals[g] = g;
     slot[g] = g;
   }
@@ -358,12 +365,17 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   uint32_t *slot = w.slot, *slot2 = w.slot2;
   uint32_t *du[2] = {w.d_u, w.d_u + 1};
   const uint32_t g = grid_for(n_max);
-  PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, keys[0], vals[0], slot, du[0]);
-  int cur = radix_sort(keys, vals, du[0], n_max, 32 + bits_for(nb_max > 0 ? nb_max - 1 : 0), items, w.counts,
-                       w.d_count_n, w.scan_tmp, s);
+  // first prefix: 7 bytes under an 8-bit block id, or 6 bytes under a 16-bit
+  // one (noisy 16-bit data leaves most rotations tied after 4 bytes, far
+  // fewer after 7)
+  const int nbytes = nb_max <= 256 ? 7 : nb_max <= 65536 ? 6 : 4;
+  PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, nbytes, keys[0], vals[0], slot,
+              du[0]);
+  int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items,
+                       w.counts, w.d_count_n, w.scan_tmp, s);
   const int rbits = bits_for(n_max - 1);
   int u = 0;  // which count slot holds the current unresolved count
-  uint32_t compared = 4;
+  uint32_t compared = (uint32_t)nbytes;
   int rounds = 0;
   uint32_t n_cur = n_max;  // bound on the unresolved count (exact when read back)
   for (;;) {
