@@ -18,12 +18,17 @@ namespace pcbz {
 
 // ---------------------------------------------------------------- tracing
 bool g_trace_on = false;
+thread_local const char *g_trace_stage = nullptr;
 
 namespace {
 struct TraceRec {
   const char *name;
+  const char *stage;
   hipEvent_t a, b;
 };
+std::string trace_key(const char *stage, const char *name) {
+  return stage ? std::string(stage) + "|" + name : std::string(name);
+}
 struct Tracer {
   std::string filter;
   std::vector<TraceRec> open, done;
@@ -32,7 +37,7 @@ struct Tracer {
   std::vector<double> ms;
   std::vector<uint64_t> calls;
   std::vector<uint64_t> bytes;
-  size_t slot(const char *name) {
+  size_t slot(const std::string &name) {
     size_t i = 0;
     while (i < names.size() && names[i] != name) i++;
     if (i == names.size()) {
@@ -59,7 +64,7 @@ struct Tracer {
       float t = 0.f;
       (void)hipEventSynchronize(r.b);
       (void)hipEventElapsedTime(&t, r.a, r.b);
-      const size_t i = slot(r.name);
+      const size_t i = slot(trace_key(r.stage, r.name));
       ms[i] += t;
       calls[i]++;
       pool.push_back(r.a);
@@ -73,14 +78,14 @@ Tracer g_tracer;
 
 void trace_begin_impl(const char *name, hipStream_t s) {
   if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
-  TraceRec r{name, g_tracer.ev(), g_tracer.ev()};
+  TraceRec r{name, g_trace_stage, g_tracer.ev(), g_tracer.ev()};
   (void)hipEventRecord(r.a, s);
   g_tracer.open.push_back(r);
 }
 
 void trace_bytes_impl(const char *name, uint64_t bytes) {
   if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
-  g_tracer.bytes[g_tracer.slot(name)] += bytes;
+  g_tracer.bytes[g_tracer.slot(trace_key(g_trace_stage, name))] += bytes;
 }
 
 void trace_end_impl(const char *name, hipStream_t s) {
@@ -419,6 +424,7 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr));
   w.bw.d_u = w.ctr ? w.ctr + 10 : nullptr;        // [10], [11]
   w.bw.d_count_n = w.ctr ? w.ctr + 12 : nullptr;
+  w.bw.d_min_m = w.ctr ? w.ctr + 13 : nullptr;
   w.sa = A.get<uint32_t>(nr + 1);
   w.L = A.get<uint8_t>(nr + 16);
   w.codes = A.get<BlockCode>(S + 1);
@@ -606,8 +612,10 @@ int ensure_small(pcbz_ctx *ctx) {
 // Judge stages shared by pcbz_judge and the compress path.
 void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
   const uint8_t *forced = P.use_forced() ? w.forced : nullptr;
+  trace_stage("arrange");
   launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
                 0xFu, s);
+  trace_stage("judge");
   if (!P.tasks.empty()) {
     fill_u32(w.hist, 0, (size_t)P.tasks.size() * 65536, s);
     fill_u32((uint32_t *)w.score, 0, P.tasks.size() * 2, s);
@@ -630,6 +638,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   const uint32_t nbands = (uint32_t)P.bands.size();
   const uint32_t N = (uint32_t)P.ntot;
   const bool eager = tu.rounds == 0;
+  trace_stage("arrange");
   fill_u32(w.ctr, 0, 64, s);
   if (P.use_forced()) {
     launch_gather_forced(w.frames, (uint32_t)P.frames.size(), w.forced, s);
@@ -637,6 +646,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   }
   if (P.selector) {
     // learned selector: confident bands get their id here and skip the judge
+    trace_stage("select");
     launch_features(w.bands, nbands, w.feat, s);
     int st = selector_forward(ctx->sel, w.feat, nbands, w.logits, s);
     if (st) return fail(ctx, st, "selector forward failed");
@@ -645,7 +655,9 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   enqueue_judge(ctx, P, w, s);
   launch_choose2(w.bands, nbands, w.task_of, w.score, w.tasks, P.use_forced() ? w.forced : nullptr, w.choice, nullptr,
                  nullptr, s);
+  trace_stage("gather");
   launch_gather2(w.band_start, nbands, w.cb, w.choice, w.chosen, P.ntot, s);
+  trace_stage("rle1");
   // first run-length stage, block cuts, CRCs
   launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, s);
   launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
@@ -663,21 +675,26 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
     nrle = ctx->h_small[16];
   }
   // suffix sort of every block
+  trace_stage("bwt");
   const int rounds = run_bwt(w.rle, d_nrle, nrle, w.ctr + 1, nb, w.blk_rle_start, w.bw, w.sa, w.L, w.codes,
                              eager ? 40 : tu.rounds, tu.radix_items, eager ? ctx->h_small + 32 : nullptr, w.ctr + 9,
                              s);
   if (rounds_out) *rounds_out = rounds;
   // move-to-front, zero runs, tables, bit-packing
+  trace_stage("mtf");
   launch_mtf2(w.L, d_nrle, nrle, w.blk_rle_start, w.ctr + 1, nb, nrle / 4096 + nb + 1, w.mw, w.codes, w.sym, w.freq,
               w.ctr + 5, s);
   const uint32_t max_sym = nrle + nb;
+  trace_stage("tables");
   launch_huff2(w.sym, w.ctr + 1, nb, max_sym / kGroupSize + nb + 1, w.codes, w.freq, w.cost, w.tfreq, w.group_base,
                w.ctr + 6, w.sel, w.lens, w.code_words, s);
   const uint32_t max_words =
       (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)max_sym * 9 / 8 + (uint64_t)nb * 20600) / 4 + nb);
+  trace_stage("pack");
   launch_pack2(w.ctr + 1, nb, w.blocks, w.codes, w.mw.used, w.sel, w.lens, w.code_words, w.sym, w.ctr + 5, max_sym,
                w.prefix, w.sym_bits, w.sym_off, w.blk_sym_start, w.scan_tmp, w.frames, (uint32_t)P.frames.size(),
                w.bands, w.choice, w.band_len, w.frame_len, w.word_start, w.ctr + 7, max_words, s);
+  trace_stage(nullptr);
   return PCBZ_OK;
 }
 
@@ -1008,6 +1025,7 @@ int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, c
   enqueue_judge(ctx, P, w, s);
   launch_choose2(w.bands, (uint32_t)P.bands.size(), w.task_of, w.score, w.tasks, nullptr, d_choice, d_entropy,
                  d_score, s);
+  trace_stage(nullptr);
   HIPCHK(ctx, hipGetLastError());
   return PCBZ_OK;
 }

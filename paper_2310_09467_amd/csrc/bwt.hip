@@ -254,16 +254,20 @@ __global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const ui
 // group of one (or whose block is fully compared); flags the others.
 __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
                              const uint32_t *newrank, const uint32_t *d_u, const uint32_t *blk_start,
-                             const uint32_t *d_nb, uint32_t compared, uint32_t *rank, uint32_t *sa, uint32_t *unres) {
+                             const uint32_t *d_nb, const uint32_t *d_min_m, uint32_t compared, uint32_t *rank,
+                             uint32_t *sa, uint32_t *unres) {
   const uint32_t U = *d_u, nb = *d_nb;
+  const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     const uint32_t g = vals[k];
     rank[g] = newrank[k];
     const bool first = (k == 0) || keys[k] != keys[k - 1];
     const bool last = (k + 1 == U) || keys[k + 1] != keys[k];
-    const uint32_t b = block_of(blk_start, nb, g);
-    const uint32_t m = blk_start[b + 1] - blk_start[b];
-    const bool done = (first && last) || m <= compared;
+    bool done = first && last;
+    if (!done && any_short) {
+      const uint32_t b = block_of(blk_start, nb, g);
+      done = blk_start[b + 1] - blk_start[b] <= compared;
+    }
     if (done) sa[slot[k]] = g;  // final position; unresolved ones are written in a later round
     unres[k] = done ? 0u : 1u;
   }
@@ -290,6 +294,20 @@ __global__ void k_bwt_keys(const uint32_t *vals, const uint32_t *d_u, const uint
     const uint32_t g2 = s + (uint32_t)(((uint64_t)(g - s) + h) % m);
     keys[k] = ((uint64_t)rank[g] << bits) | rank[g2];
   }
+}
+
+__global__ void k_min_block(const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *d_min_m) {
+  __shared__ uint32_t red[256];
+  const uint32_t nb = *d_nb;
+  uint32_t mn = 0xFFFFFFFFu;
+  for (uint32_t b = threadIdx.x; b < nb; b += 256) mn = min(mn, blk_start[b + 1] - blk_start[b]);
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d_min_m = red[0];
 }
 
 __global__ void k_bwt_emit(const uint32_t *sa, const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start,
@@ -371,6 +389,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   const int nbytes = nb_max <= 256 ? 7 : nb_max <= 65536 ? 6 : 4;
   PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, nbytes, keys[0], vals[0], slot,
               du[0]);
+  PCBZ_LAUNCH(k_min_block, dim3(1), dim3(256), 0, s, blk_start, d_nb, w.d_min_m);
   int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items,
                        w.counts, w.d_count_n, w.scan_tmp, s);
   const int rbits = bits_for(n_max - 1);
@@ -384,7 +403,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag);
     scan_inclusive_max_u32(w.flag, w.flag, du[u], n_cur, w.scan_tmp, s);
     PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
-                compared, w.rank, sa, w.flag2);
+                w.d_min_m, compared, w.rank, sa, w.flag2);
     scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
     PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, du[u], vals[cur ^ 1],
                 slot2);

@@ -139,6 +139,9 @@ __device__ __forceinline__ void stage_to_lds(T *dst, const T *src, uint32_t n) {
 // Optional HIP-event timing of named kernel launches (see pcbz_trace_*).
 // When tracing is off these are a single branch.
 extern bool g_trace_on;
+// Stage label recorded with traced launches ("stage|kernel"); nullptr = none.
+extern thread_local const char *g_trace_stage;
+inline void trace_stage(const char *stage) { g_trace_stage = stage; }
 void trace_begin_impl(const char *name, hipStream_t s);
 void trace_end_impl(const char *name, hipStream_t s);
 inline void trace_begin(const char *name, hipStream_t s) {
@@ -227,6 +230,7 @@ struct BwtWork {
   uint32_t *counts;     // radix tile counts
   uint32_t *d_u;        // [2] unresolved counts (device)
   uint32_t *d_count_n;  // size of the current count table (device)
+  uint32_t *d_min_m;    // length of the shortest block (device)
   void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max);
