@@ -435,6 +435,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.mw.plist = A.get<uint8_t>((size_t)w.max_chunks * 256);
   w.mw.plen = A.get<uint32_t>(w.max_chunks);
   w.mw.inlist = A.get<uint8_t>((size_t)w.max_chunks * 256);
+  w.mw.seglist = A.get<uint8_t>((size_t)S * kMtfSegs * 256);
+  w.mw.seglen = A.get<uint32_t>((size_t)S * kMtfSegs);
   w.mw.idx = A.get<uint8_t>(nr + 16);
   // the MTF stage runs after the suffix sort: reuse the sort's key buffers
   w.mw.zs = w.bw.key[0] ? (uint32_t *)w.bw.key[0] : nullptr;

@@ -4,8 +4,8 @@
 // 4096 positions.  The list after a chunk depends on the list before it only
 // through a fixed rule: the chunk's distinct symbols in order of last
 // occurrence (most recent first) move to the front, the rest keep their
-// order.  So (1) every chunk computes that partial list, (2) one wavefront per
-// block chains the partial lists to get each chunk's incoming list, and
+// order.  So (1) every chunk computes that partial list, (2) the partial lists
+// are chained (in three shallow steps) into each chunk's incoming list, and
 // (3) every chunk replays move-to-front from its incoming list (ranks in
 // registers, see k_mtf_run).
 //
@@ -110,54 +110,109 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
   if (threadIdx.x == 0) plen[c] = cnt;
 }
 
-// Chains the partial lists of a block's chunks: the list entering chunk k+1
-// is chunk k's partial list followed by the entering list without those
-// symbols.  The block's partial lists are staged in LDS first; one thread
-// per list entry.
-constexpr uint32_t kMaxBlockChunks = (899981u + kChunk - 1) / kChunk + 1;
+// List chaining.  Folding a partial list P onto a list C gives P followed by
+// C without P's symbols (order kept); folding is associative, so a block's
+// chunks are chained in three shallow steps instead of one long one:
+//   1. each of kMtfSegs segments of the block folds its chunks' partial lists
+//      (from an empty list) into a segment partial list;
+//   2. one workgroup per block folds the segment lists from the initial list
+//      (ascending order), recording the list entering each segment;
+//   3. each segment folds its chunks again from its entering list, recording
+//      the list entering each chunk.
+// A fold step runs on one workgroup of 256 threads, one list entry each.
+struct FoldLds {
+  uint8_t cur[256], nxt[256], mem[256];
+  uint32_t len;
+  uint32_t wcnt[4];
+};
 
-__global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes,
-                                                   const uint8_t *plist, const uint32_t *plen, uint8_t *inlist) {
-  __shared__ uint4 pl4[kMaxBlockChunks * 16];
-  __shared__ uint32_t pn[kMaxBlockChunks];
-  __shared__ uint8_t cur[256], nxt[256], mem[256];
-  __shared__ uint32_t wcnt[4];
-  const uint32_t b = blockIdx.x;
-  if (b >= *d_nb) return;
-  const uint32_t nu = codes[b].n_in_use;
-  const uint32_t c0 = codes[b].chunk_start, nc = min(codes[b].n_chunks, kMaxBlockChunks);
+// cur/len := P ++ (cur - P) for units [0, n) of (lists, lens); before unit k
+// the current list is written to out_in + k * 256 when out_in is set.
+__device__ void fold_units(FoldLds &F, const uint8_t *lists, const uint32_t *lens, uint32_t n, uint8_t *out_in) {
   const uint32_t e = threadIdx.x;
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t lt = lanemask_lt();
-  const uint4 *src = (const uint4 *)(plist + (size_t)c0 * 256);
-  stage_to_lds(pl4, src, nc * 16);
-  stage_to_lds(pn, plen + c0, nc);
-  const uint8_t *pl = (const uint8_t *)pl4;
-  cur[e] = (uint8_t)e;
-  nxt[e] = (uint8_t)e;
-  __syncthreads();
-  for (uint32_t k = 0; k < nc; k++) {
-    inlist[(size_t)(c0 + k) * 256 + e] = cur[e];
-    mem[e] = 0;
+  for (uint32_t k = 0; k < n; k++) {
+    if (out_in) out_in[(size_t)k * 256 + e] = F.cur[e];
+    F.mem[e] = 0;
     __syncthreads();
-    const uint32_t pln = pn[k];
-    if (e < pln) {
-      const uint8_t v = pl[k * 256 + e];
-      mem[v] = 1;
-      nxt[e] = v;
+    const uint32_t pl = lens[k];
+    if (e < pl) {
+      const uint8_t v = lists[(size_t)k * 256 + e];
+      F.mem[v] = 1;
+      F.nxt[e] = v;
     }
     __syncthreads();
-    const bool keep = e < nu && !mem[cur[e]];
+    const bool keep = e < F.len && !F.mem[F.cur[e]];
     const uint64_t bal = ballot64(keep);
-    if (lane == 0) wcnt[w] = (uint32_t)__popcll(bal);
+    if (lane == 0) F.wcnt[w] = (uint32_t)__popcll(bal);
     __syncthreads();
-    uint32_t off = (uint32_t)__popcll(bal & lt);
-    for (int q = 0; q < w; q++) off += wcnt[q];
-    if (keep) nxt[pln + off] = cur[e];
+    uint32_t off = (uint32_t)__popcll(bal & lt), tot = 0;
+    for (int q = 0; q < 4; q++) {
+      if (q < w) off += F.wcnt[q];
+      tot += F.wcnt[q];
+    }
+    if (keep) F.nxt[pl + off] = F.cur[e];
     __syncthreads();
-    cur[e] = nxt[e];
+    F.cur[e] = F.nxt[e];
+    if (e == 0) F.len = pl + tot;
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ void seg_range(const BlockCode &C, uint32_t j, uint32_t &u0, uint32_t &u1) {
+  const uint32_t per = (C.n_chunks + kMtfSegs - 1) / kMtfSegs;
+  u0 = min(C.n_chunks, j * per);
+  u1 = min(C.n_chunks, u0 + per);
+}
+
+// step 1: grid (kMtfSegs, blocks)
+__global__ __launch_bounds__(256) void k_mtf_seg_fold(const uint32_t *d_nb, const BlockCode *codes,
+                                                      const uint8_t *plist, const uint32_t *plen, uint8_t *seglist,
+                                                      uint32_t *seglen) {
+  __shared__ FoldLds F;
+  const uint32_t b = blockIdx.y, j = blockIdx.x;
+  if (b >= *d_nb) return;
+  const BlockCode C = codes[b];
+  uint32_t u0, u1;
+  seg_range(C, j, u0, u1);
+  if (threadIdx.x == 0) F.len = 0;
+  __syncthreads();
+  fold_units(F, plist + (size_t)(C.chunk_start + u0) * 256, plen + C.chunk_start + u0, u1 - u0, nullptr);
+  seglist[((size_t)b * kMtfSegs + j) * 256 + threadIdx.x] = F.cur[threadIdx.x];
+  if (threadIdx.x == 0) seglen[(size_t)b * kMtfSegs + j] = F.len;
+}
+
+// step 2: one workgroup per block; the segment lists are replaced by the
+// lists entering the segments
+__global__ __launch_bounds__(256) void k_mtf_seg_chain(const uint32_t *d_nb, uint8_t *seglist, const uint32_t *seglen) {
+  __shared__ FoldLds F;
+  __shared__ uint8_t parts[kMtfSegs * 256];
+  const uint32_t b = blockIdx.x;
+  if (b >= *d_nb) return;
+  uint8_t *sl = seglist + (size_t)b * kMtfSegs * 256;
+  for (uint32_t i = threadIdx.x; i < kMtfSegs * 256; i += 256) parts[i] = sl[i];
+  F.cur[threadIdx.x] = (uint8_t)threadIdx.x;
+  if (threadIdx.x == 0) F.len = 256;
+  __syncthreads();
+  fold_units(F, parts, seglen + (size_t)b * kMtfSegs, kMtfSegs, sl);
+}
+
+// step 3: grid (kMtfSegs, blocks)
+__global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
+                                                   const uint32_t *plen, const uint8_t *seglist, uint8_t *inlist) {
+  __shared__ FoldLds F;
+  const uint32_t b = blockIdx.y, j = blockIdx.x;
+  if (b >= *d_nb) return;
+  const BlockCode C = codes[b];
+  uint32_t u0, u1;
+  seg_range(C, j, u0, u1);
+  if (u0 >= u1) return;
+  F.cur[threadIdx.x] = seglist[((size_t)b * kMtfSegs + j) * 256 + threadIdx.x];
+  if (threadIdx.x == 0) F.len = 256;
+  __syncthreads();
+  fold_units(F, plist + (size_t)(C.chunk_start + u0) * 256, plen + C.chunk_start + u0, u1 - u0,
+             inlist + (size_t)(C.chunk_start + u0) * 256);
 }
 
 // Replay of one chunk by one wavefront.  The list is held as ranks (the
@@ -314,7 +369,11 @@ void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32
   PCBZ_LAUNCH(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used, d_nb, w.seq, codes);
   PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.plist, w.plen);
-  PCBZ_LAUNCH(k_mtf_chain, dim3(max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.inlist);
+  PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
+              w.seglen);
+  PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(256), 0, s, d_nb, w.seglist, w.seglen);
+  PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
+              w.inlist);
   PCBZ_LAUNCH(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.inlist, w.idx);
   PCBZ_LAUNCH(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);

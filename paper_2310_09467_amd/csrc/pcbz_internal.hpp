@@ -241,6 +241,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
             int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
+constexpr uint32_t kMtfSegs = 16;  // segments per block in the move-to-front list chain
 struct MtfWork {
   uint8_t *seq;          // [max_blocks * 256] byte -> rank among used bytes
   uint32_t *used;        // [max_blocks * 8] used-byte bitmaps
@@ -248,6 +249,8 @@ struct MtfWork {
   uint8_t *plist;        // [max_chunks * 256] chunk partial lists
   uint32_t *plen;        // [max_chunks]
   uint8_t *inlist;       // [max_chunks * 256]
+  uint8_t *seglist;      // [max_blocks * kMtfSegs * 256] segment partial lists, then segment incoming lists
+  uint32_t *seglen;      // [max_blocks * kMtfSegs]
   uint8_t *idx;          // [N] MTF indices
   uint32_t *zs;          // [N]
   uint32_t *len;         // [N]

@@ -21,30 +21,35 @@ namespace pcbz {
 namespace {
 
 constexpr uint32_t kPoly = 0x04C11DB7u;
-constexpr int kCrcChunk = 256;
+constexpr int kCrcChunk = 64;  // bytes per thread: short table-lookup chains, many threads
 
 __device__ __forceinline__ uint32_t piece_len_out(uint32_t o) { return o < 3 ? 1u : (o == 3 ? 2u : 0u); }
 
+// Run-start markers, four bytes per thread: v[i] = i where a run of equal
+// bytes starts (a band start or a byte that differs from its predecessor),
+// else 0.  Loads are 4-byte words and stores 16-byte vectors, both
+// contiguous across the wavefront.
 __global__ void k_r1_starts(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N,
                             uint32_t *v) {
-  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (i0 >= N) return;
-  const uint32_t i1 = (uint32_t)min<uint64_t>(i0 + 16, N);
   uint32_t b = upper_index(band_start, n_bands, (uint32_t)i0);
-  uint32_t next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
+  const uint32_t wd = *(const uint32_t *)(x + i0);  // the buffer has 16 bytes of slack past N
   uint32_t prevc = i0 > 0 ? x[i0 - 1] : 0u;
-  const uint4 v16 = *(const uint4 *)(x + i0);  // the buffer has 16 bytes of slack past N
-  const uint32_t wd[4] = {v16.x, v16.y, v16.z, v16.w};
-  for (uint32_t i = (uint32_t)i0; i < i1; i++) {
-    if (i == next) {
-      b++;
-      next = b + 1 < n_bands ? band_start[b + 1] : 0xFFFFFFFFu;
-    }
-    const uint32_t k = i - (uint32_t)i0;
-    uint32_t c = (wd[k >> 2] >> (8 * (k & 3))) & 255u;
-    bool start = (i == band_start[b]) || c != prevc;
-    v[i] = start ? i : 0u;
+  uint32_t r[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint32_t i = (uint32_t)i0 + k;
+    while (b + 1 < n_bands && band_start[b + 1] <= i) b++;  // bands can be shorter than 4 bytes
+    const uint32_t c = (wd >> (8 * k)) & 255u;
+    const bool start = i == band_start[b] || c != prevc;
+    r[k] = start ? i : 0u;
     prevc = c;
+  }
+  if (i0 + 4 <= N) {
+    *(uint4 *)(v + i0) = make_uint4(r[0], r[1], r[2], r[3]);
+  } else {
+    for (uint32_t k = 0; k < 4 && i0 + k < N; k++) v[i0 + k] = r[k];
   }
 }
 
@@ -220,11 +225,12 @@ __global__ __launch_bounds__(256) void k_crc_chunks(const uint8_t *x, uint32_t N
       uint32_t r = 0;
       if (lo == c0 && hi == c0 + kCrcChunk) {
         const uint4 *p = (const uint4 *)(x + c0);
-        uint4 v[16];
+        constexpr int kVec = kCrcChunk / 16;
+        uint4 v[kVec];
 #pragma unroll
-        for (int i = 0; i < 16; i++) v[i] = p[i];
+        for (int i = 0; i < kVec; i++) v[i] = p[i];
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
+        for (int i = 0; i < kVec; i++) {
           const uint32_t wds[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
 #pragma unroll
           for (int q = 0; q < 4; q++) {
@@ -274,7 +280,7 @@ __global__ void k_crc_final(BlockDesc *blocks, const uint32_t *d_n_blocks, const
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
                    uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s) {
   if (!N) return;
-  uint32_t thr = (N + 15) / 16;
+  uint32_t thr = (N + 3) / 4;
   PCBZ_LAUNCH(k_r1_starts, dim3((thr + 255) / 256), dim3(256), 0, s, band_start, n_bands, x, N, runstart);
   scan_inclusive_max_u32(runstart, runstart, nullptr, N, scan_tmp, s);
   uint32_t grid = std::min<uint32_t>((N + 255) / 256, 8192);
