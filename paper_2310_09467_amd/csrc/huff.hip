@@ -22,39 +22,54 @@ namespace {
 constexpr int kLevels = kMaxCodeLen;
 constexpr int kMaxItems = 2 * kMaxAlpha + 4;
 
-__global__ void k_tab_init(const uint32_t *d_nb, BlockCode *codes, const uint32_t *freq, uint8_t *cost) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+// One workgroup per block: the frequencies are staged in LDS, one thread cuts
+// the alphabet into G contiguous ranges of about equal remaining frequency,
+// and the workgroup writes the 0/1 cost tables.
+__global__ __launch_bounds__(256) void k_tab_init(const uint32_t *d_nb, BlockCode *codes, const uint32_t *freq,
+                                                  uint8_t *cost) {
+  __shared__ uint32_t f[kMaxAlpha];
+  __shared__ uint32_t lo[kMaxGroups], hi[kMaxGroups];
+  const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
-  BlockCode C = codes[b];
+  const BlockCode C = codes[b];
   const uint32_t nmtf = C.n_mtf, alpha = C.alpha;
   uint32_t G = nmtf < 200 ? 2 : nmtf < 800 ? 3 : nmtf < 2400 ? 4 : nmtf < 6000 ? 5 : 6;
   if (G > alpha) G = alpha;
-  codes[b].n_groups = G;
-  codes[b].n_sel = (nmtf + kGroupSize - 1) / kGroupSize;
-  const uint32_t *f = freq + (size_t)b * kMaxAlpha;
-  uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
-  uint64_t remaining = nmtf;
-  uint32_t start = 0;
-  for (uint32_t g = 0; g < G; g++) {
-    const uint32_t left = G - g;
-    uint64_t acc = 0;
-    uint32_t end;
-    if (g == G - 1) {
-      end = alpha - 1;
-      for (uint32_t s = start; s <= end; s++) acc += f[s];
-    } else {
-      uint32_t s = start;
-      for (;;) {
-        acc += f[s];
-        if (acc * left >= remaining) break;
-        if (alpha - 1 - s == left - 1) break;
-        s++;
+  for (uint32_t s = threadIdx.x; s < alpha; s += blockDim.x) f[s] = freq[(size_t)b * kMaxAlpha + s];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    codes[b].n_groups = G;
+    codes[b].n_sel = (nmtf + kGroupSize - 1) / kGroupSize;
+    uint64_t remaining = nmtf;
+    uint32_t start = 0;
+    for (uint32_t g = 0; g < G; g++) {
+      const uint32_t left = G - g;
+      uint64_t acc = 0;
+      uint32_t end;
+      if (g == G - 1) {
+        end = alpha - 1;
+        for (uint32_t s = start; s <= end; s++) acc += f[s];
+      } else {
+        uint32_t s = start;
+        for (;;) {
+          acc += f[s];
+          if (acc * left >= remaining) break;
+          if (alpha - 1 - s == left - 1) break;
+          s++;
+        }
+        end = s;
       }
-      end = s;
+      lo[g] = start;
+      hi[g] = end;
+      remaining -= acc;
+      start = end + 1;
     }
-    for (uint32_t s = 0; s < alpha; s++) cst[g * kMaxAlpha + s] = (s >= start && s <= end) ? 0 : 1;
-    remaining -= acc;
-    start = end + 1;
+  }
+  __syncthreads();
+  uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
+  for (uint32_t i = threadIdx.x; i < G * alpha; i += blockDim.x) {
+    const uint32_t g = i / alpha, sy = i % alpha;
+    cst[g * kMaxAlpha + sy] = (sy >= lo[g] && sy <= hi[g]) ? 0 : 1;
   }
 }
 
@@ -277,7 +292,7 @@ void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks
                   BlockCode *codes, const uint32_t *freq, uint8_t *cost, uint32_t *tfreq, uint32_t *group_base,
                   uint32_t *d_n_groups, uint8_t *sel, uint8_t *lens, uint32_t *code_words, hipStream_t s) {
   fill_u32(tfreq, 0, (size_t)max_blocks * kMaxGroups * kMaxAlpha, s);
-  PCBZ_LAUNCH(k_tab_init, dim3((max_blocks + 63) / 64), dim3(64), 0, s, d_nb, codes, freq, cost);
+  PCBZ_LAUNCH(k_tab_init, dim3(max_blocks), dim3(256), 0, s, d_nb, codes, freq, cost);
   PCBZ_LAUNCH(k_sel_bases, dim3(1), dim3(64), 0, s, d_nb, codes, group_base, d_n_groups);
   for (int it = 0; it < 4; it++) {
     PCBZ_LAUNCH(k_tab_select, dim3((max_groups + 255) / 256), dim3(256), 0, s, sym, d_nb, codes, group_base,
