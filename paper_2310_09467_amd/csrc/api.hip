@@ -428,9 +428,10 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.sa = A.get<uint32_t>(nr + 1);
   w.L = A.get<uint8_t>(nr + 16);
   w.codes = A.get<BlockCode>(S + 1);
-  w.max_chunks = (uint32_t)(nr / 4096 + S + 2);
+  w.max_chunks = (uint32_t)(nr / kMtfChunk + S + 2);
   w.mw.seq = A.get<uint8_t>((size_t)S * 256);
   w.mw.used = A.get<uint32_t>((size_t)S * 8);
+  w.mw.used_chunk = A.get<uint32_t>((size_t)(nr / kMtfChunk + S + 2) * 8);
   w.mw.chunk_block = A.get<uint32_t>(w.max_chunks + 1);
   w.mw.plist = A.get<uint8_t>((size_t)w.max_chunks * 256);
   w.mw.plen = A.get<uint32_t>(w.max_chunks);
@@ -684,7 +685,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   if (rounds_out) *rounds_out = rounds;
   // move-to-front, zero runs, tables, bit-packing
   trace_stage("mtf");
-  launch_mtf2(w.L, d_nrle, nrle, w.blk_rle_start, w.ctr + 1, nb, nrle / 4096 + nb + 1, w.mw, w.codes, w.sym, w.freq,
+  launch_mtf2(w.L, d_nrle, nrle, w.blk_rle_start, w.ctr + 1, nb, nrle / kMtfChunk + nb + 1, w.mw, w.codes, w.sym, w.freq,
               w.ctr + 5, s);
   const uint32_t max_sym = nrle + nb;
   trace_stage("tables");

@@ -121,8 +121,9 @@ __global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const u
   stage_to_lds(ssym, sym + first_sym, end_sym - first_sym);
   __syncthreads();
   const uint32_t gi = g0 + threadIdx.x;
+  const uint32_t b0_end = group_base[b0 + 1];
   if (gi < ngroups) {
-    const uint32_t b = upper_index(group_base, nb, gi);
+    const uint32_t b = gi < b0_end ? b0 : upper_index(group_base, nb, gi);
     const BlockCode C = codes[b];
     const uint32_t j = gi - group_base[b];
     const uint32_t lo = C.sym_start + j * kGroupSize;

@@ -1,7 +1,7 @@
 // mtf.hip -- move-to-front and the zero-run stage of bzip2.
 //
 // Move-to-front is sequential per block, so each block is cut into chunks of
-// 4096 positions.  The list after a chunk depends on the list before it only
+// kMtfChunk positions.  The list after a chunk depends on the list before it only
 // through a fixed rule: the chunk's distinct symbols in order of last
 // occurrence (most recent first) move to the front, the rest keep their
 // order.  So (1) every chunk computes that partial list, (2) the partial lists
@@ -17,7 +17,7 @@
 namespace pcbz {
 namespace {
 
-constexpr uint32_t kChunk = 4096;
+constexpr uint32_t kChunk = kMtfChunk;
 
 __device__ __forceinline__ void chunk_range(uint32_t c, const uint32_t *chunk_base, const uint32_t *blk_start,
                                             uint32_t nb, uint32_t &b, uint32_t &p0, uint32_t &p1, uint32_t &bs,
@@ -47,8 +47,9 @@ __global__ void k_mtf_chunks(const uint32_t *blk_start, const uint32_t *d_nb, ui
   *d_n_chunks = acc;
 }
 
+// Used-byte bitmap of each chunk (8 words, plain stores; k_seq ORs a block's).
 __global__ __launch_bounds__(256) void k_used(const uint8_t *L, const uint32_t *chunk_base, const uint32_t *d_n_chunks,
-                                              const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *used) {
+                                              const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *used_chunk) {
   __shared__ uint32_t f[256];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
@@ -60,18 +61,30 @@ __global__ __launch_bounds__(256) void k_used(const uint8_t *L, const uint32_t *
   __syncthreads();
   const uint64_t bal = ballot64(f[threadIdx.x] != 0);
   if (lane_id() == 0) {
-    uint32_t wbase = threadIdx.x / 32;  // word index of this lane group
-    if ((uint32_t)bal) atomicOr(&used[b * 8 + wbase], (uint32_t)bal);
-    if ((uint32_t)(bal >> 32)) atomicOr(&used[b * 8 + wbase + 1], (uint32_t)(bal >> 32));
+    const uint32_t wbase = threadIdx.x / 32;  // word index of this lane group
+    used_chunk[(size_t)c * 8 + wbase] = (uint32_t)bal;
+    used_chunk[(size_t)c * 8 + wbase + 1] = (uint32_t)(bal >> 32);
   }
+  (void)b;
 }
 
-__global__ __launch_bounds__(256) void k_seq(const uint32_t *used, const uint32_t *d_nb, uint8_t *seq,
-                                             BlockCode *codes) {
+__global__ __launch_bounds__(256) void k_seq(const uint32_t *used_chunk, uint32_t *used, const uint32_t *d_nb,
+                                             uint8_t *seq, BlockCode *codes) {
+  __shared__ uint32_t u[8];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
   const uint32_t c = threadIdx.x;
-  const uint32_t *u = used + b * 8;
+  if (c < 8) u[c] = 0;
+  __syncthreads();
+  {
+    // OR of the block's chunk bitmaps: thread t ORs word t % 8 of chunks t / 8, t / 8 + 32, ...
+    const uint32_t k0 = codes[b].chunk_start, nc = codes[b].n_chunks, wd = c & 7u;
+    uint32_t acc = 0;
+    for (uint32_t k = c >> 3; k < nc; k += 32) acc |= used_chunk[(size_t)(k0 + k) * 8 + wd];
+    if (acc) atomicOr(&u[wd], acc);
+  }
+  __syncthreads();
+  if (c < 8) used[b * 8 + c] = u[c];
   uint32_t before = 0;
   for (uint32_t k = 0; k < c / 32; k++) before += __popc(u[k]);
   before += __popc(u[c / 32] & ((1u << (c % 32)) - 1u));
@@ -361,12 +374,11 @@ __global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const ui
 void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
                  uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
                  uint32_t *d_n_sym, hipStream_t s) {
-  fill_u32(w.used, 0, (size_t)max_blocks * 8, s);
   fill_u32(freq, 0, (size_t)max_blocks * kMaxAlpha, s);
   PCBZ_LAUNCH(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
   const uint32_t *cb = w.chunk_block;
-  PCBZ_LAUNCH(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used);
-  PCBZ_LAUNCH(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used, d_nb, w.seq, codes);
+  PCBZ_LAUNCH(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used_chunk);
+  PCBZ_LAUNCH(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used_chunk, w.used, d_nb, w.seq, codes);
   PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.plist, w.plen);
   PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,

@@ -241,10 +241,12 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
             int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
-constexpr uint32_t kMtfSegs = 16;  // segments per block in the move-to-front list chain
+constexpr uint32_t kMtfSegs = 16;    // segments per block in the move-to-front list chain
+constexpr uint32_t kMtfChunk = 2048;  // positions per move-to-front chunk (one wavefront replays one)
 struct MtfWork {
   uint8_t *seq;          // [max_blocks * 256] byte -> rank among used bytes
   uint32_t *used;        // [max_blocks * 8] used-byte bitmaps
+  uint32_t *used_chunk;  // [max_chunks * 8] used-byte bitmaps of the chunks
   uint32_t *chunk_block; // [max_chunks + 1] first chunk of each block
   uint8_t *plist;        // [max_chunks * 256] chunk partial lists
   uint32_t *plen;        // [max_chunks]
