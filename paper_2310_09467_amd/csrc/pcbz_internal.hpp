@@ -241,8 +241,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
             int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
-constexpr uint32_t kMtfSegs = 16;    // segments per block in the move-to-front list chain
-constexpr uint32_t kMtfChunk = 2048;  // positions per move-to-front chunk (one wavefront replays one)
+constexpr uint32_t kMtfSegs = 32;    // segments per block in the move-to-front list chain
+constexpr uint32_t kMtfChunk = 1024;  // positions per move-to-front chunk (one wavefront replays one)
 struct MtfWork {
   uint8_t *seq;          // [max_blocks * 256] byte -> rank among used bytes
   uint32_t *used;        // [max_blocks * 8] used-byte bitmaps
