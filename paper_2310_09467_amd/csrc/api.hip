@@ -109,6 +109,7 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   uint64_t gen = 0;
   int items = 16, rounds = 0;
+  uint64_t seg_mask = 0;
 };
 
 // Autotuner record: the schedule chosen for a batch shape.
@@ -116,6 +117,7 @@ struct TuneRec {
   std::string key;
   int items = 16;   // radix tile elements per thread
   int rounds = 0;   // doubling rounds enqueued in the graph
+  uint64_t seg_mask = 0;  // rounds sorted group by group in the graph
   double ms = 0.0;  // timed graph replay of the winner
 };
 int peek_container(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands,
@@ -139,6 +141,7 @@ struct pcbz_ctx {
   uint32_t *h_small = nullptr;  // pinned read-back area (4 KB)
   uint64_t last_raw = 0, last_rle = 0;
   uint32_t last_blocks = 0, last_rounds = 0, last_graph = 0;
+  uint64_t last_seg_mask = 0;  // rounds the last eager call sorted group by group
   // captured graphs and the autotuner's per-shape choices
   uint64_t gen = 1;  // bumped whenever a buffer a graph refers to is reallocated
   hipStream_t gstream = nullptr;
@@ -425,6 +428,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.bw.d_u = w.ctr ? w.ctr + 10 : nullptr;        // [10], [11]
   w.bw.d_count_n = w.ctr ? w.ctr + 12 : nullptr;
   w.bw.d_min_m = w.ctr ? w.ctr + 13 : nullptr;
+  w.bw.d_maxg = w.ctr ? w.ctr + 16 : nullptr;  // d_u + 6: read back with the counts
+  w.bw.d_fail = w.ctr ? w.ctr + 17 : nullptr;
   w.sa = A.get<uint32_t>(nr + 1);
   w.L = A.get<uint8_t>(nr + 16);
   w.codes = A.get<BlockCode>(S + 1);
@@ -532,14 +537,15 @@ int ensure_tables(pcbz_ctx *ctx, uint32_t band_n_max) {
   return PCBZ_OK;
 }
 
-// Autotuner cache: one JSON object per line, {"key": ..., "items": ..., "rounds": ..., "ms": ...}.
+// Autotuner cache: one JSON object per line,
+// {"key": ..., "items": ..., "rounds": ..., "seg": ..., "ms": ...}.
 void save_tuning(pcbz_ctx *ctx) {
   if (ctx->tune_path.empty()) return;
   FILE *f = fopen(ctx->tune_path.c_str(), "w");
   if (!f) return;
   for (const TuneRec &r : ctx->tune)
-    fprintf(f, "{\"key\": \"%s\", \"items\": %d, \"rounds\": %d, \"ms\": %.4f}\n", r.key.c_str(), r.items, r.rounds,
-            r.ms);
+    fprintf(f, "{\"key\": \"%s\", \"items\": %d, \"rounds\": %d, \"seg\": %llu, \"ms\": %.4f}\n", r.key.c_str(),
+            r.items, r.rounds, (unsigned long long)r.seg_mask, r.ms);
   fclose(f);
 }
 
@@ -551,10 +557,12 @@ void load_tuning(pcbz_ctx *ctx) {
   while (fgets(line, sizeof line, f)) {
     TuneRec r;
     double ms = 0.0;
-    if (sscanf(line, "{\"key\": \"%3071[^\"]\", \"items\": %d, \"rounds\": %d, \"ms\": %lf}", key, &r.items, &r.rounds,
-               &ms) == 4) {
+    unsigned long long seg = 0;
+    if (sscanf(line, "{\"key\": \"%3071[^\"]\", \"items\": %d, \"rounds\": %d, \"seg\": %llu, \"ms\": %lf}", key,
+               &r.items, &r.rounds, &seg, &ms) == 5) {
       r.key = key;
       r.ms = ms;
+      r.seg_mask = seg;
       if ((r.items == 8 || r.items == 16) && r.rounds > 0 && r.rounds < 64) ctx->tune.push_back(r);
     }
   }
@@ -631,6 +639,7 @@ void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
 struct Tuning {
   int radix_items = 16;  // elements per thread of a radix tile (8 or 16)
   int rounds = 0;        // doubling rounds to enqueue; 0 = read the count back and stop early
+  uint64_t seg_mask = 0;  // rounds sorted group by group (bit r - 1: the sort after round r)
 };
 
 // Enqueues the whole compression of a plan.  With tu.rounds == 0 the host
@@ -679,9 +688,11 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   }
   // suffix sort of every block
   trace_stage("bwt");
+  uint64_t seg_mask = eager ? 0ull : tu.seg_mask;
   const int rounds = run_bwt(w.rle, d_nrle, nrle, w.ctr + 1, nb, w.blk_rle_start, w.bw, w.sa, w.L, w.codes,
-                             eager ? 40 : tu.rounds, tu.radix_items, eager ? ctx->h_small + 32 : nullptr, w.ctr + 9,
-                             s);
+                             eager ? 40 : tu.rounds, tu.radix_items, eager ? ctx->h_small + 32 : nullptr, &seg_mask,
+                             w.ctr + 9, s);
+  if (eager) ctx->last_seg_mask = seg_mask;
   if (rounds_out) *rounds_out = rounds;
   // move-to-front, zero runs, tables, bit-packing
   trace_stage("mtf");
@@ -798,9 +809,19 @@ std::string shape_key(pcbz_ctx *ctx, const std::vector<FrameIn> &fin) {
   return k;
 }
 
+// Rounds a graph sorts group by group, from the last eager call: the rounds
+// it sorted that way, and every round after its last (normally empty).
+uint64_t seg_schedule(const pcbz_ctx *ctx) {
+  const uint32_t r = ctx->last_rounds;
+  const uint64_t later = r >= 1 && r <= 64 ? ~0ull << (r - 1) : (r == 0 ? ~0ull : 0ull);
+  return ctx->last_seg_mask | later;
+}
+
 GraphEntry *find_graph(pcbz_ctx *ctx, const std::string &key, const Tuning &tu) {
   for (GraphEntry &g : ctx->graphs)
-    if (g.key == key && g.items == tu.radix_items && g.rounds == tu.rounds && g.gen == ctx->gen) return &g;
+    if (g.key == key && g.items == tu.radix_items && g.rounds == tu.rounds && g.seg_mask == tu.seg_mask &&
+        g.gen == ctx->gen)
+      return &g;
   return nullptr;
 }
 
@@ -829,6 +850,7 @@ int capture(pcbz_ctx *ctx, const Plan &P, Work &w, const std::vector<UploadItem>
   g.key = key;
   g.items = tu.radix_items;
   g.rounds = tu.rounds;
+  g.seg_mask = tu.seg_mask;
   g.gen = ctx->gen;
   HIPCHK(ctx, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
   (void)hipGraphDestroy(graph);
@@ -871,6 +893,7 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
     TuneRec r;
     r.key = key;
     r.rounds = (int)ctx->last_rounds + 1;
+    r.seg_mask = seg_schedule(ctx);
     r.items = 16;
     r.ms = 0.0;
     Plan P;
@@ -883,6 +906,7 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
       Tuning tu;
       tu.radix_items = c;
       tu.rounds = r.rounds;
+      tu.seg_mask = r.seg_mask;
       if ((st = stage_plan(ctx, P, w, s, items))) return st;
       GraphEntry *g = nullptr;
       if ((st = capture(ctx, P, w, items, key, tu, &g))) return st;
@@ -910,6 +934,7 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
   Tuning tu;
   tu.radix_items = rec->items;
   tu.rounds = rec->rounds;
+  tu.seg_mask = rec->seg_mask;
   std::vector<UploadItem> items;
   if ((st = stage_plan(ctx, P, w, s, items))) return st;
   GraphEntry *g = find_graph(ctx, key, tu);
@@ -924,10 +949,12 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
   ctx->last_sel_bands = P.selector ? (uint32_t)P.bands.size() : 0;
   ctx->last_sel_fallback = P.selector ? ctr[14] : 0;
   if (ctr[9] != 0) {
-    // more rounds needed than the budget: redo eagerly and remember
+    // more rounds needed than the budget, or a group too large for the
+    // in-group sort: redo eagerly and remember
     st = run_compress(ctx, fin, s, lens, {});
     if (st) return st;
     rec->rounds = std::max(rec->rounds, (int)ctx->last_rounds + 1);
+    rec->seg_mask &= seg_schedule(ctx);
     save_tuning(ctx);
     return PCBZ_OK;
   }

@@ -12,12 +12,21 @@
 // length m (equal rotations of a periodic block are then ordered by start
 // index, which the stable sort preserved from the initial index order).
 //
-// Sorting is a least-significant-digit radix sort (8-bit digits) on 64-bit
-// keys with 32-bit values: per-tile digit counts, an exclusive scan of each
+// Round 0 and any round with a group larger than kSegMaxGroup use a
+// least-significant-digit radix sort (8-bit digits) on 64-bit keys with
+// 32-bit values: per-tile digit counts, an exclusive scan of each
 // digit's row of counts (one workgroup per digit, which also yields the
 // digit totals), then a stable scatter.  The scatter ranks
 // equal digits inside each wavefront with ballot matching, sorts the tile by
 // digit in LDS, and writes each digit's run with consecutive threads.
+//
+// The other rounds sort each group on its own (k_seg_sort): the unresolved
+// list is already ordered by group, so only the second rank has to be
+// ordered inside each group.  A workgroup owns the groups whose first element
+// lies in its tile of kSegTile positions, stages them (at most kSegCap
+// elements) in LDS, sorts every 64-element chunk in registers, and places
+// each element by counting, with a binary search per chunk its group spans,
+// the elements that precede it.
 //
 // Every count (elements, blocks, unresolved rotations) is read from device
 // memory and every kernel loops over its work with a capped grid, so the
@@ -244,20 +253,27 @@ __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32
 
 // Group-start markers (the slot of each group's first element), for a
 // max-scan that yields every element's new rank.
-__global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const uint32_t *d_u, uint32_t *mark) {
+__global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const uint32_t *d_u, uint32_t *mark,
+                            uint32_t *d_maxg) {
   const uint32_t U = *d_u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x)
     mark[k] = (k == 0 || keys[k] != keys[k - 1]) ? slot[k] : 0u;
 }
 
 // Writes ranks, and suffix-array entries of the elements that are now in a
-// group of one (or whose block is fully compared); flags the others.
-__global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
-                             const uint32_t *newrank, const uint32_t *d_u, const uint32_t *blk_start,
-                             const uint32_t *d_nb, const uint32_t *d_min_m, uint32_t compared, uint32_t *rank,
-                             uint32_t *sa, uint32_t *unres) {
+// group of one (or whose block is fully compared); flags the others.  Also
+// records the largest group that stays unresolved (its last element knows
+// the size: slots of a group are consecutive and its rank is the first slot).
+__global__ __launch_bounds__(256) void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
+                                                    const uint32_t *newrank, const uint32_t *d_u,
+                                                    const uint32_t *blk_start, const uint32_t *d_nb,
+                                                    const uint32_t *d_min_m, uint32_t compared, uint32_t *rank,
+                                                    uint32_t *sa, uint32_t *unres, uint32_t *d_maxg) {
+  __shared__ uint32_t red[256 / kWave];
   const uint32_t U = *d_u, nb = *d_nb;
   const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
+  uint32_t gmax = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     const uint32_t g = vals[k];
     rank[g] = newrank[k];
@@ -270,6 +286,15 @@ __global__ void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const u
     }
     if (done) sa[slot[k]] = g;  // final position; unresolved ones are written in a later round
     unres[k] = done ? 0u : 1u;
+    if (!done && last) gmax = max(gmax, slot[k] - newrank[k] + 1u);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, d));
+  if (lane_id() == 0) red[threadIdx.x / kWave] = gmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int i = 0; i < 256 / kWave; i++) m = max(m, red[i]);
+    if (m) atomicMax(d_maxg, m);
   }
 }
 
@@ -294,6 +319,174 @@ __global__ void k_bwt_keys(const uint32_t *vals, const uint32_t *d_u, const uint
     const uint32_t g2 = s + (uint32_t)(((uint64_t)(g - s) + h) % m);
     keys[k] = ((uint64_t)rank[g] << bits) | rank[g2];
   }
+}
+
+// ---------------------------------------------------------------- in-group sort
+constexpr int kSegThreads = 1024;
+constexpr uint32_t kSegCap = 8192;                     // elements staged per workgroup
+constexpr uint32_t kSegTile = 4096;                    // positions whose group starts a workgroup owns
+constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
+constexpr int kSegItems = (int)(kSegCap / kSegThreads);
+
+// A position starts a group when its slot is the group's rank (ranks are
+// first slots, and the slots of a group are consecutive).
+__device__ __forceinline__ bool seg_head(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank,
+                                         uint32_t k) {
+  return slot[k] == rank[vals[k]];
+}
+
+// First group start in [p, lim); lim if there is none.  Whole workgroup.
+__device__ uint32_t seg_first_head(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, uint32_t p,
+                                   uint32_t lim, uint32_t *red) {
+  const int w = threadIdx.x / kWave;
+  for (uint32_t base = p; base < lim; base += kSegThreads) {
+    const uint32_t k = base + threadIdx.x;
+    const uint64_t b = ballot64(k < lim && seg_head(vals, slot, rank, k));
+    if (lane_id() == 0) red[w] = b ? base + (uint32_t)w * kWave + (uint32_t)__builtin_ctzll(b) : 0xFFFFFFFFu;
+    __syncthreads();
+    uint32_t best = 0xFFFFFFFFu;
+    for (int i = 0; i < kSegThreads / kWave; i++) best = min(best, red[i]);
+    __syncthreads();
+    if (best != 0xFFFFFFFFu) return best;
+  }
+  return lim;
+}
+
+// Owner boundary at position t: the first group start at or after t (U if
+// none).  Both workgroups that share a boundary compute it the same way.
+// A group that covers more than kSegMaxGroup positions after t makes the
+// search give up: the boundary is then t itself and *ok is cleared.
+__device__ uint32_t seg_boundary(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, uint32_t t,
+                                 uint32_t U, uint32_t *red, bool *ok) {
+  if (t == 0 || t >= U) return t >= U ? U : 0u;
+  const uint64_t lim64 = (uint64_t)t + kSegMaxGroup + 1;
+  const uint32_t lim = lim64 < U ? (uint32_t)lim64 : U;
+  const uint32_t h = seg_first_head(vals, slot, rank, t, lim, red);
+  if (h == lim && lim < U) {
+    *ok = false;
+    return t;
+  }
+  return h;
+}
+
+// bitonic sort of one value per lane across the wavefront (ascending by lane)
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
+      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
+      const uint64_t o = ((uint64_t)hi << 32) | lo;
+      const bool keep_min = (((lane & k) == 0) == ((lane & j) == 0));
+      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  return v;
+}
+
+// number of entries of a sorted 64-entry run below v
+__device__ __forceinline__ uint32_t run_below(const uint64_t *a, uint64_t v) {
+  uint32_t p = a[31] < v ? 32u : 0u;
+  p += a[p + 15] < v ? 16u : 0u;
+  p += a[p + 7] < v ? 8u : 0u;
+  p += a[p + 3] < v ? 4u : 0u;
+  p += a[p + 1] < v ? 2u : 0u;
+  p += a[p] < v ? 1u : 0u;
+  if (p == 63) p += a[63] < v ? 1u : 0u;
+  return p;
+}
+
+// Sorts every unresolved group by the rank h positions further on, stably.
+// Input: the unresolved list (vals = rotation, slot = its position in the
+// suffix array), ordered by group; rank[] holds each rotation's group rank.
+// Output: vals_out in the new order and keys_out = (rank << rbits) | rank2,
+// the keys the radix path would have sorted.  A group above kSegMaxGroup
+// sets *d_fail and its workgroup copies its range unsorted (the result of
+// the call is then invalid, every index stays in range).
+__global__ __launch_bounds__(kSegThreads) void k_seg_sort(const uint32_t *vals, const uint32_t *slot,
+                                                         const uint32_t *rank, const uint32_t *d_u,
+                                                         const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h,
+                                                         int rbits, uint32_t *vals_out, uint64_t *keys_out,
+                                                         uint32_t *d_fail) {
+  __shared__ uint64_t scomp[kSegCap];  // sorted 64-element chunks of composite keys
+  __shared__ uint16_t sgs[kSegCap];    // group start of each element, then group end at each start
+  __shared__ uint32_t red[kSegThreads / kWave];
+  const uint32_t U = *d_u, nb = *d_nb;
+  const uint64_t t0 = (uint64_t)blockIdx.x * kSegTile;
+  if (t0 >= U) return;
+  const uint32_t t1 = (uint32_t)min<uint64_t>(U, t0 + kSegTile);
+  bool ok = true;
+  const uint32_t R0 = seg_boundary(vals, slot, rank, (uint32_t)t0, U, red, &ok);
+  const uint32_t R1 = seg_boundary(vals, slot, rank, t1, U, red, &ok);
+  if (R1 <= R0) return;  // a group from an earlier tile covers this one
+  const uint32_t len = R1 - R0;
+  if (!ok || len > kSegCap) {
+    if (threadIdx.x == 0) *d_fail = 1u;
+    for (uint32_t k = R0 + threadIdx.x; k < R1; k += kSegThreads) {
+      vals_out[k] = vals[k];
+      keys_out[k] = 0;
+    }
+    return;
+  }
+  uint32_t g[kSegItems], r[kSegItems], k2[kSegItems], gs[kSegItems];
+  uint64_t comp[kSegItems];
+#pragma unroll
+  for (int j = 0; j < kSegItems; j++) {
+    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
+    g[j] = r[j] = k2[j] = gs[j] = 0;
+    comp[j] = ~0ull;
+    if (x < len) {
+      const uint32_t k = R0 + x;
+      g[j] = vals[k];
+      r[j] = rank[g[j]];
+      const uint32_t off = slot[k] - r[j];
+      gs[j] = off <= x ? x - off : 0u;
+      const uint32_t b = block_of(blk_start, nb, g[j]);
+      const uint32_t s = blk_start[b], m = blk_start[b + 1] - s;
+      const uint32_t g2 = s + (uint32_t)(((uint64_t)(g[j] - s) + h) % m);
+      k2[j] = rank[g2];
+      comp[j] = ((uint64_t)gs[j] << 45) | ((uint64_t)k2[j] << 13) | x;
+    }
+    sgs[x] = (uint16_t)gs[j];
+  }
+  __syncthreads();
+  bool last[kSegItems];
+#pragma unroll
+  for (int j = 0; j < kSegItems; j++) {
+    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
+    last[j] = x < len && (x + 1 == len || sgs[x + 1] == x + 1);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSegItems; j++) {
+    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
+    if (last[j]) sgs[gs[j]] = (uint16_t)(x + 1);
+  }
+  // chunk j of this wavefront holds elements (wave + 16 j) * 64 + lane
+#pragma unroll
+  for (int j = 0; j < kSegItems; j++) {
+    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
+    scomp[x] = wave_sort64(comp[j]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSegItems; j++) {
+    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
+    if (x >= len) continue;
+    const uint32_t ge = sgs[gs[j]];
+    const uint32_t c0 = gs[j] >> 6, c1 = (ge - 1) >> 6;
+    uint32_t pos = c0 << 6;
+    for (uint32_t c = c0; c <= c1; c++) pos += run_below(scomp + (c << 6), comp[j]);
+    if (pos >= len) continue;  // only reachable with an inconsistent list
+    vals_out[R0 + pos] = g[j];
+    keys_out[R0 + pos] = ((uint64_t)r[j] << rbits) | k2[j];
+  }
+}
+
+__global__ void k_bwt_left(const uint32_t *d_u, const uint32_t *d_fail, uint32_t *d_left) {
+  *d_left = *d_u + *d_fail;
 }
 
 __global__ void k_min_block(const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *d_min_m) {
@@ -370,19 +563,26 @@ int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32
   return radix_sort_t<16>(keys, vals, d_n, n_max, bits, counts, d_count_n, scan_tmp, s);
 }
 
-// Prefix doubling over every block.  With `pinned_u` the unresolved count is
-// read back after each round and the loop stops when it reaches zero (at most
-// max_rounds); without it exactly max_rounds rounds are enqueued and the
-// final unresolved count is left in *d_left.  Returns the rounds enqueued.
+// Prefix doubling over every block.  With `pinned_u` the unresolved count and
+// the largest group are read back after each round (pinned_u[0..6] receive
+// d_u[0..6]), the loop stops when nothing is left (at most max_rounds), and a
+// round whose groups all fit kSegMaxGroup is sorted group by group; *seg_mask
+// receives the rounds sorted that way (bit r - 1 for the sort after round r).
+// Without it exactly max_rounds rounds are enqueued, the rounds in *seg_mask
+// are sorted group by group (a group that does not fit sets the fail word),
+// and the final unresolved count plus the fail word is left in *d_left.
+// Returns the rounds enqueued.
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
             const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
-            int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s) {
+            int items, uint32_t *pinned_u, uint64_t *seg_mask, uint32_t *d_left, hipStream_t s) {
   if (n_max == 0) return 0;
   uint64_t *keys[2] = {w.key[0], w.key[1]};
   uint32_t *vals[2] = {w.val[0], w.val[1]};
   uint32_t *slot = w.slot, *slot2 = w.slot2;
   uint32_t *du[2] = {w.d_u, w.d_u + 1};
   const uint32_t g = grid_for(n_max);
+  const uint64_t mask_in = seg_mask ? *seg_mask : 0ull;
+  uint64_t mask_out = 0;
   // first prefix: 7 bytes under an 8-bit block id, or 6 bytes under a 16-bit
   // one (noisy 16-bit data leaves most rotations tied after 4 bytes, far
   // fewer after 7)
@@ -393,28 +593,32 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items,
                        w.counts, w.d_count_n, w.scan_tmp, s);
   const int rbits = bits_for(n_max - 1);
+  const ptrdiff_t maxg_at = w.d_maxg - w.d_u;  // read back together with the counts
   int u = 0;  // which count slot holds the current unresolved count
   uint32_t compared = (uint32_t)nbytes;
   int rounds = 0;
   uint32_t n_cur = n_max;  // bound on the unresolved count (exact when read back)
+  uint32_t maxg = 0xFFFFFFFFu;
   for (;;) {
     const uint32_t gc = grid_for(n_cur);
     // new ranks: max-scan of group-start slots
-    PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag);
+    PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag, w.d_maxg);
     scan_inclusive_max_u32(w.flag, w.flag, du[u], n_cur, w.scan_tmp, s);
     PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
-                w.d_min_m, compared, w.rank, sa, w.flag2);
+                w.d_min_m, compared, w.rank, sa, w.flag2, w.d_maxg);
     scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
     PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, du[u], vals[cur ^ 1],
                 slot2);
     u ^= 1;
     rounds++;
     if (pinned_u) {
-      hipMemcpyAsync(pinned_u, du[u], sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+      hipMemcpyAsync(pinned_u, w.d_u, (size_t)(maxg_at + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
       hipStreamSynchronize(s);
+      n_cur = pinned_u[u];
+      maxg = pinned_u[maxg_at];
       if (getenv("PCBZ_DEBUG_BWT"))
-        fprintf(stderr, "pcbz bwt: round %d compared=%u unresolved=%u\n", rounds, compared, *pinned_u);
-      n_cur = *pinned_u;
+        fprintf(stderr, "pcbz bwt: round %d compared=%u unresolved=%u largest group=%u\n", rounds, compared, n_cur,
+                maxg);
       if (n_cur == 0) break;
     }
     if (rounds >= max_rounds || compared >= (1u << 30)) break;
@@ -423,14 +627,24 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     uint32_t *t = slot;
     slot = slot2;
     slot2 = t;
-    PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(n_cur)), dim3(256), 0, s, vals[cur], du[u], w.rank, blk_start, d_nb,
-                compared, rbits, keys[cur]);
-    uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
-    uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
-    if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, w.counts, w.d_count_n, w.scan_tmp, s) == 1) cur ^= 1;
+    const bool seg = pinned_u ? maxg <= kSegMaxGroup : rounds <= 64 && ((mask_in >> (rounds - 1)) & 1ull);
+    if (seg) {
+      if (rounds <= 64) mask_out |= 1ull << (rounds - 1);
+      const uint32_t gs = (uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile);
+      PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.rank, du[u], blk_start, d_nb,
+                  compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
+      cur ^= 1;
+    } else {
+      PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(n_cur)), dim3(256), 0, s, vals[cur], du[u], w.rank, blk_start, d_nb,
+                  compared, rbits, keys[cur]);
+      uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
+      uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
+      if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, w.counts, w.d_count_n, w.scan_tmp, s) == 1) cur ^= 1;
+    }
     compared *= 2;
   }
-  if (d_left) copy_u32(d_left, du[u], s);
+  if (d_left) PCBZ_LAUNCH(k_bwt_left, dim3(1), dim3(1), 0, s, du[u], w.d_fail, d_left);
+  if (seg_mask && pinned_u) *seg_mask = mask_out;
   PCBZ_LAUNCH(k_bwt_emit, dim3(g), dim3(256), 0, s, sa, rle, d_N, blk_start, d_nb, L, codes);
   return rounds;
 }

@@ -231,6 +231,8 @@ struct BwtWork {
   uint32_t *d_u;        // [2] unresolved counts (device)
   uint32_t *d_count_n;  // size of the current count table (device)
   uint32_t *d_min_m;    // length of the shortest block (device)
+  uint32_t *d_maxg;     // largest unresolved group of the last round (device, d_u + 6)
+  uint32_t *d_fail;     // set when a group did not fit the in-group sort (device)
   void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max);
@@ -238,7 +240,7 @@ int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32
                uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
             const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
-            int items, uint32_t *pinned_u, uint32_t *d_left, hipStream_t s);
+            int items, uint32_t *pinned_u, uint64_t *seg_mask, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
 constexpr uint32_t kMtfSegs = 32;    // segments per block in the move-to-front list chain

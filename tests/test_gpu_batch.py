@@ -80,3 +80,31 @@ def test_radix_tile_schedules_give_identical_bytes(orc):
         ctx.close()
     assert out[0] == out[1]
     assert out[0] == orc.compress(f, None, 15, 9, 7)[0]
+
+
+def test_graph_falls_back_when_a_group_is_too_large(orc, tmp_path):
+    """A graph learned on noisy frames sorts later rounds group by group; a
+    frame of the same shape with groups of 10350 rotations (a 20-byte period)
+    cannot be sorted that way and needs more rounds, so the replay flags
+    itself and the call is redone eagerly (still exact)."""
+    from paper_2310_09467_amd import pcbz, synth
+
+    os.environ["PCBZ_TUNE_CACHE"] = str(tmp_path / "tune.jsonl")
+    try:
+        ctx = pcbz.Context(0)
+    finally:
+        del os.environ["PCBZ_TUNE_CACHE"]
+    h, w = 300, 345
+    noisy, _ = synth.beads_frame(h, w, 40, 200.0, 11)
+    rng = np.random.default_rng(3)
+    pat = rng.integers(0, 256, 20, dtype=np.uint8)
+    periodic = np.resize(pat, 2 * h * w).view(np.uint16).reshape(h, w).copy()
+    nb = orc.plan(h, w, 15, 9)[1]
+    raster = [np.zeros(nb, np.uint8)]
+    want = {k: orc.compress(f, None, 15, 9, 0x7, forced_choice=raster[0])[0]
+            for k, f in (("noisy", noisy), ("periodic", periodic))}
+    for rep, name in enumerate(["noisy", "noisy", "periodic", "periodic", "noisy"]):
+        print("call", rep, name, flush=True)
+        f = noisy if name == "noisy" else periodic
+        assert ctx.compress_batch([f], None, [(15, 9, 0x7)], forced=raster) == [want[name]]
+    ctx.close()

@@ -189,3 +189,24 @@ def test_batch_equals_single_frames(ctx, orc):
     for f, (p, lv, m), blob in zip(frames, params, blobs):
         assert blob == ctx.compress(f, None, p, lv, m)
         assert blob == orc.compress(f, None, p, lv, m)[0]
+
+
+def _periodic(h, w, period=50, seed=3):
+    """Raster bytes repeating a random pattern: the band's single block keeps
+    groups of (length / period) rotations in every doubling round."""
+    rng = np.random.default_rng(seed)
+    pat = rng.integers(0, 256, period, dtype=np.uint8)
+    return np.resize(pat, 2 * h * w).view(np.uint16).reshape(h, w).copy()
+
+
+@pytest.mark.parametrize("w,largest", [(330, 3960), (345, 4140)])
+def test_group_sort_limit(ctx, orc, capfd, monkeypatch, w, largest):
+    """Groups of 3960 rotations are sorted group by group in LDS, groups of
+    4140 exceed the 4096 limit and take the radix sort; both are exact."""
+    monkeypatch.setenv("PCBZ_DEBUG_BWT", "1")
+    f = _periodic(300, w)
+    nb = orc.plan(300, w, 15, 9)[1]
+    _say("periodic 300 x", w)
+    check_compress(ctx, orc, f, level=9, mask=0x7, forced=np.zeros(nb, np.uint8))
+    err = capfd.readouterr().err
+    assert f"largest group={largest}" in err
