@@ -298,13 +298,31 @@ __global__ __launch_bounds__(256) void k_bwt_update(const uint64_t *keys, const 
   }
 }
 
-__global__ void k_bwt_compact(const uint32_t *vals, const uint32_t *slot, const uint32_t *unres,
-                              const uint32_t *pos, const uint32_t *d_u, uint32_t *vals2, uint32_t *slot2) {
+constexpr int kSegThreads = 1024;
+constexpr uint32_t kSegCap = 8192;                     // elements staged per workgroup
+constexpr uint32_t kSegTile = 4096;                    // positions whose group starts a workgroup owns
+constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
+
+// Moves the unresolved elements to the front (their order kept).  The last
+// element of each unresolved group also records the in-group sort's tile
+// boundaries: bound[t] = the first group start at or after t * kSegTile,
+// which for every t * kSegTile inside (group start, group end] is this
+// group's end.
+__global__ void k_bwt_compact(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
+                              const uint32_t *unres, const uint32_t *pos, const uint32_t *d_u,
+                              const uint32_t *rank, uint32_t *vals2, uint32_t *slot2, uint32_t *bound) {
   const uint32_t U = *d_u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) bound[0] = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     if (unres[k]) {
-      vals2[pos[k]] = vals[k];
-      slot2[pos[k]] = slot[k];
+      const uint32_t q = pos[k];
+      vals2[q] = vals[k];
+      slot2[q] = slot[k];
+      if (k + 1 == U || keys[k + 1] != keys[k]) {
+        const uint32_t size = slot[k] - rank[vals[k]] + 1u;  // ranks are first slots
+        const uint32_t head = q + 1u - size, end = q + 1u;
+        for (uint32_t t = head / kSegTile + 1; (uint64_t)t * kSegTile <= end; t++) bound[t] = end;
+      }
     }
   }
 }
@@ -322,80 +340,29 @@ __global__ void k_bwt_keys(const uint32_t *vals, const uint32_t *d_u, const uint
 }
 
 // ---------------------------------------------------------------- in-group sort
-constexpr int kSegThreads = 1024;
-constexpr uint32_t kSegCap = 8192;                     // elements staged per workgroup
-constexpr uint32_t kSegTile = 4096;                    // positions whose group starts a workgroup owns
-constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
-constexpr int kSegItems = (int)(kSegCap / kSegThreads);
 
-// A position starts a group when its slot is the group's rank (ranks are
-// first slots, and the slots of a group are consecutive).
-__device__ __forceinline__ bool seg_head(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank,
-                                         uint32_t k) {
-  return slot[k] == rank[vals[k]];
+// sorting network for 8 values in registers (19 compare-exchanges)
+__device__ __forceinline__ void cx(uint64_t &a, uint64_t &b) {
+  const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+__device__ __forceinline__ void sort8(uint64_t *v) {
+  cx(v[0], v[2]); cx(v[1], v[3]); cx(v[4], v[6]); cx(v[5], v[7]);
+  cx(v[0], v[4]); cx(v[1], v[5]); cx(v[2], v[6]); cx(v[3], v[7]);
+  cx(v[0], v[1]); cx(v[2], v[3]); cx(v[4], v[5]); cx(v[6], v[7]);
+  cx(v[2], v[4]); cx(v[3], v[5]);
+  cx(v[1], v[4]); cx(v[3], v[6]);
+  cx(v[1], v[2]); cx(v[3], v[4]); cx(v[5], v[6]);
 }
 
-// First group start in [p, lim); lim if there is none.  Whole workgroup.
-__device__ uint32_t seg_first_head(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, uint32_t p,
-                                   uint32_t lim, uint32_t *red) {
-  const int w = threadIdx.x / kWave;
-  for (uint32_t base = p; base < lim; base += kSegThreads) {
-    const uint32_t k = base + threadIdx.x;
-    const uint64_t b = ballot64(k < lim && seg_head(vals, slot, rank, k));
-    if (lane_id() == 0) red[w] = b ? base + (uint32_t)w * kWave + (uint32_t)__builtin_ctzll(b) : 0xFFFFFFFFu;
-    __syncthreads();
-    uint32_t best = 0xFFFFFFFFu;
-    for (int i = 0; i < kSegThreads / kWave; i++) best = min(best, red[i]);
-    __syncthreads();
-    if (best != 0xFFFFFFFFu) return best;
-  }
-  return lim;
-}
-
-// Owner boundary at position t: the first group start at or after t (U if
-// none).  Both workgroups that share a boundary compute it the same way.
-// A group that covers more than kSegMaxGroup positions after t makes the
-// search give up: the boundary is then t itself and *ok is cleared.
-__device__ uint32_t seg_boundary(const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, uint32_t t,
-                                 uint32_t U, uint32_t *red, bool *ok) {
-  if (t == 0 || t >= U) return t >= U ? U : 0u;
-  const uint64_t lim64 = (uint64_t)t + kSegMaxGroup + 1;
-  const uint32_t lim = lim64 < U ? (uint32_t)lim64 : U;
-  const uint32_t h = seg_first_head(vals, slot, rank, t, lim, red);
-  if (h == lim && lim < U) {
-    *ok = false;
-    return t;
-  }
-  return h;
-}
-
-// bitonic sort of one value per lane across the wavefront (ascending by lane)
-__device__ __forceinline__ uint64_t wave_sort64(uint64_t v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, j);
-      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), j);
-      const uint64_t o = ((uint64_t)hi << 32) | lo;
-      const bool keep_min = (((lane & k) == 0) == ((lane & j) == 0));
-      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
-    }
-  }
-  return v;
-}
-
-// number of entries of a sorted 64-entry run below v
-__device__ __forceinline__ uint32_t run_below(const uint64_t *a, uint64_t v) {
-  uint32_t p = a[31] < v ? 32u : 0u;
-  p += a[p + 15] < v ? 16u : 0u;
-  p += a[p + 7] < v ? 8u : 0u;
-  p += a[p + 3] < v ? 4u : 0u;
-  p += a[p + 1] < v ? 2u : 0u;
-  p += a[p] < v ? 1u : 0u;
-  if (p == 63) p += a[63] < v ? 1u : 0u;
-  return p;
+// The rotation h positions after g, inside g's block [s, s + m); h < m for
+// every rotation that is still unresolved (a block is final once h >= m).
+__device__ __forceinline__ uint32_t rot_ahead(uint32_t g, uint32_t s, uint32_t m, uint32_t h) {
+  uint32_t t = (g - s) + h;
+  if (t >= m) t -= m;
+  if (t >= m) t %= m;  // only for an invalid list
+  return s + t;
 }
 
 // Sorts every unresolved group by the rank h positions further on, stably.
@@ -405,24 +372,32 @@ __device__ __forceinline__ uint32_t run_below(const uint64_t *a, uint64_t v) {
 // the keys the radix path would have sorted.  A group above kSegMaxGroup
 // sets *d_fail and its workgroup copies its range unsorted (the result of
 // the call is then invalid, every index stays in range).
-__global__ __launch_bounds__(kSegThreads) void k_seg_sort(const uint32_t *vals, const uint32_t *slot,
-                                                         const uint32_t *rank, const uint32_t *d_u,
-                                                         const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h,
-                                                         int rbits, uint32_t *vals_out, uint64_t *keys_out,
-                                                         uint32_t *d_fail) {
-  __shared__ uint64_t scomp[kSegCap];  // sorted 64-element chunks of composite keys
-  __shared__ uint16_t sgs[kSegCap];    // group start of each element, then group end at each start
-  __shared__ uint32_t red[kSegThreads / kWave];
+//
+// In LDS each element is the composite (group start, rank2, position): the
+// range is already ordered by group start, so sorting the composites sorts
+// each group and keeps equal ranks in position order.  Each thread sorts 8
+// consecutive composites in registers, then sorted runs are merged pairwise
+// (8 -> 16 -> ... -> 8192) along merge paths: a thread finds where its 8
+// outputs start with one binary search on its diagonal and merges them
+// sequentially.  A level is skipped when no group crosses the middle of a
+// window of that level (its merge would move nothing).
+__global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_seg_sort(
+    const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, const uint32_t *d_u, const uint32_t *bound,
+    const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h, int rbits, uint32_t *vals_out, uint64_t *keys_out,
+    uint32_t *d_fail) {
+  constexpr int kPer = (int)(kSegCap / kSegThreads);  // 8 consecutive elements per thread
+  constexpr int kLevels = 10;                         // runs of 8 << i, i < 10
+  __shared__ uint64_t scomp[kSegCap];  // composites, in runs sorted so far
+  __shared__ uint16_t sgs[kSegCap];    // group starts, then group ends at each start
+  uint32_t *red = (uint32_t *)sgs;     // scratch words while sgs holds nothing else
   const uint32_t U = *d_u, nb = *d_nb;
   const uint64_t t0 = (uint64_t)blockIdx.x * kSegTile;
   if (t0 >= U) return;
-  const uint32_t t1 = (uint32_t)min<uint64_t>(U, t0 + kSegTile);
-  bool ok = true;
-  const uint32_t R0 = seg_boundary(vals, slot, rank, (uint32_t)t0, U, red, &ok);
-  const uint32_t R1 = seg_boundary(vals, slot, rank, t1, U, red, &ok);
+  const uint32_t R0 = min(bound[blockIdx.x], U);
+  const uint32_t R1 = t0 + kSegTile >= U ? U : min(bound[blockIdx.x + 1], U);
   if (R1 <= R0) return;  // a group from an earlier tile covers this one
   const uint32_t len = R1 - R0;
-  if (!ok || len > kSegCap) {
+  if (len > kSegCap) {
     if (threadIdx.x == 0) *d_fail = 1u;
     for (uint32_t k = R0 + threadIdx.x; k < R1; k += kSegThreads) {
       vals_out[k] = vals[k];
@@ -430,58 +405,119 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sort(const uint32_t *vals, 
     }
     return;
   }
-  uint32_t g[kSegItems], r[kSegItems], k2[kSegItems], gs[kSegItems];
-  uint64_t comp[kSegItems];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  // the block table in one register per lane when it fits a wavefront
+  const bool lane_tab = nb < (uint32_t)kWave;
+  const uint32_t bs = lane_tab && (uint32_t)lane <= nb ? blk_start[lane] : 0u;
+  // coalesced loads: element x = threadIdx.x + i * kSegThreads
 #pragma unroll
-  for (int j = 0; j < kSegItems; j++) {
-    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
-    g[j] = r[j] = k2[j] = gs[j] = 0;
-    comp[j] = ~0ull;
-    if (x < len) {
-      const uint32_t k = R0 + x;
-      g[j] = vals[k];
-      r[j] = rank[g[j]];
-      const uint32_t off = slot[k] - r[j];
-      gs[j] = off <= x ? x - off : 0u;
-      const uint32_t b = block_of(blk_start, nb, g[j]);
-      const uint32_t s = blk_start[b], m = blk_start[b + 1] - s;
-      const uint32_t g2 = s + (uint32_t)(((uint64_t)(g[j] - s) + h) % m);
-      k2[j] = rank[g2];
-      comp[j] = ((uint64_t)gs[j] << 45) | ((uint64_t)k2[j] << 13) | x;
+  for (int i = 0; i < kPer; i++) {
+    const uint32_t x = threadIdx.x + (uint32_t)i * kSegThreads;
+    const bool in = x < len;
+    const uint32_t k = R0 + (in ? x : 0u);
+    const uint32_t g = vals[k];
+    const uint32_t r = rank[g];
+    const uint32_t off = slot[k] - r;
+    const uint32_t gsx = off <= x ? x - off : 0u;
+    uint32_t s0, s1;
+    if (lane_tab) {
+      uint32_t b = 0;
+      for (uint32_t j = 1; j < nb; j++) b += g >= (uint32_t)__builtin_amdgcn_readlane((int)bs, (int)j) ? 1u : 0u;
+      s0 = (uint32_t)__shfl((int)bs, (int)b);
+      s1 = (uint32_t)__shfl((int)bs, (int)b + 1);
+    } else {
+      const uint32_t b = block_of(blk_start, nb, g);
+      s0 = blk_start[b];
+      s1 = blk_start[b + 1];
     }
-    sgs[x] = (uint16_t)gs[j];
+    const uint32_t k2 = rank[rot_ahead(g, s0, s1 - s0, h)];
+    scomp[x] = in ? ((uint64_t)gsx << 45) | ((uint64_t)k2 << 13) | x : ~0ull;  // padding sorts last
+    sgs[x] = (uint16_t)(in ? gsx : 0u);
   }
   __syncthreads();
-  bool last[kSegItems];
+  // from here on a thread owns the 8 consecutive elements x0 .. x0 + 7
+  const uint32_t x0 = threadIdx.x * kPer;
+  uint64_t v[kPer];
+  uint32_t gs[kPer];
 #pragma unroll
-  for (int j = 0; j < kSegItems; j++) {
-    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
-    last[j] = x < len && (x + 1 == len || sgs[x + 1] == x + 1);
+  for (int i = 0; i < kPer; i++) {
+    v[i] = scomp[x0 + i];
+    gs[i] = sgs[x0 + i];
+  }
+  // the last element of each group records the group's end at its start
+  bool last[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; i++) {
+    const uint32_t x = x0 + i;
+    last[i] = x < len && (x + 1 == len || sgs[x + 1] == x + 1);
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSegItems; j++) {
-    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
-    if (last[j]) sgs[gs[j]] = (uint16_t)(x + 1);
-  }
-  // chunk j of this wavefront holds elements (wave + 16 j) * 64 + lane
-#pragma unroll
-  for (int j = 0; j < kSegItems; j++) {
-    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
-    scomp[x] = wave_sort64(comp[j]);
-  }
+  for (int i = 0; i < kPer; i++)
+    if (last[i]) sgs[gs[i]] = (uint16_t)(x0 + i + 1);
   __syncthreads();
+  // level i (runs of 8 << i) is needed when some group holds an odd multiple
+  // of the run length strictly inside
+  uint32_t levels = 0;
 #pragma unroll
-  for (int j = 0; j < kSegItems; j++) {
-    const uint32_t x = threadIdx.x + (uint32_t)j * kSegThreads;
-    if (x >= len) continue;
-    const uint32_t ge = sgs[gs[j]];
-    const uint32_t c0 = gs[j] >> 6, c1 = (ge - 1) >> 6;
-    uint32_t pos = c0 << 6;
-    for (uint32_t c = c0; c <= c1; c++) pos += run_below(scomp + (c << 6), comp[j]);
-    if (pos >= len) continue;  // only reachable with an inconsistent list
-    vals_out[R0 + pos] = g[j];
-    keys_out[R0 + pos] = ((uint64_t)r[j] << rbits) | k2[j];
+  for (int i = 0; i < kPer; i++) {
+    const uint32_t x = x0 + i;
+    if (x < len && x == gs[i]) {
+      const uint32_t ge = sgs[x];
+      for (int l = 0; l < kLevels; l++) {
+        const uint32_t L = 8u << l;
+        const uint32_t m0 = (x >> (3 + l)) + 1;  // first multiple of L above the start
+        if (m0 * L < ge && ((m0 & 1u) || (m0 + 1) * L < ge)) levels |= 1u << l;
+      }
+    }
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) levels |= (uint32_t)__shfl_xor((int)levels, d);
+  __syncthreads();  // every group end has been read
+  if (lane == 0) red[w] = levels;
+  __syncthreads();
+  levels = 0;
+  for (int i = 0; i < kSegThreads / kWave; i++) levels |= red[i];
+  sort8(v);
+#pragma unroll
+  for (int i = 0; i < kPer; i++) scomp[x0 + i] = v[i];
+  __syncthreads();
+  for (int l = 0; l < kLevels; l++) {
+    if (!((levels >> l) & 1u)) continue;
+    const uint32_t L = 8u << l;
+    const uint32_t d = x0 & (2 * L - 1);  // diagonal of this thread inside its window
+    const uint32_t W = x0 - d;
+    const uint64_t *A = scomp + W, *B = scomp + W + L;
+    uint32_t lo = d > L ? d - L : 0u, hi = d < L ? d : L;
+    while (lo < hi) {  // A elements among the window's first d outputs (A first on ties)
+      const uint32_t mid = (lo + hi) >> 1;
+      if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    uint32_t ia = lo, ib = d - lo;
+    uint64_t a = A[min(ia, L - 1)], b = B[min(ib, L - 1)];
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+      const bool take_a = ia < L && (ib >= L || a <= b);
+      v[i] = take_a ? a : b;
+      ia += take_a ? 1u : 0u;
+      ib += take_a ? 0u : 1u;
+      const uint64_t nx = take_a ? A[min(ia, L - 1)] : B[min(ib, L - 1)];
+      if (take_a) a = nx;
+      else b = nx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; i++) scomp[x0 + i] = v[i];
+    __syncthreads();
+  }
+  // sorted position p holds the composite of the element that goes there
+  for (uint32_t p = threadIdx.x; p < len; p += kSegThreads) {
+    const uint64_t c = scomp[p];
+    const uint32_t x = (uint32_t)c & (kSegCap - 1);
+    const uint32_t gsp = (uint32_t)(c >> 45);
+    const uint32_t k2 = (uint32_t)(c >> 13);
+    vals_out[R0 + p] = vals[R0 + x];
+    keys_out[R0 + p] = ((uint64_t)slot[R0 + gsp] << rbits) | k2;
   }
 }
 
@@ -553,6 +589,8 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
 
 }  // namespace
 
+size_t seg_bound_words(uint32_t n_max) { return (size_t)n_max / kSegTile + 2; }
+
 size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + 2047) / 2048 + 1); }
 
 // Sorts (keys[0], vals[0]) by the low `bits` bits of the key (n read from
@@ -607,8 +645,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
                 w.d_min_m, compared, w.rank, sa, w.flag2, w.d_maxg);
     scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
-    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, vals[cur], slot, w.flag2, w.flag, du[u], vals[cur ^ 1],
-                slot2);
+    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag2, w.flag, du[u], w.rank,
+                vals[cur ^ 1], slot2, w.seg_bound);
     u ^= 1;
     rounds++;
     if (pinned_u) {
@@ -631,8 +669,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     if (seg) {
       if (rounds <= 64) mask_out |= 1ull << (rounds - 1);
       const uint32_t gs = (uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile);
-      PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.rank, du[u], blk_start, d_nb,
-                  compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
+      PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.rank, du[u], w.seg_bound,
+                  blk_start, d_nb, compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
       cur ^= 1;
     } else {
       PCBZ_LAUNCH(k_bwt_keys, dim3(grid_for(n_cur)), dim3(256), 0, s, vals[cur], du[u], w.rank, blk_start, d_nb,

@@ -233,9 +233,11 @@ struct BwtWork {
   uint32_t *d_min_m;    // length of the shortest block (device)
   uint32_t *d_maxg;     // largest unresolved group of the last round (device, d_u + 6)
   uint32_t *d_fail;     // set when a group did not fit the in-group sort (device)
+  uint32_t *seg_bound;  // [seg_bound_words] tile boundaries of the in-group sort
   void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max);
+size_t seg_bound_words(uint32_t n_max);
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
                uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
