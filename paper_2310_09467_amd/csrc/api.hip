@@ -426,6 +426,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.bw.flag2 = A.get<uint32_t>(nr + 1);
   w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr));
   w.bw.seg_bound = A.get<uint32_t>(seg_bound_words((uint32_t)nr));
+  w.bw.goff = A.get<uint32_t>(nr + 1);
+  w.bw.gstart = A.get<uint32_t>(nr + 1);
   w.bw.d_u = w.ctr ? w.ctr + 10 : nullptr;        // [10], [11]
   w.bw.d_count_n = w.ctr ? w.ctr + 12 : nullptr;
   w.bw.d_min_m = w.ctr ? w.ctr + 13 : nullptr;

@@ -262,14 +262,15 @@ __global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const ui
 }
 
 // Writes ranks, and suffix-array entries of the elements that are now in a
-// group of one (or whose block is fully compared); flags the others.  Also
-// records the largest group that stays unresolved (its last element knows
-// the size: slots of a group are consecutive and its rank is the first slot).
+// group of one (or whose block is fully compared); flags the others and
+// records each element's position inside its group.  Also records the
+// largest group that stays unresolved (its last element knows the size:
+// slots of a group are consecutive and its rank is the first slot).
 __global__ __launch_bounds__(256) void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
                                                     const uint32_t *newrank, const uint32_t *d_u,
                                                     const uint32_t *blk_start, const uint32_t *d_nb,
                                                     const uint32_t *d_min_m, uint32_t compared, uint32_t *rank,
-                                                    uint32_t *sa, uint32_t *unres, uint32_t *d_maxg) {
+                                                    uint32_t *sa, uint32_t *unres, uint32_t *goff, uint32_t *d_maxg) {
   __shared__ uint32_t red[256 / kWave];
   const uint32_t U = *d_u, nb = *d_nb;
   const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
@@ -286,7 +287,11 @@ __global__ __launch_bounds__(256) void k_bwt_update(const uint64_t *keys, const 
     }
     if (done) sa[slot[k]] = g;  // final position; unresolved ones are written in a later round
     unres[k] = done ? 0u : 1u;
-    if (!done && last) gmax = max(gmax, slot[k] - newrank[k] + 1u);
+    if (!done) {
+      const uint32_t off = slot[k] - newrank[k];  // position inside the group
+      goff[k] = off;
+      if (last) gmax = max(gmax, off + 1u);
+    }
   }
   for (int d = kWave / 2; d > 0; d >>= 1) gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, d));
   if (lane_id() == 0) red[threadIdx.x / kWave] = gmax;
@@ -303,24 +308,25 @@ constexpr uint32_t kSegCap = 8192;                     // elements staged per wo
 constexpr uint32_t kSegTile = 4096;                    // positions whose group starts a workgroup owns
 constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
 
-// Moves the unresolved elements to the front (their order kept).  The last
-// element of each unresolved group also records the in-group sort's tile
-// boundaries: bound[t] = the first group start at or after t * kSegTile,
-// which for every t * kSegTile inside (group start, group end] is this
-// group's end.
+// Moves the unresolved elements to the front (their order kept), with the
+// compact position of each one's group start.  The last element of each
+// unresolved group also records the in-group sort's tile boundaries:
+// bound[t] = the first group start at or after t * kSegTile, which for every
+// t * kSegTile inside (group start, group end] is this group's end.
 __global__ void k_bwt_compact(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
                               const uint32_t *unres, const uint32_t *pos, const uint32_t *d_u,
-                              const uint32_t *rank, uint32_t *vals2, uint32_t *slot2, uint32_t *bound) {
+                              const uint32_t *goff, uint32_t *vals2, uint32_t *slot2, uint32_t *gstart2,
+                              uint32_t *bound) {
   const uint32_t U = *d_u;
   if (blockIdx.x == 0 && threadIdx.x == 0) bound[0] = 0;
   for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
     if (unres[k]) {
-      const uint32_t q = pos[k];
+      const uint32_t q = pos[k], off = goff[k];
       vals2[q] = vals[k];
       slot2[q] = slot[k];
+      gstart2[q] = q - off;
       if (k + 1 == U || keys[k + 1] != keys[k]) {
-        const uint32_t size = slot[k] - rank[vals[k]] + 1u;  // ranks are first slots
-        const uint32_t head = q + 1u - size, end = q + 1u;
+        const uint32_t head = q - off, end = q + 1u;
         for (uint32_t t = head / kSegTile + 1; (uint64_t)t * kSegTile <= end; t++) bound[t] = end;
       }
     }
@@ -367,7 +373,8 @@ __device__ __forceinline__ uint32_t rot_ahead(uint32_t g, uint32_t s, uint32_t m
 
 // Sorts every unresolved group by the rank h positions further on, stably.
 // Input: the unresolved list (vals = rotation, slot = its position in the
-// suffix array), ordered by group; rank[] holds each rotation's group rank.
+// suffix array, gstart = position of its group's first element), ordered by
+// group; rank[] holds each rotation's group rank.
 // Output: vals_out in the new order and keys_out = (rank << rbits) | rank2,
 // the keys the radix path would have sorted.  A group above kSegMaxGroup
 // sets *d_fail and its workgroup copies its range unsorted (the result of
@@ -382,14 +389,14 @@ __device__ __forceinline__ uint32_t rot_ahead(uint32_t g, uint32_t s, uint32_t m
 // sequentially.  A level is skipped when no group crosses the middle of a
 // window of that level (its merge would move nothing).
 __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_seg_sort(
-    const uint32_t *vals, const uint32_t *slot, const uint32_t *rank, const uint32_t *d_u, const uint32_t *bound,
+    const uint32_t *vals, const uint32_t *slot, const uint32_t *gstart, const uint32_t *rank, const uint32_t *d_u,
+    const uint32_t *bound,
     const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h, int rbits, uint32_t *vals_out, uint64_t *keys_out,
     uint32_t *d_fail) {
   constexpr int kPer = (int)(kSegCap / kSegThreads);  // 8 consecutive elements per thread
   constexpr int kLevels = 10;                         // runs of 8 << i, i < 10
   __shared__ uint64_t scomp[kSegCap];  // composites, in runs sorted so far
   __shared__ uint16_t sgs[kSegCap];    // group starts, then group ends at each start
-  uint32_t *red = (uint32_t *)sgs;     // scratch words while sgs holds nothing else
   const uint32_t U = *d_u, nb = *d_nb;
   const uint64_t t0 = (uint64_t)blockIdx.x * kSegTile;
   if (t0 >= U) return;
@@ -416,9 +423,8 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))
     const bool in = x < len;
     const uint32_t k = R0 + (in ? x : 0u);
     const uint32_t g = vals[k];
-    const uint32_t r = rank[g];
-    const uint32_t off = slot[k] - r;
-    const uint32_t gsx = off <= x ? x - off : 0u;
+    const uint32_t gh = gstart[k];
+    const uint32_t gsx = gh >= R0 && gh - R0 <= x ? gh - R0 : 0u;
     uint32_t s0, s1;
     if (lane_tab) {
       uint32_t b = 0;
@@ -456,58 +462,78 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))
   for (int i = 0; i < kPer; i++)
     if (last[i]) sgs[gs[i]] = (uint16_t)(x0 + i + 1);
   __syncthreads();
-  // level i (runs of 8 << i) is needed when some group holds an odd multiple
-  // of the run length strictly inside
+  // Level l (runs of L = 8 << l) can move something only if a group holds a
+  // multiple of L strictly inside, which needs L <= the highest bit where
+  // its first and last positions differ.
   uint32_t levels = 0;
 #pragma unroll
   for (int i = 0; i < kPer; i++) {
     const uint32_t x = x0 + i;
     if (x < len && x == gs[i]) {
-      const uint32_t ge = sgs[x];
-      for (int l = 0; l < kLevels; l++) {
-        const uint32_t L = 8u << l;
-        const uint32_t m0 = (x >> (3 + l)) + 1;  // first multiple of L above the start
-        if (m0 * L < ge && ((m0 & 1u) || (m0 + 1) * L < ge)) levels |= 1u << l;
-      }
+      const uint32_t diff = x ^ (sgs[x] - 1u);
+      const int hb = diff ? 31 - __builtin_clz(diff) : -1;
+      if (hb >= 3) levels |= (2u << min(hb - 3, kLevels - 1)) - 1u;
     }
   }
   for (int d = kWave / 2; d > 0; d >>= 1) levels |= (uint32_t)__shfl_xor((int)levels, d);
-  __syncthreads();  // every group end has been read
+  // scratch words in scomp: this thread's composites are in registers
+  uint32_t *red = (uint32_t *)scomp;
+  __syncthreads();
   if (lane == 0) red[w] = levels;
   __syncthreads();
   levels = 0;
   for (int i = 0; i < kSegThreads / kWave; i++) levels |= red[i];
+  __syncthreads();
   sort8(v);
 #pragma unroll
   for (int i = 0; i < kPer; i++) scomp[x0 + i] = v[i];
   __syncthreads();
+  // sgs now maps positions to groups: sgs[p] is p's group start, except at a
+  // group start, where it holds the group end (> p)
   for (int l = 0; l < kLevels; l++) {
     if (!((levels >> l) & 1u)) continue;
     const uint32_t L = 8u << l;
     const uint32_t d = x0 & (2 * L - 1);  // diagonal of this thread inside its window
     const uint32_t W = x0 - d;
-    const uint64_t *A = scomp + W, *B = scomp + W + L;
-    uint32_t lo = d > L ? d - L : 0u, hi = d < L ? d : L;
-    while (lo < hi) {  // A elements among the window's first d outputs (A first on ties)
-      const uint32_t mid = (lo + hi) >> 1;
-      if (A[mid] <= B[d - 1 - mid]) lo = mid + 1;
-      else hi = mid;
+    // only the group holding the window's middle can cross it; threads whose
+    // outputs miss that group keep their elements
+    const uint32_t mid = W + L;
+    bool work = false;
+    if (mid < len) {
+      const uint32_t sm = sgs[mid];
+      if (sm < mid) work = x0 < sgs[sm] && x0 + kPer > sm;
     }
-    uint32_t ia = lo, ib = d - lo;
-    uint64_t a = A[min(ia, L - 1)], b = B[min(ib, L - 1)];
+    uint64_t o[kPer];
+    if (work) {
+      const uint64_t *A = scomp + W, *B = scomp + W + L;
+      uint32_t lo = d > L ? d - L : 0u, hi = d < L ? d : L;
+      while (lo < hi) {  // A elements among the window's first d outputs (A first on ties)
+        const uint32_t m = (lo + hi) >> 1;
+        if (A[m] <= B[d - 1 - m]) lo = m + 1;
+        else hi = m;
+      }
+      uint32_t ia = lo, ib = d - lo;
+      uint64_t a = ia < L ? A[ia] : ~0ull, b = ib < L ? B[ib] : ~0ull;
 #pragma unroll
-    for (int i = 0; i < kPer; i++) {
-      const bool take_a = ia < L && (ib >= L || a <= b);
-      v[i] = take_a ? a : b;
-      ia += take_a ? 1u : 0u;
-      ib += take_a ? 0u : 1u;
-      const uint64_t nx = take_a ? A[min(ia, L - 1)] : B[min(ib, L - 1)];
-      if (take_a) a = nx;
-      else b = nx;
+      for (int i = 0; i < kPer; i++) {
+        // an exhausted run reads as all ones; ties with padding give the same value
+        const bool take_a = a <= b;
+        o[i] = take_a ? a : b;
+        const uint32_t na = ia + (take_a ? 1u : 0u), nb = ib + (take_a ? 0u : 1u);
+        const uint32_t at = take_a ? na : L + nb;
+        const bool in = take_a ? na < L : nb < L;
+        const uint64_t nx = scomp[W + (in ? at : 0u)];
+        ia = na;
+        ib = nb;
+        if (take_a) a = in ? nx : ~0ull;
+        else b = in ? nx : ~0ull;
+      }
     }
     __syncthreads();
+    if (work) {
 #pragma unroll
-    for (int i = 0; i < kPer; i++) scomp[x0 + i] = v[i];
+      for (int i = 0; i < kPer; i++) scomp[x0 + i] = o[i];
+    }
     __syncthreads();
   }
   // sorted position p holds the composite of the element that goes there
@@ -643,10 +669,10 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag, w.d_maxg);
     scan_inclusive_max_u32(w.flag, w.flag, du[u], n_cur, w.scan_tmp, s);
     PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
-                w.d_min_m, compared, w.rank, sa, w.flag2, w.d_maxg);
+                w.d_min_m, compared, w.rank, sa, w.flag2, w.goff, w.d_maxg);
     scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
-    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag2, w.flag, du[u], w.rank,
-                vals[cur ^ 1], slot2, w.seg_bound);
+    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag2, w.flag, du[u], w.goff,
+                vals[cur ^ 1], slot2, w.gstart, w.seg_bound);
     u ^= 1;
     rounds++;
     if (pinned_u) {
@@ -669,7 +695,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     if (seg) {
       if (rounds <= 64) mask_out |= 1ull << (rounds - 1);
       const uint32_t gs = (uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile);
-      PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.rank, du[u], w.seg_bound,
+      PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.gstart, w.rank, du[u], w.seg_bound,
                   blk_start, d_nb, compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
       cur ^= 1;
     } else {

@@ -236,17 +236,18 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
 // both halves of both registers with packed 16-bit arithmetic: ranks below r
 // grow by one, the rank equal to r (the symbol itself; ranks are distinct)
 // becomes 0.  No lane diverges and no data moves between lanes.
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ u16x2 as_u16x2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
-__device__ __forceinline__ uint32_t as_u32(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
-
-// ranks x (two halves, each <= 255) after the symbol at rank r moves to front
+// ranks x (two halves, each <= 255) after the symbol at rank r moves to front:
+// t = x - r per half (wrapping below r), lt = t >> 15 (1 where x < r),
+// ne = min(t, 1) (1 where x != r), result (x + lt) * ne.  Written as packed
+// 16-bit instructions: the compiler otherwise splits the halves apart.
 __device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r2) {
-  const u16x2 xv = as_u16x2(x), rv = as_u16x2(r2);
-  const u16x2 lt = (u16x2)((xv - rv) >> (u16x2)15);                       // 1 where x < r
-  const u16x2 ne = (u16x2)(((xv ^ rv) + (u16x2)0x7FFF) >> (u16x2)15);      // 1 where x != r
-  return as_u32((xv + lt) * ne);
+  uint32_t t, lt, y, ne, out;
+  asm("v_pk_sub_u16 %0, %1, %2" : "=v"(t) : "v"(x), "s"(r2));
+  asm("v_pk_lshrrev_b16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(lt) : "v"(t));
+  asm("v_pk_add_u16 %0, %1, %2" : "=v"(y) : "v"(x), "v"(lt));
+  asm("v_pk_min_u16 %0, %1, 1 op_sel_hi:[1,0]" : "=v"(ne) : "v"(t));
+  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(out) : "v"(y), "v"(ne));
+  return out;
 }
 
 __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
   for (uint32_t base = p0; base < p1; base += 64) {
     const uint32_t p = base + lane;
     const uint32_t vl = p < p1 ? (uint32_t)ssym[p - p0] : 0u;
-    const uint32_t steps = min(64u, p1 - base);
+    const uint32_t steps = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(64u, p1 - base));
     uint32_t mine = 0;
     for (uint32_t k = 0; k < steps; k++) {
       const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
@@ -290,7 +291,8 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
       const uint32_t r2 = r * 0x10001u;
       R0 = mtf_ranks(R0, r2);
       R1 = mtf_ranks(R1, r2);
-      mine = lane == k ? r : mine;
+      // lane k keeps its index (one SGPR operand per instruction: the lane goes through m0)
+      asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(r), "s"(k) : "m0");
     }
     if (p < p1) idx[p] = (uint8_t)mine;
   }
