@@ -251,85 +251,219 @@ __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32
   }
 }
 
-// Group-start markers (the slot of each group's first element), for a
-// max-scan that yields every element's new rank.
-__global__ void k_bwt_heads(const uint64_t *keys, const uint32_t *slot, const uint32_t *d_u, uint32_t *mark,
-                            uint32_t *d_maxg) {
-  const uint32_t U = *d_u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x)
-    mark[k] = (k == 0 || keys[k] != keys[k - 1]) ? slot[k] : 0u;
-}
-
-// Writes ranks, and suffix-array entries of the elements that are now in a
-// group of one (or whose block is fully compared); flags the others and
-// records each element's position inside its group.  Also records the
-// largest group that stays unresolved (its last element knows the size:
-// slots of a group are consecutive and its rank is the first slot).
-__global__ __launch_bounds__(256) void k_bwt_update(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
-                                                    const uint32_t *newrank, const uint32_t *d_u,
-                                                    const uint32_t *blk_start, const uint32_t *d_nb,
-                                                    const uint32_t *d_min_m, uint32_t compared, uint32_t *rank,
-                                                    uint32_t *sa, uint32_t *unres, uint32_t *goff, uint32_t *d_maxg) {
-  __shared__ uint32_t red[256 / kWave];
-  const uint32_t U = *d_u, nb = *d_nb;
-  const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
-  uint32_t gmax = 0;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
-    const uint32_t g = vals[k];
-    rank[g] = newrank[k];
-    const bool first = (k == 0) || keys[k] != keys[k - 1];
-    const bool last = (k + 1 == U) || keys[k + 1] != keys[k];
-    bool done = first && last;
-    if (!done && any_short) {
-      const uint32_t b = block_of(blk_start, nb, g);
-      done = blk_start[b + 1] - blk_start[b] <= compared;
-    }
-    if (done) sa[slot[k]] = g;  // final position; unresolved ones are written in a later round
-    unres[k] = done ? 0u : 1u;
-    if (!done) {
-      const uint32_t off = slot[k] - newrank[k];  // position inside the group
-      goff[k] = off;
-      if (last) gmax = max(gmax, off + 1u);
-    }
-  }
-  for (int d = kWave / 2; d > 0; d >>= 1) gmax = max(gmax, (uint32_t)__shfl_xor((int)gmax, d));
-  if (lane_id() == 0) red[threadIdx.x / kWave] = gmax;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t m = 0;
-    for (int i = 0; i < 256 / kWave; i++) m = max(m, red[i]);
-    if (m) atomicMax(d_maxg, m);
-  }
-}
-
 constexpr int kSegThreads = 1024;
 constexpr uint32_t kSegCap = 8192;                     // elements staged per workgroup
 constexpr uint32_t kSegTile = 4096;                    // positions whose group starts a workgroup owns
 constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
 
-// Moves the unresolved elements to the front (their order kept), with the
-// compact position of each one's group start.  The last element of each
-// unresolved group also records the in-group sort's tile boundaries:
-// bound[t] = the first group start at or after t * kSegTile, which for every
-// t * kSegTile inside (group start, group end] is this group's end.
-__global__ void k_bwt_compact(const uint64_t *keys, const uint32_t *vals, const uint32_t *slot,
-                              const uint32_t *unres, const uint32_t *pos, const uint32_t *d_u,
-                              const uint32_t *goff, uint32_t *vals2, uint32_t *slot2, uint32_t *gstart2,
-                              uint32_t *bound) {
+// ---------------------------------------------------------------- one doubling round
+// A round turns the sorted list into ranks in three launches over tiles of
+// 4096 elements (256 threads x 16):
+//   k_rnd_marks    per-tile maximum of the group-start marks (a group start
+//                  is marked with its slot, other elements with 0);
+//   k_rnd_update   max-scan of the marks (each element's rank = its group's
+//                  first slot), rank and suffix-array writes, and per-tile
+//                  counts of the elements that stay unresolved;
+//   k_rnd_compact  exclusive scan of those flags and the compaction.
+// Each scan takes its carry by reducing the tile aggregates in front of its
+// tile itself (see scan.hip for why there is no look-back).
+constexpr int kRThreads = 256;
+constexpr int kRItems = 16;
+constexpr uint32_t kRTile = kRThreads * kRItems;
+constexpr uint32_t kUnresNone = 0xFFFFFFFFu;  // goffw entry of a resolved element
+
+__device__ __forceinline__ int rpad(int j) { return j + (j >> 5); }
+
+template <bool kMax>
+__device__ __forceinline__ uint32_t rop(uint32_t a, uint32_t b) { return kMax ? (a > b ? a : b) : a + b; }
+
+// Workgroup reduction of one value per thread (all threads get the result).
+template <bool kMax>
+__device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t *sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = rop<kMax>(v, (uint32_t)__shfl_xor((int)v, d));
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int i = 0; i < kRThreads / kWave; i++) t = rop<kMax>(t, sh[i]);
+  return t;
+}
+
+// Exclusive scan of 16 consecutive LDS values per thread (in place), from a
+// carry; returns the tile total (without the carry).
+template <bool kMax, bool kInclusive>
+__device__ __forceinline__ uint32_t tile_scan(uint32_t *buf, uint32_t carry, uint32_t *sh) {
+  uint32_t v[kRItems], acc = 0;
+#pragma unroll
+  for (int i = 0; i < kRItems; i++) {
+    v[i] = buf[rpad(threadIdx.x * kRItems + i)];
+    acc = rop<kMax>(acc, v[i]);
+  }
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  uint32_t x = acc;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)x, d);
+    if (lane >= d) x = rop<kMax>(o, x);
+  }
+  uint32_t xe = (uint32_t)__shfl_up((int)x, 1);
+  if (lane == 0) xe = 0;
+  __syncthreads();
+  if (lane == kWave - 1) sh[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < kRThreads / kWave; w++) {
+    if (w < wave) before = rop<kMax>(before, sh[w]);
+    total = rop<kMax>(total, sh[w]);
+  }
+  uint32_t run = rop<kMax>(carry, rop<kMax>(before, xe));
+#pragma unroll
+  for (int i = 0; i < kRItems; i++) {
+    const uint32_t nv = rop<kMax>(run, v[i]);
+    buf[rpad(threadIdx.x * kRItems + i)] = kInclusive ? nv : run;
+    run = nv;
+  }
+  __syncthreads();
+  return total;
+}
+
+// carry over aggs[counted, tile), extending a running carry
+template <bool kMax>
+__device__ __forceinline__ uint32_t tile_carry(const uint32_t *aggs, uint32_t &counted, uint32_t tile,
+                                               uint32_t carry, uint32_t *sh) {
+  uint32_t part = 0;
+  for (uint32_t j = counted + threadIdx.x; j < tile; j += kRThreads) part = rop<kMax>(part, aggs[j]);
+  counted = tile;
+  return rop<kMax>(carry, block_reduce<kMax>(part, sh));
+}
+
+__device__ __forceinline__ bool group_first(const uint64_t *keys, uint32_t k) {
+  return k == 0 || keys[k] != keys[k - 1];
+}
+
+__global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, const uint32_t *slot,
+                                                         const uint32_t *d_u, uint32_t *aggs, uint32_t *d_maxg) {
+  __shared__ uint32_t sh[kRThreads / kWave];
   const uint32_t U = *d_u;
-  if (blockIdx.x == 0 && threadIdx.x == 0) bound[0] = 0;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < U; k += gridDim.x * blockDim.x) {
-    if (unres[k]) {
-      const uint32_t q = pos[k], off = goff[k];
+  const uint32_t nt = (U + kRTile - 1) / kRTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t base = tile * kRTile;
+    uint32_t m = 0;
+#pragma unroll 4
+    for (int i = 0; i < kRItems; i++) {
+      const uint32_t k = base + (uint32_t)i * kRThreads + threadIdx.x;
+      if (k < U && group_first(keys, k)) m = max(m, slot[k]);
+    }
+    m = block_reduce<true>(m, sh);
+    if (threadIdx.x == 0) aggs[tile] = m;
+  }
+}
+
+// Ranks, suffix-array entries of the elements now in a group of one (or
+// whose block is fully compared), and for every other element its position
+// inside its group (goffw; kUnresNone for resolved ones).  Also the largest
+// group that stays unresolved (its last element knows the size: slots of a
+// group are consecutive and its rank is the first slot).
+__global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, const uint32_t *vals,
+                                                          const uint32_t *slot, const uint32_t *d_u,
+                                                          const uint32_t *aggs_m, const uint32_t *blk_start,
+                                                          const uint32_t *d_nb, const uint32_t *d_min_m,
+                                                          uint32_t compared, uint32_t *rank, uint32_t *sa,
+                                                          uint32_t *goffw, uint32_t *aggs_s, uint32_t *d_maxg) {
+  __shared__ uint32_t buf[kRTile + kRTile / 32];
+  __shared__ uint32_t sh[kRThreads / kWave];
+  const uint32_t U = *d_u, nb = *d_nb;
+  const uint32_t nt = (U + kRTile - 1) / kRTile;
+  const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
+  uint32_t carry = 0, counted = 0, gmax = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+    const uint32_t base = tile * kRTile;
+#pragma unroll 4
+    for (int i = 0; i < kRItems; i++) {
+      const int j = i * kRThreads + threadIdx.x;
+      const uint32_t k = base + (uint32_t)j;
+      buf[rpad(j)] = k < U && group_first(keys, k) ? slot[k] : 0u;
+    }
+    __syncthreads();
+    tile_scan<true, true>(buf, carry, sh);
+    uint32_t cnt = 0;
+#pragma unroll 4
+    for (int i = 0; i < kRItems; i++) {
+      const int j = i * kRThreads + threadIdx.x;
+      const uint32_t k = base + (uint32_t)j;
+      if (k >= U) continue;
+      const uint32_t nr = buf[rpad(j)], g = vals[k], sl = slot[k];
+      rank[g] = nr;
+      const bool first = sl == nr;  // ranks are first slots
+      const bool last = k + 1 == U || keys[k + 1] != keys[k];
+      bool done = first && last;
+      if (!done && any_short) {
+        const uint32_t b = block_of(blk_start, nb, g);
+        done = blk_start[b + 1] - blk_start[b] <= compared;
+      }
+      if (done) sa[sl] = g;  // final position; unresolved ones are written in a later round
+      const uint32_t off = sl - nr;
+      goffw[k] = done ? kUnresNone : off;
+      cnt += done ? 0u : 1u;
+      if (!done && last) gmax = max(gmax, off + 1u);
+    }
+    cnt = block_reduce<false>(cnt, sh);
+    if (threadIdx.x == 0) aggs_s[tile] = cnt;
+  }
+  gmax = block_reduce<true>(gmax, sh);
+  if (threadIdx.x == 0 && gmax) atomicMax(d_maxg, gmax);
+}
+
+// Moves the unresolved elements to the front (their order kept), with the
+// compact position of each one's group start; writes the new count.  The
+// last element of each unresolved group also records the in-group sort's
+// tile boundaries: bound[t] = the first group start at or after
+// t * kSegTile, which for every t * kSegTile inside (group start, group end]
+// is this group's end.
+__global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals, const uint32_t *slot,
+                                                           const uint32_t *goffw, const uint32_t *d_u,
+                                                           const uint32_t *aggs_s, uint32_t *vals2, uint32_t *slot2,
+                                                           uint32_t *gstart2, uint32_t *bound, uint32_t *d_unew) {
+  __shared__ uint32_t buf[kRTile + kRTile / 32];
+  __shared__ uint32_t sh[kRThreads / kWave];
+  const uint32_t U = *d_u;
+  const uint32_t nt = (U + kRTile - 1) / kRTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bound[0] = 0;
+    if (nt == 0) *d_unew = 0;
+  }
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    carry = tile_carry<false>(aggs_s, counted, tile, carry, sh);
+    const uint32_t base = tile * kRTile;
+    uint32_t w[kRItems];
+#pragma unroll
+    for (int i = 0; i < kRItems; i++) {
+      const int j = i * kRThreads + threadIdx.x;
+      const uint32_t k = base + (uint32_t)j;
+      w[i] = k < U ? goffw[k] : kUnresNone;
+      buf[rpad(j)] = w[i] != kUnresNone ? 1u : 0u;
+    }
+    __syncthreads();
+    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
+#pragma unroll
+    for (int i = 0; i < kRItems; i++) {
+      const int j = i * kRThreads + threadIdx.x;
+      const uint32_t k = base + (uint32_t)j;
+      if (w[i] == kUnresNone) continue;
+      const uint32_t q = buf[rpad(j)], off = w[i];
       vals2[q] = vals[k];
       slot2[q] = slot[k];
       gstart2[q] = q - off;
-      if (k + 1 == U || keys[k + 1] != keys[k]) {
+      const uint32_t wn = k + 1 < U ? goffw[k + 1] : kUnresNone;
+      if (wn == 0 || wn == kUnresNone) {  // last of its group: the next element starts another or is resolved
         const uint32_t head = q - off, end = q + 1u;
         for (uint32_t t = head / kSegTile + 1; (uint64_t)t * kSegTile <= end; t++) bound[t] = end;
       }
     }
+    if (tile == nt - 1 && threadIdx.x == 0) *d_unew = carry + total;
+    __syncthreads();
   }
 }
 
@@ -617,6 +751,8 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
 
 size_t seg_bound_words(uint32_t n_max) { return (size_t)n_max / kSegTile + 2; }
 
+size_t rnd_aggs_words(uint32_t n_max) { return 2 * ((size_t)n_max / kRTile + 2); }
+
 size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + 2047) / 2048 + 1); }
 
 // Sorts (keys[0], vals[0]) by the low `bits` bits of the key (n read from
@@ -664,15 +800,14 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   uint32_t n_cur = n_max;  // bound on the unresolved count (exact when read back)
   uint32_t maxg = 0xFFFFFFFFu;
   for (;;) {
-    const uint32_t gc = grid_for(n_cur);
-    // new ranks: max-scan of group-start slots
-    PCBZ_LAUNCH(k_bwt_heads, dim3(gc), dim3(256), 0, s, keys[cur], slot, du[u], w.flag, w.d_maxg);
-    scan_inclusive_max_u32(w.flag, w.flag, du[u], n_cur, w.scan_tmp, s);
-    PCBZ_LAUNCH(k_bwt_update, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag, du[u], blk_start, d_nb,
-                w.d_min_m, compared, w.rank, sa, w.flag2, w.goff, w.d_maxg);
-    scan_exclusive_u32(w.flag2, w.flag, du[u], n_cur, w.scan_tmp, du[u ^ 1], s);
-    PCBZ_LAUNCH(k_bwt_compact, dim3(gc), dim3(256), 0, s, keys[cur], vals[cur], slot, w.flag2, w.flag, du[u], w.goff,
-                vals[cur ^ 1], slot2, w.gstart, w.seg_bound);
+    // new ranks (max-scan of group-start slots), then the compaction
+    const uint32_t gt = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kGridCap, (n_cur + kRTile - 1) / kRTile));
+    uint32_t *aggs_m = w.aggs, *aggs_s = w.aggs + rnd_aggs_words(n_max) / 2;
+    PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot, du[u], aggs_m, w.d_maxg);
+    PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot, du[u], aggs_m, blk_start,
+                d_nb, w.d_min_m, compared, w.rank, sa, w.goff, aggs_s, w.d_maxg);
+    PCBZ_LAUNCH(k_rnd_compact, dim3(gt), dim3(kRThreads), 0, s, vals[cur], slot, w.goff, du[u], aggs_s, vals[cur ^ 1],
+                slot2, w.gstart, w.seg_bound, du[u ^ 1]);
     u ^= 1;
     rounds++;
     if (pinned_u) {

@@ -225,8 +225,6 @@ struct BwtWork {
   uint32_t *slot;
   uint32_t *slot2;
   uint32_t *rank;
-  uint32_t *flag;       // [N+1]
-  uint32_t *flag2;      // [N+1]
   uint32_t *counts;     // radix tile counts
   uint32_t *d_u;        // [2] unresolved counts (device)
   uint32_t *d_count_n;  // size of the current count table (device)
@@ -234,12 +232,14 @@ struct BwtWork {
   uint32_t *d_maxg;     // largest unresolved group of the last round (device, d_u + 6)
   uint32_t *d_fail;     // set when a group did not fit the in-group sort (device)
   uint32_t *seg_bound;  // [seg_bound_words] tile boundaries of the in-group sort
-  uint32_t *goff;       // [N+1] position of each element inside its group
+  uint32_t *goff;       // [N+1] position of each element inside its group (all ones: resolved)
   uint32_t *gstart;     // [N+1] compact position of each unresolved element's group start
+  uint32_t *aggs;       // [rnd_aggs_words] tile aggregates of a doubling round's two scans
   void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max);
 size_t seg_bound_words(uint32_t n_max);
+size_t rnd_aggs_words(uint32_t n_max);
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
                uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
