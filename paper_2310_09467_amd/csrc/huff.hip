@@ -87,23 +87,29 @@ __global__ void k_sel_bases(const uint32_t *d_nb, BlockCode *codes, uint32_t *gr
   *d_n_groups = acc;
 }
 
-__global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const uint32_t *d_nb,
-                                                    const BlockCode *codes, const uint32_t *group_base,
-                                                    const uint32_t *d_n_groups, const uint8_t *cost, uint8_t *sel,
-                                                    uint32_t *tfreq) {
+// One workgroup per 256 selector groups, four lanes per group (each sums
+// the costs of every fourth symbol; the lanes then combine their sums).
+constexpr int kSelLanes = 4;
+constexpr int kSelGroups = 256;
+constexpr int kSelThreads = kSelGroups * kSelLanes;
+
+__global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym, const uint32_t *d_nb,
+                                                            const BlockCode *codes, const uint32_t *group_base,
+                                                            const uint32_t *d_n_groups, const uint8_t *cost,
+                                                            uint8_t *sel, uint32_t *tfreq) {
   __shared__ uint32_t tf[kMaxGroups * kMaxAlpha];
   __shared__ uint64_t c03[kMaxAlpha];  // costs of tables 0..3 in 16-bit lanes (a group sums to <= 50*17)
   __shared__ uint32_t c45[kMaxAlpha];  // tables 4..5
-  __shared__ uint16_t ssym[256 * kGroupSize];
+  __shared__ uint16_t ssym[kSelGroups * kGroupSize];
   const uint32_t ngroups = *d_n_groups, nb = *d_nb;
-  const uint32_t g0 = blockIdx.x * blockDim.x;
+  const uint32_t g0 = blockIdx.x * kSelGroups;
   if (g0 >= ngroups) return;
-  for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += 256) tf[i] = 0;
+  for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += kSelThreads) tf[i] = 0;
   const uint32_t b0 = upper_index(group_base, nb, g0);
   const BlockCode C0 = codes[b0];
   {
     const uint8_t *cst = cost + (size_t)b0 * kMaxGroups * kMaxAlpha;
-    for (uint32_t s = threadIdx.x; s < C0.alpha; s += 256) {
+    for (uint32_t s = threadIdx.x; s < C0.alpha; s += kSelThreads) {
       c03[s] = (uint64_t)cst[s] | ((uint64_t)cst[kMaxAlpha + s] << 16) | ((uint64_t)cst[2 * kMaxAlpha + s] << 32) |
                ((uint64_t)cst[3 * kMaxAlpha + s] << 48);
       c45[s] = (uint32_t)cst[4 * kMaxAlpha + s] | ((uint32_t)cst[5 * kMaxAlpha + s] << 16);
@@ -113,61 +119,63 @@ __global__ __launch_bounds__(256) void k_tab_select(const uint16_t *sym, const u
   const uint32_t first_sym = C0.sym_start + (g0 - group_base[b0]) * kGroupSize;
   uint32_t end_sym;
   {
-    const uint32_t gl = min(g0 + 256u, ngroups) - 1u;
+    const uint32_t gl = min(g0 + (uint32_t)kSelGroups, ngroups) - 1u;
     const uint32_t bl = upper_index(group_base, nb, gl);
     const BlockCode CL = codes[bl];
     end_sym = min(CL.sym_start + (gl - group_base[bl]) * kGroupSize + kGroupSize, CL.sym_start + CL.n_mtf);
   }
   stage_to_lds(ssym, sym + first_sym, end_sym - first_sym);
   __syncthreads();
-  const uint32_t gi = g0 + threadIdx.x;
+  const uint32_t gi = g0 + threadIdx.x / kSelLanes, sub = threadIdx.x % kSelLanes;
   const uint32_t b0_end = group_base[b0 + 1];
-  if (gi < ngroups) {
-    const uint32_t b = gi < b0_end ? b0 : upper_index(group_base, nb, gi);
-    const BlockCode C = codes[b];
-    const uint32_t j = gi - group_base[b];
-    const uint32_t lo = C.sym_start + j * kGroupSize;
-    const uint32_t hi = min(C.sym_start + C.n_mtf, lo + kGroupSize);
-    uint32_t c[kMaxGroups] = {0, 0, 0, 0, 0, 0};
-    if (b == b0) {
-      uint64_t a03 = 0;
-      uint32_t a45 = 0;
-      for (uint32_t k = lo; k < hi; k++) {
-        const uint32_t s = ssym[k - first_sym];
-        a03 += c03[s];
-        a45 += c45[s];
-      }
-      c[0] = (uint32_t)(a03 & 0xFFFFu);
-      c[1] = (uint32_t)((a03 >> 16) & 0xFFFFu);
-      c[2] = (uint32_t)((a03 >> 32) & 0xFFFFu);
-      c[3] = (uint32_t)(a03 >> 48);
-      c[4] = a45 & 0xFFFFu;
-      c[5] = a45 >> 16;
-    } else {
-      const uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
-      for (uint32_t k = lo; k < hi; k++) {
-        const uint32_t s = ssym[k - first_sym];
-#pragma unroll
-        for (int g = 0; g < kMaxGroups; g++) c[g] += cst[g * kMaxAlpha + s];
-      }
+  // every lane of a group takes the same branches (the group index decides them)
+  const bool valid = gi < ngroups;
+  const uint32_t b = !valid || gi < b0_end ? b0 : upper_index(group_base, nb, gi);
+  const BlockCode C = codes[b];
+  const uint32_t j = valid ? gi - group_base[b] : 0u;
+  const uint32_t lo = C.sym_start + j * kGroupSize;
+  const uint32_t hi = valid ? min(C.sym_start + C.n_mtf, lo + kGroupSize) : lo;
+  uint64_t a03 = 0;
+  uint32_t a45 = 0;
+  if (b == b0) {
+    for (uint32_t k = lo + sub; k < hi; k += kSelLanes) {
+      const uint32_t s = ssym[k - first_sym];
+      a03 += c03[s];
+      a45 += c45[s];
     }
+  } else {
+    const uint8_t *cst = cost + (size_t)b * kMaxGroups * kMaxAlpha;
+    for (uint32_t k = lo + sub; k < hi; k += kSelLanes) {
+      const uint32_t s = ssym[k - first_sym];
+      a03 += (uint64_t)cst[s] | ((uint64_t)cst[kMaxAlpha + s] << 16) | ((uint64_t)cst[2 * kMaxAlpha + s] << 32) |
+             ((uint64_t)cst[3 * kMaxAlpha + s] << 48);
+      a45 += (uint32_t)cst[4 * kMaxAlpha + s] | ((uint32_t)cst[5 * kMaxAlpha + s] << 16);
+    }
+  }
+  // combine the four lanes of the group (16-bit fields cannot carry over: <= 50 * 17)
+  for (int d = 1; d < kSelLanes; d <<= 1) {
+    const uint32_t lo32 = (uint32_t)__shfl_xor((int)(uint32_t)a03, d);
+    const uint32_t hi32 = (uint32_t)__shfl_xor((int)(uint32_t)(a03 >> 32), d);
+    a03 += ((uint64_t)hi32 << 32) | lo32;
+    a45 += (uint32_t)__shfl_xor((int)a45, d);
+  }
+  if (valid) {
+    const uint32_t c[kMaxGroups] = {(uint32_t)(a03 & 0xFFFFu), (uint32_t)((a03 >> 16) & 0xFFFFu),
+                                    (uint32_t)((a03 >> 32) & 0xFFFFu), (uint32_t)(a03 >> 48), a45 & 0xFFFFu,
+                                    a45 >> 16};
     uint32_t best = 0, bc = c[0];
     for (uint32_t g = 1; g < C.n_groups; g++)
       if (c[g] < bc) {
         bc = c[g];
         best = g;
       }
-    sel[C.sel_start + j] = (uint8_t)best;
-    if (b == b0) {
-      for (uint32_t k = lo; k < hi; k++) atomicAdd(&tf[best * kMaxAlpha + ssym[k - first_sym]], 1u);
-    } else {
-      uint32_t *t = tfreq + ((size_t)b * kMaxGroups + best) * kMaxAlpha;
-      for (uint32_t k = lo; k < hi; k++) atomicAdd(&t[ssym[k - first_sym]], 1u);
-    }
+    if (sub == 0) sel[C.sel_start + j] = (uint8_t)best;
+    uint32_t *t = b == b0 ? tf + best * kMaxAlpha : tfreq + ((size_t)b * kMaxGroups + best) * kMaxAlpha;
+    for (uint32_t k = lo + sub; k < hi; k += kSelLanes) atomicAdd(&t[ssym[k - first_sym]], 1u);
   }
   __syncthreads();
   uint32_t *t0 = tfreq + (size_t)b0 * kMaxGroups * kMaxAlpha;
-  for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += 256)
+  for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += kSelThreads)
     if (tf[i]) atomicAdd(&t0[i], tf[i]);
 }
 
@@ -203,6 +211,8 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
   __shared__ uint8_t pk[kLevels + 1][kMaxItems];
   __shared__ uint8_t ln[kMaxAlpha];
   __shared__ uint32_t nlen[kMaxCodeLen + 2], base[kMaxCodeLen + 2];
+  __shared__ uint64_t pkw[kLevels + 1][2 * kPmThreads / kWave];  // package flags of each level as bit words
+  __shared__ uint32_t leaves_sel[kLevels + 1];                      // leaves among each level's selected prefix
   const uint32_t b = blockIdx.x / kMaxGroups, g = blockIdx.x % kMaxGroups;
   if (b >= *d_nb) return;
   const BlockCode C = codes[b];
@@ -245,16 +255,34 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
     size = n + np;
     cur ^= 1;
     __syncthreads();
+    // this level's package flags as bit words (positions t and t + kPmThreads)
+    const uint64_t w0 = ballot64(t < size && pk[j][t]);
+    const uint64_t w1 = ballot64(t + kPmThreads < size && pk[j][t + kPmThreads]);
+    if (lane_id() == 0) {
+      pkw[j][t / kWave] = w0;
+      pkw[j][kPmThreads / kWave + t / kWave] = w1;
+    }
   }
-  // select the first 2(n-1) items at the top and follow the packages down
+  __syncthreads();
+  // select the first 2(n-1) items at the top and follow the packages down:
+  // at each level p = packages among the selected prefix, its leaves are the
+  // first selc - p leaves, and the level below selects 2p items
+  if (t == 0) {
+    uint32_t selc = 2 * (n - 1);
+    for (int j = 1; j <= kLevels; j++) {
+      uint32_t p = 0;
+      if (j < kLevels) {
+        const uint32_t full = selc / kWave, rest = selc % kWave;
+        for (uint32_t q = 0; q < full; q++) p += (uint32_t)__popcll(pkw[j][q]);
+        if (rest) p += (uint32_t)__popcll(pkw[j][full] & ((1ull << rest) - 1ull));
+      }
+      leaves_sel[j] = selc - p;
+      selc = 2 * p;
+    }
+  }
+  __syncthreads();
   uint32_t cnt = 0;
-  uint32_t selc = 2 * (n - 1);
-  for (int j = 1; j <= kLevels; j++) {
-    const uint32_t p = (uint32_t)__syncthreads_count(t < selc && pk[j][t]) +
-                       (uint32_t)__syncthreads_count(t + kPmThreads < selc && pk[j][t + kPmThreads]);
-    if (t < n && t < selc - p) cnt++;
-    selc = 2 * p;
-  }
+  for (int j = 1; j <= kLevels; j++) cnt += t < n && t < leaves_sel[j] ? 1u : 0u;
   if (t < n) {
     ln[lsym[t]] = (uint8_t)cnt;
     atomicAdd(&nlen[cnt], 1u);
@@ -296,8 +324,8 @@ void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks
   PCBZ_LAUNCH(k_tab_init, dim3(max_blocks), dim3(256), 0, s, d_nb, codes, freq, cost);
   PCBZ_LAUNCH(k_sel_bases, dim3(1), dim3(64), 0, s, d_nb, codes, group_base, d_n_groups);
   for (int it = 0; it < 4; it++) {
-    PCBZ_LAUNCH(k_tab_select, dim3((max_groups + 255) / 256), dim3(256), 0, s, sym, d_nb, codes, group_base,
-                       d_n_groups, cost, sel, tfreq);
+    PCBZ_LAUNCH(k_tab_select, dim3((max_groups + kSelGroups - 1) / kSelGroups), dim3(kSelThreads), 0, s, sym, d_nb,
+                codes, group_base, d_n_groups, cost, sel, tfreq);
     PCBZ_LAUNCH(k_tab_lengths, dim3(max_blocks * kMaxGroups), dim3(kPmThreads), 0, s, d_nb, codes, tfreq, cost, lens,
                        code_words, it == 3 ? 1 : 0);
   }
