@@ -276,12 +276,22 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
   __syncthreads();
   uint32_t R0 = (uint32_t)rk[lane] | ((uint32_t)rk[lane + 64] << 16);
   uint32_t R1 = (uint32_t)rk[lane + 128] | ((uint32_t)rk[lane + 192] << 16);
+  // A symbol equal to the one before it has index 0 and leaves the list as
+  // it is (about half the positions of a typical block): only the other
+  // positions are replayed.  The chunk's first position is always replayed.
+  uint32_t before = 0xFFFFFFFFu;  // symbol at the position before this batch
   for (uint32_t base = p0; base < p1; base += 64) {
     const uint32_t p = base + lane;
-    const uint32_t vl = p < p1 ? (uint32_t)ssym[p - p0] : 0u;
-    const uint32_t steps = (uint32_t)__builtin_amdgcn_readfirstlane((int)min(64u, p1 - base));
+    const bool in = p < p1;
+    const uint32_t vl = in ? (uint32_t)ssym[p - p0] : 0u;
+    uint32_t pv = (uint32_t)__shfl_up((int)vl, 1);
+    if (lane == 0) pv = before;
+    uint64_t todo = ballot64(in && vl != pv);
+    before = (uint32_t)__builtin_amdgcn_readlane((int)vl, 63);
     uint32_t mine = 0;
-    for (uint32_t k = 0; k < steps; k++) {
+    while (todo) {
+      const uint32_t k = (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
       const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
       const uint32_t sl = v & 63u;
       const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
       // lane k keeps its index (one SGPR operand per instruction: the lane goes through m0)
       asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(r), "s"(k) : "m0");
     }
-    if (p < p1) idx[p] = (uint8_t)mine;
+    if (in) idx[p] = (uint8_t)mine;
   }
 }
 
