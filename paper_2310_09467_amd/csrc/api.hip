@@ -448,8 +448,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.mw.idx = A.get<uint8_t>(nr + 16);
   // the MTF stage runs after the suffix sort: reuse the sort's key buffers
   w.mw.zs = w.bw.key[0] ? (uint32_t *)w.bw.key[0] : nullptr;
-  w.mw.len = w.bw.key[0] ? (uint32_t *)w.bw.key[0] + (nr + 1) : nullptr;
   w.mw.off = w.bw.key[1] ? (uint32_t *)w.bw.key[1] : nullptr;
+  w.mw.aggs = w.bw.aggs;  // free once the suffix sort is done
   w.mw.d_n_chunks = w.ctr ? w.ctr + 4 : nullptr;
   w.max_sym = (uint32_t)(nr + S + 1);
   w.sym = A.get<uint16_t>(w.max_sym + 16);
@@ -475,7 +475,6 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.scan_tmp = A.get<uint8_t>(scan_tmp_bytes(scan_n));
   w.scan_n = scan_n;
   w.bw.scan_tmp = w.scan_tmp;
-  w.mw.scan_tmp = w.scan_tmp;
   return A.off;
 }
 

@@ -267,74 +267,10 @@ constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-t
 //   k_rnd_compact  exclusive scan of those flags and the compaction.
 // Each scan takes its carry by reducing the tile aggregates in front of its
 // tile itself (see scan.hip for why there is no look-back).
-constexpr int kRThreads = 256;
-constexpr int kRItems = 16;
-constexpr uint32_t kRTile = kRThreads * kRItems;
+constexpr int kRThreads = kTThreads;
+constexpr int kRItems = kTItems;
+constexpr uint32_t kRTile = kTTile;
 constexpr uint32_t kUnresNone = 0xFFFFFFFFu;  // goffw entry of a resolved element
-
-__device__ __forceinline__ int rpad(int j) { return j + (j >> 5); }
-
-template <bool kMax>
-__device__ __forceinline__ uint32_t rop(uint32_t a, uint32_t b) { return kMax ? (a > b ? a : b) : a + b; }
-
-// Workgroup reduction of one value per thread (all threads get the result).
-template <bool kMax>
-__device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t *sh) {
-  for (int d = kWave / 2; d > 0; d >>= 1) v = rop<kMax>(v, (uint32_t)__shfl_xor((int)v, d));
-  __syncthreads();
-  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
-  __syncthreads();
-  uint32_t t = 0;
-  for (int i = 0; i < kRThreads / kWave; i++) t = rop<kMax>(t, sh[i]);
-  return t;
-}
-
-// Exclusive scan of 16 consecutive LDS values per thread (in place), from a
-// carry; returns the tile total (without the carry).
-template <bool kMax, bool kInclusive>
-__device__ __forceinline__ uint32_t tile_scan(uint32_t *buf, uint32_t carry, uint32_t *sh) {
-  uint32_t v[kRItems], acc = 0;
-#pragma unroll
-  for (int i = 0; i < kRItems; i++) {
-    v[i] = buf[rpad(threadIdx.x * kRItems + i)];
-    acc = rop<kMax>(acc, v[i]);
-  }
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
-  uint32_t x = acc;
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = (uint32_t)__shfl_up((int)x, d);
-    if (lane >= d) x = rop<kMax>(o, x);
-  }
-  uint32_t xe = (uint32_t)__shfl_up((int)x, 1);
-  if (lane == 0) xe = 0;
-  __syncthreads();
-  if (lane == kWave - 1) sh[wave] = x;
-  __syncthreads();
-  uint32_t before = 0, total = 0;
-  for (int w = 0; w < kRThreads / kWave; w++) {
-    if (w < wave) before = rop<kMax>(before, sh[w]);
-    total = rop<kMax>(total, sh[w]);
-  }
-  uint32_t run = rop<kMax>(carry, rop<kMax>(before, xe));
-#pragma unroll
-  for (int i = 0; i < kRItems; i++) {
-    const uint32_t nv = rop<kMax>(run, v[i]);
-    buf[rpad(threadIdx.x * kRItems + i)] = kInclusive ? nv : run;
-    run = nv;
-  }
-  __syncthreads();
-  return total;
-}
-
-// carry over aggs[counted, tile), extending a running carry
-template <bool kMax>
-__device__ __forceinline__ uint32_t tile_carry(const uint32_t *aggs, uint32_t &counted, uint32_t tile,
-                                               uint32_t carry, uint32_t *sh) {
-  uint32_t part = 0;
-  for (uint32_t j = counted + threadIdx.x; j < tile; j += kRThreads) part = rop<kMax>(part, aggs[j]);
-  counted = tile;
-  return rop<kMax>(carry, block_reduce<kMax>(part, sh));
-}
 
 __device__ __forceinline__ bool group_first(const uint64_t *keys, uint32_t k) {
   return k == 0 || keys[k] != keys[k - 1];
@@ -383,7 +319,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, 
     for (int i = 0; i < kRItems; i++) {
       const int j = i * kRThreads + threadIdx.x;
       const uint32_t k = base + (uint32_t)j;
-      buf[rpad(j)] = k < U && group_first(keys, k) ? slot[k] : 0u;
+      buf[tpad(j)] = k < U && group_first(keys, k) ? slot[k] : 0u;
     }
     __syncthreads();
     tile_scan<true, true>(buf, carry, sh);
@@ -393,7 +329,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, 
       const int j = i * kRThreads + threadIdx.x;
       const uint32_t k = base + (uint32_t)j;
       if (k >= U) continue;
-      const uint32_t nr = buf[rpad(j)], g = vals[k], sl = slot[k];
+      const uint32_t nr = buf[tpad(j)], g = vals[k], sl = slot[k];
       rank[g] = nr;
       const bool first = sl == nr;  // ranks are first slots
       const bool last = k + 1 == U || keys[k + 1] != keys[k];
@@ -443,7 +379,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals,
       const int j = i * kRThreads + threadIdx.x;
       const uint32_t k = base + (uint32_t)j;
       w[i] = k < U ? goffw[k] : kUnresNone;
-      buf[rpad(j)] = w[i] != kUnresNone ? 1u : 0u;
+      buf[tpad(j)] = w[i] != kUnresNone ? 1u : 0u;
     }
     __syncthreads();
     const uint32_t total = tile_scan<false, false>(buf, carry, sh);
@@ -452,7 +388,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals,
       const int j = i * kRThreads + threadIdx.x;
       const uint32_t k = base + (uint32_t)j;
       if (w[i] == kUnresNone) continue;
-      const uint32_t q = buf[rpad(j)], off = w[i];
+      const uint32_t q = buf[tpad(j)], off = w[i];
       vals2[q] = vals[k];
       slot2[q] = slot[k];
       gstart2[q] = q - off;

@@ -170,8 +170,15 @@ __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym,
         best = g;
       }
     if (sub == 0) sel[C.sel_start + j] = (uint8_t)best;
-    uint32_t *t = b == b0 ? tf + best * kMaxAlpha : tfreq + ((size_t)b * kMaxGroups + best) * kMaxAlpha;
-    for (uint32_t k = lo + sub; k < hi; k += kSelLanes) atomicAdd(&t[ssym[k - first_sym]], 1u);
+    // separate loops keep the LDS counters on LDS atomics (a pointer that may
+    // point to either memory would make every update a flat atomic)
+    if (b == b0) {
+      uint32_t *t = tf + best * kMaxAlpha;
+      for (uint32_t k = lo + sub; k < hi; k += kSelLanes) atomicAdd(&t[ssym[k - first_sym]], 1u);
+    } else {
+      uint32_t *t = tfreq + ((size_t)b * kMaxGroups + best) * kMaxAlpha;
+      for (uint32_t k = lo + sub; k < hi; k += kSelLanes) atomicAdd(&t[ssym[k - first_sym]], 1u);
+    }
   }
   __syncthreads();
   uint32_t *t0 = tfreq + (size_t)b0 * kMaxGroups * kMaxAlpha;

@@ -12,6 +12,8 @@
 // Zero runs: a run of r zero indices becomes the bijective base-2 digits of
 // r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
 // non-zero index v becomes v + 1; each block ends with nInUse + 1.
+#include <algorithm>
+
 #include "pcbz_internal.hpp"
 
 namespace pcbz {
@@ -308,40 +310,164 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
   }
 }
 
-// zero-run start markers: a position starts a segment if it begins the block
-// or follows a non-zero index
-__global__ __launch_bounds__(256) void k_rle2_mark(const uint8_t *idx, const uint32_t *chunk_base,
-                                                   const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                   const uint32_t *d_nb, uint32_t *mark) {
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
-  uint32_t b, p0, p1, bs, be;
-  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) mark[p] = (p == bs || idx[p - 1] != 0) ? p : 0u;
-}
+// ---------------------------------------------------------------- zero runs
+// Every position p of a block belongs to a segment that starts at zs[p]: the
+// block start or the position after the last nonzero index.  Its symbol
+// count is 1 for a nonzero index, the number of bijective base-2 digits of
+// the run at the run's last zero, 0 elsewhere inside a run, plus 1 for the
+// end-of-block symbol at the block's last position.  Three launches over
+// tiles of 4096 positions (per-tile maxima of the segment-start marks;
+// max-scan of the marks (zs) with per-tile symbol counts; exclusive scan of
+// the counts), then the symbol output, one workgroup per chunk.
 
 __device__ __forceinline__ uint32_t ndigits(uint32_t r) { return 31u - __clz(r + 1u); }
 
-__global__ __launch_bounds__(256) void k_rle2_len(const uint8_t *idx, const uint32_t *zs, const uint32_t *chunk_base,
-                                                  const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                  const uint32_t *d_nb, uint32_t *len) {
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
-  uint32_t b, p0, p1, bs, be;
-  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
-    uint32_t l;
-    if (idx[p] != 0)
-      l = 1;
-    else if (p + 1 == be || idx[p + 1] != 0)
-      l = ndigits(p - zs[p] + 1);
-    else
-      l = 0;
-    if (p + 1 == be) l += 1;  // end-of-block symbol
-    len[p] = l;
+// The blocks a tile touches: the first one's bounds are kept in registers,
+// positions past it (tiles that cross a block end) search forward.
+struct TileBlocks {
+  const uint32_t *blk_start;
+  uint32_t nb, b0, s0, e0;
+  __device__ TileBlocks(const uint32_t *bs, uint32_t n, uint32_t base) : blk_start(bs), nb(n) {
+    b0 = upper_index(bs, n, base);
+    s0 = bs[b0];
+    e0 = bs[b0 + 1];
+  }
+  // block of p (p >= the tile base), with its start and end
+  __device__ __forceinline__ uint32_t find(uint32_t p, uint32_t &s, uint32_t &e) const {
+    if (p < e0) {
+      s = s0;
+      e = e0;
+      return b0;
+    }
+    uint32_t b = b0;
+    while (b + 1 < nb && blk_start[b + 1] <= p) b++;
+    s = blk_start[b];
+    e = blk_start[b + 1];
+    return b;
+  }
+};
+
+__device__ __forceinline__ uint32_t zrun_len(const uint8_t *idx, uint32_t p, uint32_t z, uint32_t be) {
+  uint32_t l;
+  if (idx[p] != 0)
+    l = 1;
+  else if (p + 1 == be || idx[p + 1] != 0)
+    l = ndigits(p - z + 1);
+  else
+    l = 0;
+  return p + 1 == be ? l + 1 : l;  // end-of-block symbol
+}
+
+__global__ __launch_bounds__(kTThreads) void k_z_marks(const uint8_t *idx, const uint32_t *d_N,
+                                                       const uint32_t *blk_start, const uint32_t *d_nb,
+                                                       uint32_t *aggs) {
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t N = *d_N, nb = *d_nb;
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t base = tile * kTTile;
+    const TileBlocks tb(blk_start, nb, base);
+    uint32_t m = 0;
+#pragma unroll 4
+    for (int i = 0; i < kTItems; i++) {
+      const uint32_t p = base + (uint32_t)i * kTThreads + threadIdx.x;
+      if (p >= N) continue;
+      uint32_t bs, be;
+      tb.find(p, bs, be);
+      if (p == bs || idx[p - 1] != 0) m = max(m, p);
+    }
+    m = block_reduce<true>(m, sh);
+    if (threadIdx.x == 0) aggs[tile] = m;
   }
 }
 
+__global__ __launch_bounds__(kTThreads) void k_z_runs(const uint8_t *idx, const uint32_t *d_N,
+                                                      const uint32_t *blk_start, const uint32_t *d_nb,
+                                                      const uint32_t *aggs_m, uint32_t *zs, uint32_t *aggs_l) {
+  __shared__ uint32_t buf[kTPad];
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t N = *d_N, nb = *d_nb;
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+    const uint32_t base = tile * kTTile;
+    const TileBlocks tb(blk_start, nb, base);
+#pragma unroll 4
+    for (int i = 0; i < kTItems; i++) {
+      const int j = i * kTThreads + threadIdx.x;
+      const uint32_t p = base + (uint32_t)j;
+      uint32_t mk = 0;
+      if (p < N) {
+        uint32_t bs, be;
+        tb.find(p, bs, be);
+        mk = p == bs || idx[p - 1] != 0 ? p : 0u;
+      }
+      buf[tpad(j)] = mk;
+    }
+    __syncthreads();
+    tile_scan<true, true>(buf, carry, sh);
+    uint32_t cnt = 0;
+#pragma unroll 4
+    for (int i = 0; i < kTItems; i++) {
+      const int j = i * kTThreads + threadIdx.x;
+      const uint32_t p = base + (uint32_t)j;
+      if (p >= N) continue;
+      const uint32_t z = buf[tpad(j)];
+      zs[p] = z;
+      uint32_t bs, be;
+      tb.find(p, bs, be);
+      cnt += zrun_len(idx, p, z, be);
+    }
+    cnt = block_reduce<false>(cnt, sh);
+    if (threadIdx.x == 0) aggs_l[tile] = cnt;
+  }
+}
+
+// Exclusive scan of the symbol counts: off[p] = first symbol of position p;
+// the total goes to *d_n_sym.
+__global__ __launch_bounds__(kTThreads) void k_z_offs(const uint8_t *idx, const uint32_t *zs, const uint32_t *d_N,
+                                                      const uint32_t *blk_start, const uint32_t *d_nb,
+                                                      const uint32_t *aggs_l, uint32_t *off, uint32_t *d_n_sym) {
+  __shared__ uint32_t buf[kTPad];
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t N = *d_N, nb = *d_nb;
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nt == 0) *d_n_sym = 0;
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    carry = tile_carry<false>(aggs_l, counted, tile, carry, sh);
+    const uint32_t base = tile * kTTile;
+    const TileBlocks tb(blk_start, nb, base);
+#pragma unroll 4
+    for (int i = 0; i < kTItems; i++) {
+      const int j = i * kTThreads + threadIdx.x;
+      const uint32_t p = base + (uint32_t)j;
+      uint32_t l = 0;
+      if (p < N) {
+        uint32_t bs, be;
+        tb.find(p, bs, be);
+        l = zrun_len(idx, p, zs[p], be);
+      }
+      buf[tpad(j)] = l;
+    }
+    __syncthreads();
+    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
+#pragma unroll 4
+    for (int i = 0; i < kTItems; i++) {
+      const int j = i * kTThreads + threadIdx.x;
+      const uint32_t p = base + (uint32_t)j;
+      if (p < N) off[p] = buf[tpad(j)];
+    }
+    if (tile == nt - 1 && threadIdx.x == 0) *d_n_sym = carry + total;
+    __syncthreads();
+  }
+}
+
+// Symbol output, one workgroup per chunk: a nonzero index v becomes v + 1, a
+// zero run of length r its bijective digits (RUNA = 0, RUNB = 1, least
+// significant first), each block ends with n_in_use + 1; per-block symbol
+// frequencies, first symbol and count.
 __global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const uint32_t *zs, const uint32_t *off,
                                                     const uint32_t *chunk_base, const uint32_t *d_n_chunks,
                                                     const uint32_t *blk_start, const uint32_t *d_nb,
@@ -400,13 +526,13 @@ void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32
               w.inlist);
   PCBZ_LAUNCH(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.inlist, w.idx);
-  PCBZ_LAUNCH(k_rle2_mark, dim3(max_chunks), dim3(256), 0, s, w.idx, cb, w.d_n_chunks, blk_start, d_nb, w.zs);
-  scan_inclusive_max_u32(w.zs, w.zs, d_N, N, w.scan_tmp, s);
-  PCBZ_LAUNCH(k_rle2_len, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, cb, w.d_n_chunks, blk_start, d_nb,
-                     w.len);
-  scan_exclusive_u32(w.len, w.off, d_N, N, w.scan_tmp, d_n_sym, s);
-  PCBZ_LAUNCH(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks,
-                     blk_start, d_nb, codes, sym, freq);
+  const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (N + kTTile - 1) / kTTile));
+  uint32_t *aggs_m = w.aggs, *aggs_l = w.aggs + (N / kTTile + 2);
+  PCBZ_LAUNCH(k_z_marks, dim3(gt), dim3(kTThreads), 0, s, w.idx, d_N, blk_start, d_nb, aggs_m);
+  PCBZ_LAUNCH(k_z_runs, dim3(gt), dim3(kTThreads), 0, s, w.idx, d_N, blk_start, d_nb, aggs_m, w.zs, aggs_l);
+  PCBZ_LAUNCH(k_z_offs, dim3(gt), dim3(kTThreads), 0, s, w.idx, w.zs, d_N, blk_start, d_nb, aggs_l, w.off, d_n_sym);
+  PCBZ_LAUNCH(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks, blk_start, d_nb,
+              codes, sym, freq);
 }
 
 }  // namespace pcbz

@@ -102,6 +102,80 @@ __device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 
+// ---------------------------------------------------------------- tile scans
+// Building blocks of the fused scans (a scan whose input is computed on the
+// fly and whose consumer runs in the same kernel): tiles of 4096 elements,
+// 256 threads x 16; the carry of a tile is the reduction of the tile
+// aggregates in front of it, which each workgroup sums itself.
+constexpr int kTThreads = 256;
+constexpr int kTItems = 16;
+constexpr uint32_t kTTile = kTThreads * kTItems;
+constexpr uint32_t kTPad = kTTile + kTTile / 32;  // LDS words of a padded tile
+
+__device__ __forceinline__ int tpad(int j) { return j + (j >> 5); }
+
+template <bool kMax>
+__device__ __forceinline__ uint32_t top(uint32_t a, uint32_t b) { return kMax ? (a > b ? a : b) : a + b; }
+
+// Workgroup reduction of one value per thread (all threads get the result).
+template <bool kMax>
+__device__ __forceinline__ uint32_t block_reduce(uint32_t v, uint32_t *sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = top<kMax>(v, (uint32_t)__shfl_xor((int)v, d));
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int i = 0; i < kTThreads / kWave; i++) t = top<kMax>(t, sh[i]);
+  return t;
+}
+
+// Scan (inclusive or exclusive) of 16 consecutive LDS values per thread, in
+// place, from a carry; returns the tile total (without the carry).
+template <bool kMax, bool kInclusive>
+__device__ __forceinline__ uint32_t tile_scan(uint32_t *buf, uint32_t carry, uint32_t *sh) {
+  uint32_t v[kTItems], acc = 0;
+#pragma unroll
+  for (int i = 0; i < kTItems; i++) {
+    v[i] = buf[tpad(threadIdx.x * kTItems + i)];
+    acc = top<kMax>(acc, v[i]);
+  }
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  uint32_t x = acc;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)x, d);
+    if (lane >= d) x = top<kMax>(o, x);
+  }
+  uint32_t xe = (uint32_t)__shfl_up((int)x, 1);
+  if (lane == 0) xe = 0;
+  __syncthreads();
+  if (lane == kWave - 1) sh[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < kTThreads / kWave; w++) {
+    if (w < wave) before = top<kMax>(before, sh[w]);
+    total = top<kMax>(total, sh[w]);
+  }
+  uint32_t run = top<kMax>(carry, top<kMax>(before, xe));
+#pragma unroll
+  for (int i = 0; i < kTItems; i++) {
+    const uint32_t nv = top<kMax>(run, v[i]);
+    buf[tpad(threadIdx.x * kTItems + i)] = kInclusive ? nv : run;
+    run = nv;
+  }
+  __syncthreads();
+  return total;
+}
+
+// carry over aggs[counted, tile), extending a running carry
+template <bool kMax>
+__device__ __forceinline__ uint32_t tile_carry(const uint32_t *aggs, uint32_t &counted, uint32_t tile,
+                                               uint32_t carry, uint32_t *sh) {
+  uint32_t part = 0;
+  for (uint32_t j = counted + threadIdx.x; j < tile; j += kTThreads) part = top<kMax>(part, aggs[j]);
+  counted = tile;
+  return top<kMax>(carry, block_reduce<kMax>(part, sh));
+}
+
 // Binary search: largest i in [0, n) with a[i] <= key (a sorted ascending, a[0] <= key).
 template <typename T>
 __device__ __forceinline__ uint32_t upper_index(const T *a, uint32_t n, T key) {
@@ -260,11 +334,10 @@ struct MtfWork {
   uint8_t *seglist;      // [max_blocks * kMtfSegs * 256] segment partial lists, then segment incoming lists
   uint32_t *seglen;      // [max_blocks * kMtfSegs]
   uint8_t *idx;          // [N] MTF indices
-  uint32_t *zs;          // [N]
-  uint32_t *len;         // [N]
-  uint32_t *off;         // [N+1]
+  uint32_t *zs;          // [N] zero-run segment start of each position
+  uint32_t *off;         // [N] first output symbol of each position
+  uint32_t *aggs;        // [2 * (N / kTTile + 2)] tile aggregates of the zero-run scans
   uint32_t *d_n_chunks;
-  void *scan_tmp;
 };
 void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
                  uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
