@@ -328,9 +328,17 @@ struct TileBlocks {
   const uint32_t *blk_start;
   uint32_t nb, b0, s0, e0;
   __device__ TileBlocks(const uint32_t *bs, uint32_t n, uint32_t base) : blk_start(bs), nb(n) {
-    b0 = upper_index(bs, n, base);
-    s0 = bs[b0];
-    e0 = bs[b0 + 1];
+    if (n < (uint32_t)kWave) {  // one load per lane instead of a chain of dependent ones
+      const int lane = lane_id();
+      const uint32_t mine = (uint32_t)lane <= n ? bs[lane] : 0xFFFFFFFFu;
+      b0 = (uint32_t)__popcll(ballot64((uint32_t)lane < n && mine <= base)) - 1u;
+      s0 = (uint32_t)__shfl((int)mine, (int)b0);
+      e0 = (uint32_t)__shfl((int)mine, (int)b0 + 1);
+    } else {
+      b0 = upper_index(bs, n, base);
+      s0 = bs[b0];
+      e0 = bs[b0 + 1];
+    }
   }
   // block of p (p >= the tile base), with its start and end
   __device__ __forceinline__ uint32_t find(uint32_t p, uint32_t &s, uint32_t &e) const {
@@ -347,12 +355,48 @@ struct TileBlocks {
   }
 };
 
-__device__ __forceinline__ uint32_t zrun_len(const uint8_t *idx, uint32_t p, uint32_t z, uint32_t be) {
+
+// A thread owns 16 consecutive positions of the tile (one 16-byte load of
+// indices); the bytes just before and after them come from the neighbouring
+// lanes.
+struct ZBytes {
+  uint8_t v[kTItems];
+  uint32_t before, after;  // index at p0 - 1 and p0 + 16 (0 outside [0, N))
+};
+
+__device__ __forceinline__ ZBytes load_zbytes(const uint8_t *idx, uint32_t p0, uint32_t N) {
+  ZBytes z;
+  if (p0 + kTItems <= N) {
+    const uint4 q = *(const uint4 *)(idx + p0);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) z.v[i] = (uint8_t)(w[i >> 2] >> (8 * (i & 3)));
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) z.v[i] = p0 + i < N ? idx[p0 + i] : (uint8_t)0;
+  }
+  const int lane = lane_id();
+  z.before = (uint32_t)__shfl_up((int)z.v[kTItems - 1], 1);
+  z.after = (uint32_t)__shfl_down((int)z.v[0], 1);
+  if (lane == 0) z.before = p0 > 0 && p0 - 1 < N ? idx[p0 - 1] : 0u;
+  if (lane == kWave - 1) z.after = p0 + kTItems < N ? idx[p0 + kTItems] : 0u;
+  return z;
+}
+
+// segment-start mark of position p0 + i (p0 + i < N)
+__device__ __forceinline__ uint32_t zmark(const ZBytes &z, int i, uint32_t p, uint32_t bs) {
+  const uint32_t prev = i == 0 ? z.before : z.v[i - 1];
+  return p == bs || prev != 0 ? p : 0u;
+}
+
+// symbols of position p0 + i, whose segment starts at zsp
+__device__ __forceinline__ uint32_t zlen(const ZBytes &z, int i, uint32_t p, uint32_t zsp, uint32_t be) {
+  const uint32_t next = i == kTItems - 1 ? z.after : z.v[i + 1];
   uint32_t l;
-  if (idx[p] != 0)
+  if (z.v[i] != 0)
     l = 1;
-  else if (p + 1 == be || idx[p + 1] != 0)
-    l = ndigits(p - z + 1);
+  else if (p + 1 == be || next != 0)
+    l = ndigits(p - zsp + 1);
   else
     l = 0;
   return p + 1 == be ? l + 1 : l;  // end-of-block symbol
@@ -367,14 +411,17 @@ __global__ __launch_bounds__(kTThreads) void k_z_marks(const uint8_t *idx, const
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const uint32_t base = tile * kTTile;
     const TileBlocks tb(blk_start, nb, base);
+    const uint32_t p0 = base + threadIdx.x * kTItems;
+    const ZBytes z = load_zbytes(idx, p0, N);
     uint32_t m = 0;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < kTItems; i++) {
-      const uint32_t p = base + (uint32_t)i * kTThreads + threadIdx.x;
-      if (p >= N) continue;
-      uint32_t bs, be;
-      tb.find(p, bs, be);
-      if (p == bs || idx[p - 1] != 0) m = max(m, p);
+      const uint32_t p = p0 + i;
+      if (p < N) {
+        uint32_t bs, be;
+        tb.find(p, bs, be);
+        m = max(m, zmark(z, i, p, bs));
+      }
     }
     m = block_reduce<true>(m, sh);
     if (threadIdx.x == 0) aggs[tile] = m;
@@ -390,34 +437,43 @@ __global__ __launch_bounds__(kTThreads) void k_z_runs(const uint8_t *idx, const 
   const uint32_t nt = (N + kTTile - 1) / kTTile;
   uint32_t carry = 0, counted = 0;
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
     const uint32_t base = tile * kTTile;
+    const uint32_t p0 = base + threadIdx.x * kTItems;
+    const ZBytes z = load_zbytes(idx, p0, N);  // issued before the carry's loads
     const TileBlocks tb(blk_start, nb, base);
-#pragma unroll 4
+    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+#pragma unroll
     for (int i = 0; i < kTItems; i++) {
-      const int j = i * kTThreads + threadIdx.x;
-      const uint32_t p = base + (uint32_t)j;
+      const uint32_t p = p0 + i;
       uint32_t mk = 0;
       if (p < N) {
         uint32_t bs, be;
         tb.find(p, bs, be);
-        mk = p == bs || idx[p - 1] != 0 ? p : 0u;
+        mk = zmark(z, i, p, bs);
       }
-      buf[tpad(j)] = mk;
+      buf[tpad(threadIdx.x * kTItems + i)] = mk;
     }
     __syncthreads();
     tile_scan<true, true>(buf, carry, sh);
-    uint32_t cnt = 0;
-#pragma unroll 4
+    uint32_t cnt = 0, zv[kTItems];
+#pragma unroll
     for (int i = 0; i < kTItems; i++) {
-      const int j = i * kTThreads + threadIdx.x;
-      const uint32_t p = base + (uint32_t)j;
-      if (p >= N) continue;
-      const uint32_t z = buf[tpad(j)];
-      zs[p] = z;
-      uint32_t bs, be;
-      tb.find(p, bs, be);
-      cnt += zrun_len(idx, p, z, be);
+      const uint32_t p = p0 + i;
+      zv[i] = buf[tpad(threadIdx.x * kTItems + i)];
+      if (p < N) {
+        uint32_t bs, be;
+        tb.find(p, bs, be);
+        cnt += zlen(z, i, p, zv[i], be);
+      }
+    }
+    if (p0 + kTItems <= N) {
+      uint4 *o = (uint4 *)(zs + p0);
+#pragma unroll
+      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(zv[4 * q], zv[4 * q + 1], zv[4 * q + 2], zv[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (p0 + i < N) zs[p0 + i] = zv[i];
     }
     cnt = block_reduce<false>(cnt, sh);
     if (threadIdx.x == 0) aggs_l[tile] = cnt;
@@ -436,28 +492,49 @@ __global__ __launch_bounds__(kTThreads) void k_z_offs(const uint8_t *idx, const 
   if (blockIdx.x == 0 && threadIdx.x == 0 && nt == 0) *d_n_sym = 0;
   uint32_t carry = 0, counted = 0;
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    carry = tile_carry<false>(aggs_l, counted, tile, carry, sh);
     const uint32_t base = tile * kTTile;
+    const uint32_t p0 = base + threadIdx.x * kTItems;
+    const ZBytes z = load_zbytes(idx, p0, N);  // issued before the carry's loads
     const TileBlocks tb(blk_start, nb, base);
-#pragma unroll 4
+    uint32_t zv[kTItems];
+    if (p0 + kTItems <= N) {
+      const uint4 *in = (const uint4 *)(zs + p0);
+#pragma unroll
+      for (int q = 0; q < kTItems / 4; q++) {
+        const uint4 t = in[q];
+        zv[4 * q] = t.x;
+        zv[4 * q + 1] = t.y;
+        zv[4 * q + 2] = t.z;
+        zv[4 * q + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++) zv[i] = p0 + i < N ? zs[p0 + i] : 0u;
+    }
+    carry = tile_carry<false>(aggs_l, counted, tile, carry, sh);
+#pragma unroll
     for (int i = 0; i < kTItems; i++) {
-      const int j = i * kTThreads + threadIdx.x;
-      const uint32_t p = base + (uint32_t)j;
+      const uint32_t p = p0 + i;
       uint32_t l = 0;
       if (p < N) {
         uint32_t bs, be;
         tb.find(p, bs, be);
-        l = zrun_len(idx, p, zs[p], be);
+        l = zlen(z, i, p, zv[i], be);
       }
-      buf[tpad(j)] = l;
+      buf[tpad(threadIdx.x * kTItems + i)] = l;
     }
     __syncthreads();
     const uint32_t total = tile_scan<false, false>(buf, carry, sh);
-#pragma unroll 4
-    for (int i = 0; i < kTItems; i++) {
-      const int j = i * kTThreads + threadIdx.x;
-      const uint32_t p = base + (uint32_t)j;
-      if (p < N) off[p] = buf[tpad(j)];
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) zv[i] = buf[tpad(threadIdx.x * kTItems + i)];
+    if (p0 + kTItems <= N) {
+      uint4 *o = (uint4 *)(off + p0);
+#pragma unroll
+      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(zv[4 * q], zv[4 * q + 1], zv[4 * q + 2], zv[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (p0 + i < N) off[p0 + i] = zv[i];
     }
     if (tile == nt - 1 && threadIdx.x == 0) *d_n_sym = carry + total;
     __syncthreads();
