@@ -272,8 +272,52 @@ constexpr int kRItems = kTItems;
 constexpr uint32_t kRTile = kTTile;
 constexpr uint32_t kUnresNone = 0xFFFFFFFFu;  // goffw entry of a resolved element
 
-__device__ __forceinline__ bool group_first(const uint64_t *keys, uint32_t k) {
-  return k == 0 || keys[k] != keys[k - 1];
+// 16 consecutive 32- or 64-bit values from k0 (vector loads when all are in
+// range)
+__device__ __forceinline__ void load16(const uint32_t *a, uint32_t k0, uint32_t n, uint32_t *v) {
+  if (k0 + kTItems <= n) {
+    const uint4 *q = (const uint4 *)(a + k0);
+#pragma unroll
+    for (int j = 0; j < kTItems / 4; j++) {
+      const uint4 t = q[j];
+      v[4 * j] = t.x;
+      v[4 * j + 1] = t.y;
+      v[4 * j + 2] = t.z;
+      v[4 * j + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) v[i] = k0 + i < n ? a[k0 + i] : 0u;
+  }
+}
+__device__ __forceinline__ void load16(const uint64_t *a, uint32_t k0, uint32_t n, uint64_t *v) {
+  if (k0 + kTItems <= n) {
+    const uint4 *q = (const uint4 *)(a + k0);
+#pragma unroll
+    for (int j = 0; j < kTItems / 2; j++) {
+      const uint4 t = q[j];
+      v[2 * j] = ((uint64_t)t.y << 32) | t.x;
+      v[2 * j + 1] = ((uint64_t)t.w << 32) | t.z;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) v[i] = k0 + i < n ? a[k0 + i] : 0ull;
+  }
+}
+__device__ __forceinline__ void store16(uint32_t *a, uint32_t k0, uint32_t n, const uint32_t *v) {
+  if (k0 + kTItems <= n) {
+    uint4 *q = (uint4 *)(a + k0);
+#pragma unroll
+    for (int j = 0; j < kTItems / 4; j++) q[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++)
+      if (k0 + i < n) a[k0 + i] = v[i];
+  }
+}
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src), hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, const uint32_t *slot,
@@ -281,14 +325,22 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
   __shared__ uint32_t sh[kRThreads / kWave];
   const uint32_t U = *d_u;
   const uint32_t nt = (U + kRTile - 1) / kRTile;
+  const int lane = lane_id();
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    const uint32_t base = tile * kRTile;
+    const uint32_t k0 = tile * kRTile + threadIdx.x * kRItems;
+    uint64_t key[kRItems];
+    uint32_t sl[kRItems];
+    load16(keys, k0, U, key);
+    load16(slot, k0, U, sl);
+    uint64_t before = shfl64(key[kRItems - 1], lane - 1);
+    if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
+    // slots grow along the list: the last group start of the thread has the largest mark
     uint32_t m = 0;
-#pragma unroll 4
+#pragma unroll
     for (int i = 0; i < kRItems; i++) {
-      const uint32_t k = base + (uint32_t)i * kRThreads + threadIdx.x;
-      if (k < U && group_first(keys, k)) m = max(m, slot[k]);
+      const uint64_t pk = i == 0 ? before : key[i - 1];
+      if (k0 + i < U && (k0 + i == 0 || key[i] != pk)) m = sl[i];
     }
     m = block_reduce<true>(m, sh);
     if (threadIdx.x == 0) aggs[tile] = m;
@@ -299,7 +351,9 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
 // whose block is fully compared), and for every other element its position
 // inside its group (goffw; kUnresNone for resolved ones).  Also the largest
 // group that stays unresolved (its last element knows the size: slots of a
-// group are consecutive and its rank is the first slot).
+// group are consecutive and its rank is the first slot).  A thread owns 16
+// consecutive elements (vector loads); keys next to them come from the
+// neighbouring lanes.
 __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, const uint32_t *vals,
                                                           const uint32_t *slot, const uint32_t *d_u,
                                                           const uint32_t *aggs_m, const uint32_t *blk_start,
@@ -311,39 +365,56 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, 
   const uint32_t U = *d_u, nb = *d_nb;
   const uint32_t nt = (U + kRTile - 1) / kRTile;
   const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
+  const int lane = lane_id();
   uint32_t carry = 0, counted = 0, gmax = 0;
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
     const uint32_t base = tile * kRTile;
-#pragma unroll 4
-    for (int i = 0; i < kRItems; i++) {
-      const int j = i * kRThreads + threadIdx.x;
-      const uint32_t k = base + (uint32_t)j;
-      buf[tpad(j)] = k < U && group_first(keys, k) ? slot[k] : 0u;
+    const uint32_t k0 = base + threadIdx.x * kRItems;
+    uint32_t sl[kRItems], g[kRItems], diff = 0;  // diff bit i: key i differs from key i - 1
+    bool ends;                                   // the last element's key differs from the next one
+    {
+      uint64_t key[kRItems];
+      load16(keys, k0, U, key);
+      uint64_t before = shfl64(key[kRItems - 1], lane - 1), after = shfl64(key[0], lane + 1);
+      if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
+      if (lane == kWave - 1) after = k0 + kRItems < U ? keys[k0 + kRItems] : 0ull;
+#pragma unroll
+      for (int i = 0; i < kRItems; i++) {
+        const uint64_t pk = i == 0 ? before : key[i - 1];
+        if (k0 + i == 0 || key[i] != pk) diff |= 1u << i;
+      }
+      ends = k0 + kRItems >= U || after != key[kRItems - 1];
     }
+    load16(slot, k0, U, sl);
+    load16(vals, k0, U, g);
+    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+#pragma unroll
+    for (int i = 0; i < kRItems; i++)
+      buf[tpad(threadIdx.x * kRItems + i)] = k0 + i < U && ((diff >> i) & 1u) ? sl[i] : 0u;
     __syncthreads();
     tile_scan<true, true>(buf, carry, sh);
-    uint32_t cnt = 0;
-#pragma unroll 4
+    uint32_t cnt = 0, gw[kRItems];
+#pragma unroll
     for (int i = 0; i < kRItems; i++) {
-      const int j = i * kRThreads + threadIdx.x;
-      const uint32_t k = base + (uint32_t)j;
+      const uint32_t k = k0 + i;
+      gw[i] = kUnresNone;
       if (k >= U) continue;
-      const uint32_t nr = buf[tpad(j)], g = vals[k], sl = slot[k];
-      rank[g] = nr;
-      const bool first = sl == nr;  // ranks are first slots
-      const bool last = k + 1 == U || keys[k + 1] != keys[k];
+      const uint32_t nr = buf[tpad(threadIdx.x * kRItems + i)];
+      rank[g[i]] = nr;
+      const bool first = sl[i] == nr;  // ranks are first slots
+      const bool last = k + 1 == U || (i + 1 < kRItems ? ((diff >> (i + 1)) & 1u) != 0 : ends);
       bool done = first && last;
       if (!done && any_short) {
-        const uint32_t b = block_of(blk_start, nb, g);
+        const uint32_t b = block_of(blk_start, nb, g[i]);
         done = blk_start[b + 1] - blk_start[b] <= compared;
       }
-      if (done) sa[sl] = g;  // final position; unresolved ones are written in a later round
-      const uint32_t off = sl - nr;
-      goffw[k] = done ? kUnresNone : off;
+      if (done) sa[sl[i]] = g[i];  // final position; unresolved ones are written in a later round
+      const uint32_t off = sl[i] - nr;
+      gw[i] = done ? kUnresNone : off;
       cnt += done ? 0u : 1u;
       if (!done && last) gmax = max(gmax, off + 1u);
     }
+    store16(goffw, k0, U, gw);
     cnt = block_reduce<false>(cnt, sh);
     if (threadIdx.x == 0) aggs_s[tile] = cnt;
   }
