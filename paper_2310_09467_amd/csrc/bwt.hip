@@ -62,11 +62,44 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     for (int i = threadIdx.x; i < (kRsThreads / kWave) * 256; i += kRsThreads) (&h[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)tile * TILE;
-#pragma unroll 8
-    for (int it = 0; it < ITEMS; it++) {
-      const uint64_t j = base + (uint64_t)it * kRsThreads + threadIdx.x;
-      if (j < n) atomicAdd(&h[w][(uint32_t)(keys[j] >> shift) & 255u], 1u);
+    // a thread counts ITEMS consecutive keys (vector loads) and adds each run
+    // of equal digits once; a digit shared by the whole wavefront (the block
+    // id, the mostly-zero high bytes) is added once per wavefront
+    const uint64_t j0 = (uint64_t)tile * TILE + (uint64_t)threadIdx.x * ITEMS;
+    uint32_t dig[ITEMS];
+    if (j0 + ITEMS <= n) {
+      const uint4 *q = (const uint4 *)(keys + j0);
+#pragma unroll
+      for (int i = 0; i < ITEMS / 2; i++) {
+        const uint4 t = q[i];
+        dig[2 * i] = (uint32_t)((((uint64_t)t.y << 32) | t.x) >> shift) & 255u;
+        dig[2 * i + 1] = (uint32_t)((((uint64_t)t.w << 32) | t.z) >> shift) & 255u;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) dig[i] = j0 + i < n ? (uint32_t)(keys[j0 + i] >> shift) & 255u : 256u;
+    }
+    uint32_t cur = dig[0], run = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+      if (dig[i] != cur) {
+        if (cur < 256u) atomicAdd(&h[w][cur], run);
+        cur = dig[i];
+        run = 0;
+      }
+      run++;
+    }
+    const bool valid = cur < 256u;
+    const uint64_t vm = ballot64(valid);
+    if (vm) {  // uniform: every lane of the wavefront takes the same branches below
+      const uint32_t dv = (uint32_t)__builtin_amdgcn_readlane((int)cur, (int)__builtin_ctzll(vm));
+      if (__all(!valid || cur == dv)) {
+        uint32_t r = valid ? run : 0u;
+        for (int dd = kWave / 2; dd > 0; dd >>= 1) r += (uint32_t)__shfl_xor((int)r, dd);
+        if (lane_id() == 0) atomicAdd(&h[w][dv], r);
+      } else if (valid) {
+        atomicAdd(&h[w][cur], run);
+      }
     }
     __syncthreads();
     const uint32_t d = threadIdx.x;
