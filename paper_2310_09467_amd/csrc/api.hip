@@ -146,6 +146,10 @@ struct pcbz_ctx {
   uint64_t gen = 1;  // bumped whenever a buffer a graph refers to is reallocated
   hipStream_t gstream = nullptr;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  // a second stream for work off the critical path (block CRCs during the
+  // suffix sort, header bits during the symbol-length scan), joined by events
+  hipStream_t side = nullptr;
+  hipEvent_t fev[3] = {nullptr, nullptr, nullptr};
   std::vector<pcbz::GraphEntry> graphs;
   std::vector<pcbz::TuneRec> tune;
   std::string tune_path;
@@ -675,8 +679,14 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, s);
   launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
               w.blk_raw_start, w.blk_rle_start, w.crc_chunk_base, w.ctr + 1, w.ctr + 2, s);
+  // the block CRCs run beside the suffix sort (only the header bits need them)
+  hipStream_t cs = ctx->side ? ctx->side : s;
+  if (ctx->side) {
+    HIPCHK(ctx, hipEventRecord(ctx->fev[0], s));
+    HIPCHK(ctx, hipStreamWaitEvent(cs, ctx->fev[0], 0));
+  }
   launch_crc2(w.chosen, N, w.blocks, w.ctr + 1, w.max_blocks, w.blk_raw_start, ctx->d_xchunk, ctx->d_xbyte,
-              ctx->d_xpow2, w.crc_acc, s);
+              ctx->d_xpow2, w.crc_acc, cs);
   uint32_t nb = w.max_blocks, nrle = w.n_rle_max;
   const uint32_t *d_nrle = w.r1off + N;
   if (eager) {
@@ -706,9 +716,17 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   const uint32_t max_words =
       (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)max_sym * 9 / 8 + (uint64_t)nb * 20600) / 4 + nb);
   trace_stage("pack");
-  launch_pack2(w.ctr + 1, nb, w.blocks, w.codes, w.mw.used, w.sel, w.lens, w.code_words, w.sym, w.ctr + 5, max_sym,
-               w.prefix, w.sym_bits, w.sym_off, w.blk_sym_start, w.scan_tmp, w.frames, (uint32_t)P.frames.size(),
-               w.bands, w.choice, w.band_len, w.frame_len, w.word_start, w.ctr + 7, max_words, s);
+  // header bits on the side stream (after the CRCs), beside the symbol lengths
+  if (ctx->side) {
+    HIPCHK(ctx, hipEventRecord(ctx->fev[1], s));
+    HIPCHK(ctx, hipStreamWaitEvent(cs, ctx->fev[1], 0));
+  }
+  launch_pack_prefix(w.ctr + 1, nb, w.blocks, w.codes, w.mw.used, w.sel, w.lens, w.prefix, cs);
+  if (ctx->side) HIPCHK(ctx, hipEventRecord(ctx->fev[2], cs));
+  launch_pack2(w.ctr + 1, nb, w.blocks, w.codes, w.sel, w.lens, w.code_words, w.sym, w.ctr + 5, max_sym, w.prefix,
+               w.sym_bits, w.sym_off, w.blk_sym_start, w.scan_tmp, w.frames, (uint32_t)P.frames.size(), w.bands,
+               w.choice, w.band_len, w.frame_len, w.word_start, w.ctr + 7, max_words, ctx->side ? ctx->fev[2] : nullptr,
+               s);
   trace_stage(nullptr);
   return PCBZ_OK;
 }
@@ -991,6 +1009,14 @@ int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
     return PCBZ_EDEVICE;
   }
   for (hipEvent_t &e : c->ev) (void)hipEventCreate(&e);
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
+  for (hipEvent_t &e : c->fev)
+    if (c->side && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  for (hipEvent_t e : c->fev)
+    if (!e && c->side) {  // without its events the side stream is not used
+      (void)hipStreamDestroy(c->side);
+      c->side = nullptr;
+    }
   const char *tp = getenv("PCBZ_TUNE_CACHE");
   if (tp) c->tune_path = tp;
   const char *ri = getenv("PCBZ_RADIX_ITEMS");  // radix tile of eager calls: 8 or 16
@@ -1011,6 +1037,14 @@ void pcbz_destroy(pcbz_ctx *c) {
   if (c->d_xchunk) (void)hipFree(c->d_xchunk);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_small) (void)hipHostFree(c->h_small);
+  for (pcbz::GraphEntry &g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->fev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  if (c->side) (void)hipStreamDestroy(c->side);
   delete c;
 }
 

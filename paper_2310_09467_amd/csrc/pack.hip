@@ -381,20 +381,26 @@ __global__ __launch_bounds__(256) void k_header(const FrameOut *frames, const ui
 
 }  // namespace
 
-void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
-                  const uint32_t *used, const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words,
-                  const uint16_t *sym, const uint32_t *d_n_sym, uint32_t max_sym, uint32_t *prefix,
-                  uint32_t *sym_bits, uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp,
-                  const FrameOut *frames, uint32_t n_frames, const BandDesc *bands, const uint8_t *choice,
-                  uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words,
-                  uint32_t max_words, hipStream_t s) {
+void launch_pack_prefix(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
+                        const uint32_t *used, const uint8_t *sel, const uint8_t *lens, uint32_t *prefix,
+                        hipStream_t s) {
   PCBZ_LAUNCH(k_prefix, dim3(max_blocks), dim3(256), 0, s, d_nb, blocks, codes, used, sel, lens, prefix);
+}
+
+void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
+                  const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words, const uint16_t *sym,
+                  const uint32_t *d_n_sym, uint32_t max_sym, const uint32_t *prefix, uint32_t *sym_bits,
+                  uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp, const FrameOut *frames,
+                  uint32_t n_frames, const BandDesc *bands, const uint8_t *choice, uint32_t *band_len,
+                  uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
+                  hipEvent_t prefix_ready, hipStream_t s) {
   PCBZ_LAUNCH(k_blk_sym_start, dim3((max_blocks + 256) / 256), dim3(256), 0, s, d_nb, codes, blk_sym_start);
   const uint32_t g = std::min<uint32_t>((max_sym + 255) / 256 + 1, 16384);
   PCBZ_LAUNCH(k_sym_bits, dim3(g), dim3(256), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
                      sym_bits);
   // exclusive scan over n_sym + 1 entries so that sym_off[n_sym] is the total
   scan_exclusive_u32(sym_bits, sym_off, nullptr, max_sym + 1, scan_tmp, nullptr, s);
+  if (prefix_ready) (void)hipStreamWaitEvent(s, prefix_ready, 0);
   PCBZ_LAUNCH(k_layout, dim3(1), dim3(64), 0, s, d_nb, blocks, codes, sym_off, blk_sym_start, frames, n_frames,
                      bands, band_len, frame_len, word_start, d_words);
   const uint32_t gw = std::min<uint32_t>((max_words + 255) / 256 + 1, 16384);

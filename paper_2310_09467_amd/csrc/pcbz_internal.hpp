@@ -349,13 +349,21 @@ void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks
                   uint32_t *d_n_groups, uint8_t *sel, uint8_t *lens, uint32_t *code_words, hipStream_t s);
 
 // pack.hip
+// Header bits of every block (the stream header, used-byte map, selectors
+// and code lengths) into prefix; sets codes[b].prefix_bits.
+void launch_pack_prefix(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
+                        const uint32_t *used, const uint8_t *sel, const uint8_t *lens, uint32_t *prefix,
+                        hipStream_t s);
+// Symbol bit lengths and offsets, stream layout, the words of every stream
+// and the container headers.  The layout waits for prefix_ready (when given:
+// the event recorded after launch_pack_prefix on another stream).
 void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
-                  const uint32_t *used, const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words,
-                  const uint16_t *sym, const uint32_t *d_n_sym, uint32_t max_sym, uint32_t *prefix,
-                  uint32_t *sym_bits, uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp,
-                  const FrameOut *frames, uint32_t n_frames, const BandDesc *bands, const uint8_t *choice,
-                  uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words,
-                  uint32_t max_words, hipStream_t s);
+                  const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words, const uint16_t *sym,
+                  const uint32_t *d_n_sym, uint32_t max_sym, const uint32_t *prefix, uint32_t *sym_bits,
+                  uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp, const FrameOut *frames,
+                  uint32_t n_frames, const BandDesc *bands, const uint8_t *choice, uint32_t *band_len,
+                  uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
+                  hipEvent_t prefix_ready, hipStream_t s);
 
 // ---------------------------------------------------------------- learned selector
 }  // namespace pcbz
