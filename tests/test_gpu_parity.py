@@ -210,3 +210,31 @@ def test_group_sort_limit(ctx, orc, capfd, monkeypatch, w, largest):
     check_compress(ctx, orc, f, level=9, mask=0x7, forced=np.zeros(nb, np.uint8))
     err = capfd.readouterr().err
     assert f"largest group={largest}" in err
+
+
+def test_many_blocks_one_frame(ctx, orc):
+    """2040x2040 at level 1 (100 kB blocks): more than 64 blocks in one call,
+    so the block lookups take their searched path instead of the per-lane
+    table."""
+    from paper_2310_09467_amd import synth
+
+    f = synth.config2_frame(100.0)
+    _say("c2 level 1")
+    blob = check_compress(ctx, orc, f, level=1, mask=0x7)
+    assert ctx.last_stats()["blocks"] > 64
+
+
+def test_many_tiny_frames_in_one_batch(ctx, orc):
+    """Eighty 30x30 frames in one call: blocks of about 1.8 kB, so a 4096-entry
+    tile of every scan and sort spans several blocks."""
+    from paper_2310_09467_amd import synth
+
+    frames, params = [], []
+    for i in range(80):
+        f, _ = synth.beads_frame(30, 30, 3, 50.0 + 10 * i, 300 + i)
+        frames.append(f)
+        params.append((15, 9 if i % 2 else 1, 0x7))
+    _say("batch of 80 tiny frames")
+    blobs = ctx.compress_batch(frames, params=params)
+    for f, (p, lv, m), blob in zip(frames, params, blobs):
+        assert blob == orc.compress(f, None, p, lv, m)[0]
