@@ -241,10 +241,12 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
 // ranks x (two halves, each <= 255) after the symbol at rank r moves to front:
 // t = x - r per half (wrapping below r), lt = t >> 15 (1 where x < r),
 // ne = min(t, 1) (1 where x != r), result (x + lt) * ne.  Written as packed
-// 16-bit instructions: the compiler otherwise splits the halves apart.
-__device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r2) {
+// 16-bit instructions: the compiler otherwise splits the halves apart.  r is
+// the low half of the scalar operand (both halves subtract it; its high
+// half is ignored).
+__device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r) {
   uint32_t t, lt, y, ne, out;
-  asm("v_pk_sub_u16 %0, %1, %2" : "=v"(t) : "v"(x), "s"(r2));
+  asm("v_pk_sub_u16 %0, %1, %2 op_sel_hi:[1,0]" : "=v"(t) : "v"(x), "s"(r));
   asm("v_pk_lshrrev_b16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(lt) : "v"(t));
   asm("v_pk_add_u16 %0, %1, %2" : "=v"(y) : "v"(x), "v"(lt));
   asm("v_pk_min_u16 %0, %1, 1 op_sel_hi:[1,0]" : "=v"(ne) : "v"(t));
@@ -299,10 +301,11 @@ __global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t
       const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
       const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)R1, (int)sl);
       const uint32_t word = (v & 128u) ? a1 : a0;
-      const uint32_t r = (v & 64u) ? (word >> 16) : (word & 0xFFFFu);  // the move-to-front index
-      const uint32_t r2 = r * 0x10001u;
-      R0 = mtf_ranks(R0, r2);
-      R1 = mtf_ranks(R1, r2);
+      // the move-to-front index in the low 16 bits (the high bits are never read:
+      // the rank update takes the low half, the index is stored as a byte)
+      const uint32_t r = (v & 64u) ? (word >> 16) : word;
+      R0 = mtf_ranks(R0, r);
+      R1 = mtf_ranks(R1, r);
       // lane k keeps its index (one SGPR operand per instruction: the lane goes through m0)
       asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(r), "s"(k) : "m0");
     }
