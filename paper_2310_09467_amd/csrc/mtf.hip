@@ -254,30 +254,49 @@ __device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r) {
   return out;
 }
 
-__global__ __launch_bounds__(64) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
-                                                const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                const uint32_t *d_nb, const uint8_t *seq, const uint8_t *inlist,
-                                                uint8_t *idx) {
-  __shared__ uint8_t rk[256];
-  __shared__ uint8_t smap[256];
-  __shared__ uint8_t ssym[kChunk];
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
-  uint32_t b, p0, p1, bs, be;
-  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+constexpr int kRunWaves = 4;  // chunks per workgroup, one per wavefront
+
+__global__ __launch_bounds__(64 * kRunWaves) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
+                                                            const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                            const uint32_t *d_nb, const uint8_t *seq,
+                                                            const uint8_t *inlist, uint8_t *idx) {
+  __shared__ uint8_t rk_all[kRunWaves][256];
+  __shared__ uint8_t smap_all[kRunWaves][256];
+  __shared__ uint8_t ssym_all[kRunWaves][kChunk];
+  const uint32_t wv = threadIdx.x / kWave;
+  uint8_t *rk = rk_all[wv], *smap = smap_all[wv], *ssym = ssym_all[wv];
+  const uint32_t c = blockIdx.x * kRunWaves + wv;
+  const bool have = c < *d_n_chunks;  // every wavefront reaches the barriers below
+  uint32_t b = 0, p0 = 0, p1 = 0, bs, be;
+  if (have) chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   const uint32_t lane = (uint32_t)lane_id();
-  const uint8_t *il = inlist + (size_t)c * 256;
-  for (uint32_t e = lane; e < 256; e += 64) {
-    rk[il[e]] = (uint8_t)e;
-    smap[e] = seq[b * 256 + e];
-  }
-  // the chunk's bytes, staged up front (many loads in flight) so that the
-  // replay never waits on global memory
   const uint32_t m = p1 - p0;
-  stage_to_lds(ssym, L + p0, m);
+  if (have) {
+    const uint8_t *il = inlist + (size_t)c * 256;
+    for (uint32_t e = lane; e < 256; e += 64) {
+      rk[il[e]] = (uint8_t)e;
+      smap[e] = seq[b * 256 + e];
+    }
+    // the chunk's bytes, staged up front (many loads in flight) so that the
+    // replay never waits on global memory
+    for (uint32_t base = 0; base < m; base += 64 * 16) {
+      uint8_t v[16];
+#pragma unroll
+      for (uint32_t k = 0; k < 16; k++) {
+        const uint32_t i = base + k * 64 + lane;
+        v[k] = i < m ? L[p0 + i] : (uint8_t)0;
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < 16; k++) {
+        const uint32_t i = base + k * 64 + lane;
+        if (i < m) ssym[i] = v[k];
+      }
+    }
+  }
   __syncthreads();
   for (uint32_t i = lane; i < m; i += 64) ssym[i] = smap[ssym[i]];
   __syncthreads();
+  if (!have) return;
   uint32_t R0 = (uint32_t)rk[lane] | ((uint32_t)rk[lane + 64] << 16);
   uint32_t R1 = (uint32_t)rk[lane + 128] | ((uint32_t)rk[lane + 192] << 16);
   // A symbol equal to the one before it has index 0 and leaves the list as
@@ -604,7 +623,8 @@ void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32
   PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(256), 0, s, d_nb, w.seglist, w.seglen);
   PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
               w.inlist);
-  PCBZ_LAUNCH(k_mtf_run, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
+  PCBZ_LAUNCH(k_mtf_run, dim3((max_chunks + kRunWaves - 1) / kRunWaves), dim3(64 * kRunWaves), 0, s, L, cb,
+              w.d_n_chunks, blk_start, d_nb, w.seq,
                      w.inlist, w.idx);
   const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (N + kTTile - 1) / kTTile));
   uint32_t *aggs_m = w.aggs, *aggs_l = w.aggs + (N / kTTile + 2);
