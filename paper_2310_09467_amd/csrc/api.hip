@@ -999,12 +999,7 @@ int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
   c->device = hip_device;
   c->budget = hbm_budget_bytes;
   if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
-    for (pcbz::GraphEntry &g : c->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  for (hipEvent_t e : c->ev)
-    if (e) (void)hipEventDestroy(e);
-  if (c->gstream) (void)hipStreamDestroy(c->gstream);
-  delete c;
+    delete c;
     *out = nullptr;
     return PCBZ_EDEVICE;
   }
