@@ -194,9 +194,11 @@ int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf);
  * them were judged (fell below min_conf). */
 int pcbz_selector_stats(const pcbz_ctx *ctx, uint32_t *n_bands, uint32_t *n_judged);
 
-/* on = 0 makes pcbz_compress_batch run eagerly instead of capturing and
- * replaying a graph per batch shape (useful when shapes rarely repeat).
- * Output bytes are the same either way. */
+/* Batch execution mode: on = 1 (the default) lets the autotuner compare, on
+ * a shape's first call, an eager call with a replay of a captured graph per
+ * candidate schedule and keep the fastest; on = 2 always replays graphs;
+ * on = 0 always runs eagerly (useful when shapes rarely repeat).  Output
+ * bytes are the same in every mode; other values give PCBZ_EINVAL. */
 int pcbz_set_graphs(pcbz_ctx *ctx, int on);
 
 /* ------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -157,7 +158,7 @@ struct pcbz_ctx {
   // learned arrangement selector (optional): confident bands skip the judge
   pcbz_selector *sel = nullptr;
   float min_conf = 1.f;
-  bool use_graphs = true;  // pcbz_compress_batch replays captured graphs
+  int use_graphs = 1;  // pcbz_compress_batch: 0 eager, 1 graphs where faster, 2 graphs
   uint32_t last_sel_bands = 0, last_sel_fallback = 0;
 };
 
@@ -568,7 +569,7 @@ void load_tuning(pcbz_ctx *ctx) {
       r.key = key;
       r.ms = ms;
       r.seg_mask = seg;
-      if ((r.items == 8 || r.items == 16) && r.rounds > 0 && r.rounds < 64) ctx->tune.push_back(r);
+      if ((r.items == 0 || r.items == 8 || r.items == 16) && r.rounds > 0 && r.rounds < 64) ctx->tune.push_back(r);
     }
   }
   fclose(f);
@@ -896,10 +897,12 @@ int launch_graph(pcbz_ctx *ctx, GraphEntry *g, hipStream_t s, float *ms) {
 
 // Batched compression through a captured graph per batch shape.  The first
 // call of a shape runs eagerly (to learn the round count and the reference
-// lengths), then the autotuner captures one graph per candidate schedule,
-// times a replay of each and keeps the fastest; later calls replay it.  If a
-// replay ends with unresolved rotations (data needing more rounds than the
-// tuned budget), the call is redone eagerly and the budget raised.
+// lengths), then the autotuner times a second eager call and one replay of a
+// captured graph per candidate schedule (host clock, read-backs included)
+// and keeps the fastest: later calls replay that graph, or run eagerly when
+// the eager call won (unless graphs are forced).  If a replay ends with
+// unresolved rotations (data needing more rounds than the tuned budget), the
+// call is redone eagerly and the budget raised.
 int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, std::vector<size_t> &lens) {
   const std::string key = shape_key(ctx, fin);
   TuneRec *rec = nullptr;
@@ -913,13 +916,20 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
     r.key = key;
     r.rounds = (int)ctx->last_rounds + 1;
     r.seg_mask = seg_schedule(ctx);
-    r.items = 16;
-    r.ms = 0.0;
+    const auto ms_since = [](std::chrono::steady_clock::time_point t) {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+    };
+    // the eager call is a candidate too (items 0)
+    std::vector<size_t> le;
+    auto t0 = std::chrono::steady_clock::now();
+    if ((st = run_compress(ctx, fin, s, le, {}))) return st;
+    r.items = 0;
+    r.ms = ms_since(t0);
+    double best = ctx->use_graphs == 2 ? 1e30 : r.ms;
     Plan P;
     Work w{};
     if ((st = prepare(ctx, fin, P, w))) return st;
     std::vector<UploadItem> items;
-    double best = 1e30;
     const int choices[2] = {8, 16};
     for (int c : choices) {
       Tuning tu;
@@ -929,12 +939,15 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
       if ((st = stage_plan(ctx, P, w, s, items))) return st;
       GraphEntry *g = nullptr;
       if ((st = capture(ctx, P, w, items, key, tu, &g))) return st;
-      float ms = 0.f;
-      if ((st = launch_graph(ctx, g, s, nullptr))) return st;
-      if ((st = launch_graph(ctx, g, s, &ms))) return st;
       std::vector<size_t> l2;
       uint32_t ctr[16];
+      if ((st = launch_graph(ctx, g, s, nullptr))) return st;  // warm
       if ((st = read_results(ctx, P, w, s, l2, ctr))) return st;
+      t0 = std::chrono::steady_clock::now();
+      if ((st = stage_plan(ctx, P, w, s, items))) return st;
+      if ((st = launch_graph(ctx, g, s, nullptr))) return st;
+      if ((st = read_results(ctx, P, w, s, l2, ctr))) return st;
+      const double ms = ms_since(t0);
       if (ctr[9] != 0 || l2 != lens) continue;  // schedule did not reproduce the eager result
       if (ms < best) {
         best = ms;
@@ -946,6 +959,7 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
     save_tuning(ctx);
     return PCBZ_OK;  // lens from the eager run
   }
+  if (rec->items == 0) return run_compress(ctx, fin, s, lens, {});  // the eager call was faster
   Plan P;
   Work w{};
   int st = prepare(ctx, fin, P, w);
@@ -1196,7 +1210,8 @@ int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf) {
 
 int pcbz_set_graphs(pcbz_ctx *ctx, int on) {
   if (!ctx) return PCBZ_EINVAL;
-  ctx->use_graphs = on != 0;
+  if (on < 0 || on > 2) return fail(ctx, PCBZ_EINVAL, "graph mode must be 0, 1 or 2");
+  ctx->use_graphs = on;
   return PCBZ_OK;
 }
 

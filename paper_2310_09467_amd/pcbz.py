@@ -337,8 +337,9 @@ class Context:
         self._sel = sel  # keeps the selector alive while it is set
 
     def set_graphs(self, on=True):
-        """pcbz_compress_batch: replay captured graphs (True) or run eagerly."""
-        st = load().pcbz_set_graphs(self._h, 1 if on else 0)
+        """pcbz_compress_batch mode: True / 1 = graphs where the autotuner finds
+        them faster than eager calls, 2 = always graphs, False / 0 = eager."""
+        st = load().pcbz_set_graphs(self._h, int(on))
         if st:
             self._err(st, "set_graphs")
 

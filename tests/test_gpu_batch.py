@@ -33,6 +33,7 @@ def test_graph_replays_equal_single_frames(orc, tmp_path):
         ctx = pcbz.Context(0)
     finally:
         del os.environ["PCBZ_TUNE_CACHE"]
+    ctx.set_graphs(2)  # replay graphs even where an eager call would be faster
     frames, prevs, params = _batch()
     ref = [orc.compress(f, p, pp, lv, m)[0] for f, p, (pp, lv, m) in zip(frames, prevs, params)]
     for rep in range(4):  # first call tunes (eager + captures), later calls replay the graph
@@ -50,6 +51,7 @@ def test_forced_choices_in_batch(orc):
     from paper_2310_09467_amd import pcbz
 
     ctx = pcbz.Context(0)
+    ctx.set_graphs(2)  # replay graphs even where an eager call would be faster
     frames, prevs, params = _batch()
     rng = np.random.default_rng(5)
     forced = []
@@ -94,6 +96,7 @@ def test_graph_falls_back_when_a_group_is_too_large(orc, tmp_path):
         ctx = pcbz.Context(0)
     finally:
         del os.environ["PCBZ_TUNE_CACHE"]
+    ctx.set_graphs(2)  # replay graphs even where an eager call would be faster
     h, w = 300, 345
     noisy, _ = synth.beads_frame(h, w, 40, 200.0, 11)
     rng = np.random.default_rng(3)
@@ -107,4 +110,21 @@ def test_graph_falls_back_when_a_group_is_too_large(orc, tmp_path):
         print("call", rep, name, flush=True)
         f = noisy if name == "noisy" else periodic
         assert ctx.compress_batch([f], None, [(15, 9, 0x7)], forced=raster) == [want[name]]
+    ctx.close()
+
+
+def test_batch_modes_agree(orc):
+    """Eager, autotuned and always-graph batch modes give the same bytes;
+    other mode values are refused."""
+    from paper_2310_09467_amd import pcbz
+
+    frames, prevs, params = _batch()
+    ref = [orc.compress(f, p, pp, lv, m)[0] for f, p, (pp, lv, m) in zip(frames, prevs, params)]
+    ctx = pcbz.Context(0)
+    for mode in (0, 1, 2, 1):
+        ctx.set_graphs(mode)
+        for _ in range(2):
+            assert ctx.compress_batch(frames, prevs, params) == ref
+    with pytest.raises(pcbz.PcbzError):
+        ctx.set_graphs(3)
     ctx.close()

@@ -173,12 +173,14 @@ def test_selector_in_batch_graph(env):
     frames = [f for f, _, _ in _frames()]
     params = [(15, 1, 0x7), (15, 1, 0x7), (15, 2, 0x7)]
     try:
+        ctx.set_graphs(2)  # replay graphs even where an eager call would be faster
         ctx.set_selector(sel, 0.6)
         first = ctx.compress_batch(frames, None, params)
         for _ in range(3):
             again = ctx.compress_batch(frames, None, params)
             assert again == first
         ctx.set_selector(None)
+        ctx.set_graphs(1)
         for blob, frame, (p, lv, m) in zip(first, frames, params):
             # expected ids: the prediction where it is confident, the judgement elsewhere
             logits = sel.forward(ctx.features(frame, None, p, lv, m)).cpu().numpy()
