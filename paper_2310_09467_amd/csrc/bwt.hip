@@ -214,17 +214,24 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
     lstart[d0] = before + incl - cnt;
     run[d0] = before + incl - cnt;
     __syncthreads();
+    // all ITEMS rows are loaded before the first barrier, so the loads of a
+    // tile overlap instead of each row waiting for the previous one
+    uint64_t tkey[ITEMS];
+    uint32_t tval[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) {
+      const uint32_t li = (uint32_t)it * kRsThreads + threadIdx.x;
+      tkey[it] = li < tn ? keys_in[base + li] : 0ull;
+      tval[it] = li < tn ? vals_in[base + li] : 0u;
+    }
     // stable local ranks, ITEMS rows of 256 elements in index order
+#pragma unroll
     for (int it = 0; it < ITEMS; it++) {
       const uint32_t li = (uint32_t)it * kRsThreads + threadIdx.x;
       const bool valid = li < tn;
-      uint64_t key = 0;
-      uint32_t val = 0, d = 0;
-      if (valid) {
-        key = keys_in[base + li];
-        val = vals_in[base + li];
-        d = (uint32_t)(key >> shift) & 255u;
-      }
+      const uint64_t key = tkey[it];
+      const uint32_t val = tval[it];
+      const uint32_t d = valid ? (uint32_t)(key >> shift) & 255u : 0u;
       const uint64_t peers = match_any8(d, ballot64(valid));
       const uint32_t rank = (uint32_t)__popcll(peers & lt);
       if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
