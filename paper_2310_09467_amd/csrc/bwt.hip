@@ -165,7 +165,6 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
   __shared__ uint32_t sval[TILE];
   __shared__ uint32_t gbase[256];   // global position of each digit's run in this tile
   __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
-  __shared__ uint32_t run[256];     // running fill of each digit's run
   __shared__ uint32_t wcnt[kRsThreads / kWave][256];
   __shared__ uint32_t wsum[kRsThreads / kWave];
   const uint32_t n = dev_n(d_n, n_max);
@@ -193,6 +192,17 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const uint64_t base = (uint64_t)tile * TILE;
     const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - base);
+    // wavefront w holds the tile's elements [w * ITEMS * 64, (w + 1) * ITEMS * 64)
+    // as ITEMS rows of 64, all loaded before the first barrier
+    const uint32_t wfirst = (uint32_t)w * (kWave * ITEMS);
+    uint64_t tkey[ITEMS];
+    uint32_t tval[ITEMS], trank[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) {
+      const uint32_t li = wfirst + (uint32_t)it * kWave + lane;
+      tkey[it] = li < tn ? keys_in[base + li] : 0ull;
+      tval[it] = li < tn ? vals_in[base + li] : 0u;
+    }
     // tile-local digit counts follow from the row-scanned table: the next
     // entry of the digit's row is the successor of (digit, tile)
     const size_t at = (size_t)d0 * nt + tile;
@@ -211,48 +221,41 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
     __syncthreads();
     uint32_t before = 0;
     for (int k = 0; k < w; k++) before += wsum[k];
-    lstart[d0] = before + incl - cnt;
-    run[d0] = before + incl - cnt;
-    __syncthreads();
-    // all ITEMS rows are loaded before the first barrier, so the loads of a
-    // tile overlap instead of each row waiting for the previous one
-    uint64_t tkey[ITEMS];
-    uint32_t tval[ITEMS];
+    const uint32_t lfirst = before + incl - cnt;
+    lstart[d0] = lfirst;
+    // stable rank of each element among its wavefront's elements of the same
+    // digit; only this wavefront touches its counter row, so the rows need no
+    // barrier between them
 #pragma unroll
     for (int it = 0; it < ITEMS; it++) {
-      const uint32_t li = (uint32_t)it * kRsThreads + threadIdx.x;
-      tkey[it] = li < tn ? keys_in[base + li] : 0ull;
-      tval[it] = li < tn ? vals_in[base + li] : 0u;
-    }
-    // stable local ranks, ITEMS rows of 256 elements in index order
-#pragma unroll
-    for (int it = 0; it < ITEMS; it++) {
-      const uint32_t li = (uint32_t)it * kRsThreads + threadIdx.x;
-      const bool valid = li < tn;
-      const uint64_t key = tkey[it];
-      const uint32_t val = tval[it];
-      const uint32_t d = valid ? (uint32_t)(key >> shift) & 255u : 0u;
+      const bool valid = wfirst + (uint32_t)it * kWave + lane < tn;
+      const uint32_t d = valid ? (uint32_t)(tkey[it] >> shift) & 255u : 0u;
       const uint64_t peers = match_any8(d, ballot64(valid));
-      const uint32_t rank = (uint32_t)__popcll(peers & lt);
-      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = run[d] + rank;
-        for (int k = 0; k < w; k++) pos += wcnt[k][d];
-        skey[pos] = key;
-        sval[pos] = val;
-      }
-      __syncthreads();
-      {
-        uint32_t add = 0;
-        for (int k = 0; k < kRsThreads / kWave; k++) {
-          add += wcnt[k][d0];
-          wcnt[k][d0] = 0;
-        }
-        run[d0] += add;
-      }
-      __syncthreads();
+      const uint32_t seen = valid ? wcnt[w][d] : 0u;
+      trank[it] = seen + (uint32_t)__popcll(peers & lt);
+      if (valid && (peers & lt) == 0) wcnt[w][d] = seen + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    // a wavefront's run of digit d starts after the tile's earlier digits and
+    // after the earlier wavefronts' elements of digit d
+    {
+      uint32_t acc = lfirst;
+      for (int k = 0; k < kRsThreads / kWave; k++) {
+        const uint32_t c = wcnt[k][d0];
+        wcnt[k][d0] = acc;
+        acc += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; it++) {
+      if (wfirst + (uint32_t)it * kWave + lane < tn) {
+        const uint32_t pos = wcnt[w][(uint32_t)(tkey[it] >> shift) & 255u] + trank[it];
+        skey[pos] = tkey[it];
+        sval[pos] = tval[it];
+      }
+    }
+    __syncthreads();
     // each digit's run is contiguous in LDS and in the output
     for (uint32_t i = threadIdx.x; i < tn; i += kRsThreads) {
       const uint64_t key = skey[i];
