@@ -87,15 +87,21 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 __device__ __forceinline__ uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
 
-// Lanes of `active` whose 8-bit value equals this lane's value.
+// Lanes of `active` whose 8-bit value equals this lane's value: for each
+// bit, the ballot of that bit where this lane's bit is set, its complement
+// where it is clear, i.e. ~(ballot ^ t) with t = the bit spread over a word
+// (one xnor-and per 32-bit half instead of a per-lane select of 64-bit masks).
 __device__ __forceinline__ uint64_t match_any8(uint32_t v, uint64_t active) {
-  uint64_t m = active;
+  uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
 #pragma unroll
   for (int b = 0; b < 8; b++) {
-    uint64_t bal = ballot64((v >> b) & 1u);
-    m &= ((v >> b) & 1u) ? bal : ~bal;
+    uint32_t t = (uint32_t)((int32_t)(v << (31 - b)) >> 31);
+    asm volatile("" : "+v"(t));  // the ballot compares t itself (no second shift)
+    const uint64_t bal = ballot64(t != 0u);
+    lo &= ~((uint32_t)bal ^ t);
+    hi &= ~((uint32_t)(bal >> 32) ^ t);
   }
-  return m;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) {
