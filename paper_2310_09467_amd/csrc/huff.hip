@@ -105,7 +105,16 @@ __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym,
   const uint32_t g0 = blockIdx.x * kSelGroups;
   if (g0 >= ngroups) return;
   for (int i = threadIdx.x; i < kMaxGroups * kMaxAlpha; i += kSelThreads) tf[i] = 0;
-  const uint32_t b0 = upper_index(group_base, nb, g0);
+  // block of a group: the number of blocks b in [1, nb) with
+  // group_base[b] <= group; with fewer than 64 blocks every lane holds one
+  // group base and a ballot counts them (one load instead of a search)
+  const bool lane_tab = nb < (uint32_t)kWave;
+  const int lane = lane_id();
+  const uint32_t gbl = lane_tab && lane >= 1 && (uint32_t)lane < nb ? group_base[lane] : 0xFFFFFFFFu;
+  auto block_of_group = [&](uint32_t grp) -> uint32_t {
+    return lane_tab ? (uint32_t)__popcll(ballot64(gbl <= grp)) : upper_index(group_base, nb, grp);
+  };
+  const uint32_t b0 = block_of_group(g0);
   const BlockCode C0 = codes[b0];
   {
     const uint8_t *cst = cost + (size_t)b0 * kMaxGroups * kMaxAlpha;
@@ -120,7 +129,7 @@ __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym,
   uint32_t end_sym;
   {
     const uint32_t gl = min(g0 + (uint32_t)kSelGroups, ngroups) - 1u;
-    const uint32_t bl = upper_index(group_base, nb, gl);
+    const uint32_t bl = block_of_group(gl);
     const BlockCode CL = codes[bl];
     end_sym = min(CL.sym_start + (gl - group_base[bl]) * kGroupSize + kGroupSize, CL.sym_start + CL.n_mtf);
   }
@@ -130,8 +139,17 @@ __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym,
   const uint32_t b0_end = group_base[b0 + 1];
   // every lane of a group takes the same branches (the group index decides them)
   const bool valid = gi < ngroups;
-  const uint32_t b = !valid || gi < b0_end ? b0 : upper_index(group_base, nb, gi);
-  const BlockCode C = codes[b];
+  uint32_t b = b0;
+  if (valid && gi >= b0_end) {  // a group past the workgroup's first block (per lane)
+    if (lane_tab) {
+      b = 0;
+      for (uint32_t j = 1; j < nb; j++) b += gi >= (uint32_t)__builtin_amdgcn_readlane((int)gbl, (int)j) ? 1u : 0u;
+    } else {
+      b = upper_index(group_base, nb, gi);
+    }
+  }
+  BlockCode C = C0;
+  if (b != b0) C = codes[b];
   const uint32_t j = valid ? gi - group_base[b] : 0u;
   const uint32_t lo = C.sym_start + j * kGroupSize;
   const uint32_t hi = valid ? min(C.sym_start + C.n_mtf, lo + kGroupSize) : lo;
