@@ -274,23 +274,67 @@ __device__ __forceinline__ uint32_t block_of(const uint32_t *blk_start, uint32_t
 }
 
 // key = (block, the first `nbytes` bytes of the rotation, cyclic), the block
-// in the bits above 8 * nbytes
+// in the bits above 8 * nbytes.  A thread builds 8 consecutive keys: when
+// their windows stay inside one block they come from one 16-byte load
+// (byte-reversed, then shifted per key), else position by position.
+__device__ __forceinline__ void bwt_init_one(const uint8_t *rle, const uint32_t *blk_start, uint32_t nb, int nbytes,
+                                             uint32_t g, uint64_t *keys, uint32_t *vals, uint32_t *slot) {
+  const uint32_t k = block_of(blk_start, nb, g);
+  const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
+  uint64_t v = 0;
+  uint32_t j = i;
+  for (int t = 0; t < nbytes; t++) {
+    v = (v << 8) | rle[s + j];
+    j = j + 1 == m ? 0u : j + 1;
+  }
+  keys[g] = ((uint64_t)k << (8 * nbytes)) | v;
+  vals[g] = g;
+  slot[g] = g;
+}
+
 __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start, const uint32_t *d_nb,
                            int nbytes, uint64_t *keys, uint32_t *vals, uint32_t *slot, uint32_t *d_u) {
   const uint32_t N = *d_N, nb = *d_nb;
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_u = N;
-  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
-    const uint32_t k = block_of(blk_start, nb, g);
-    const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
-    uint64_t v = 0;
-    uint32_t j = i;
-    for (int t = 0; t < nbytes; t++) {
-      v = (v << 8) | rle[s + j];
-      j = j + 1 == m ? 0u : j + 1;
+  // the block table in one register per lane when it fits a wavefront
+  const bool lane_tab = nb < (uint32_t)kWave;
+  const uint32_t bs = lane_tab && (uint32_t)lane_id() <= nb ? blk_start[lane_id()] : 0u;
+  const int kbits = 8 * nbytes;  // nbytes <= 7
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; (uint64_t)t * 8 < N; t += gridDim.x * blockDim.x) {
+    const uint32_t g0 = t * 8;
+    uint32_t k = 0;
+    if (lane_tab) {
+      for (uint32_t j = 1; j < nb; j++) k += g0 >= (uint32_t)__builtin_amdgcn_readlane((int)bs, (int)j) ? 1u : 0u;
+    } else {
+      k = block_of(blk_start, nb, g0);
     }
-    keys[g] = ((uint64_t)k << (8 * nbytes)) | v;
-    vals[g] = g;
-    slot[g] = g;
+    const uint32_t e = blk_start[k + 1];
+    // bytes g0 .. g0 + 7 + nbytes - 1 all inside block k (no wrap); the 16
+    // loaded bytes end below N + 8, inside the buffer's padding
+    if ((uint64_t)g0 + 8 <= N && (uint64_t)g0 + 7 + (uint32_t)nbytes <= e) {
+      const uint64_t hi = __builtin_bswap64(*(const uint64_t *)(rle + g0));
+      const uint64_t lo = __builtin_bswap64(*(const uint64_t *)(rle + g0 + 8));
+      const uint64_t top = (uint64_t)k << kbits;
+      uint64_t kk[8];
+#pragma unroll
+      for (int o = 0; o < 8; o++) {
+        const uint64_t w64 = o == 0 ? hi : (hi << (8 * o)) | (lo >> (64 - 8 * o));  // bytes g0 + o .. g0 + o + 7
+        kk[o] = top | (w64 >> (64 - kbits));
+      }
+      uint4 *kq = (uint4 *)(keys + g0);
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        kq[q] = make_uint4((uint32_t)kk[2 * q], (uint32_t)(kk[2 * q] >> 32), (uint32_t)kk[2 * q + 1],
+                           (uint32_t)(kk[2 * q + 1] >> 32));
+      const uint4 g4a = make_uint4(g0, g0 + 1, g0 + 2, g0 + 3), g4b = make_uint4(g0 + 4, g0 + 5, g0 + 6, g0 + 7);
+      ((uint4 *)(vals + g0))[0] = g4a;
+      ((uint4 *)(vals + g0))[1] = g4b;
+      ((uint4 *)(slot + g0))[0] = g4a;
+      ((uint4 *)(slot + g0))[1] = g4b;
+    } else {
+      const uint32_t g1 = min(N, g0 + 8u);
+      for (uint32_t g = g0; g < g1; g++) bwt_init_one(rle, blk_start, nb, nbytes, g, keys, vals, slot);
+    }
   }
 }
 
