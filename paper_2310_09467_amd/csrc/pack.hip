@@ -34,50 +34,55 @@ __device__ __forceinline__ void put_bits(uint32_t *w, uint32_t o, uint32_t nbits
   if (lo) atomicOr(&w[(o >> 5) + 1], lo);
 }
 
-template <typename T>
-__device__ T block_excl_sum(T v, T *sh, T &total) {
-  // 256 threads
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {
-    T t = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : (T)0;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
+// Exclusive scans over a workgroup (any multiple of 64 threads): a shuffle
+// scan inside each wavefront, then every thread combines the totals of the
+// wavefronts before its own (sh holds one entry per wavefront).
+template <typename T, typename Op>
+__device__ T wg_excl_scan(T v, T ident, Op op, T *sh, T &total) {
+  const int lane = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  T incl = v;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const T t = __shfl_up(incl, d);
+    if (lane >= d) incl = op(incl, t);
   }
-  total = sh[255];
-  T r = sh[threadIdx.x] - v;
+  if (lane == kWave - 1) sh[w] = incl;
   __syncthreads();
-  return r;
+  T before = ident, tot = ident;
+  for (int k = 0; k < nw; k++) {
+    const T x = sh[k];
+    if (k < w) before = op(before, x);
+    tot = op(tot, x);
+  }
+  __syncthreads();  // sh may be reused after this
+  T prev = __shfl_up(incl, 1);
+  if (lane == 0) prev = ident;
+  total = tot;
+  return op(before, prev);
 }
 
-__device__ int block_excl_max(int v, int *sh) {
-  // exclusive max-scan with identity -1 (256 threads)
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int d = 1; d < 256; d <<= 1) {
-    int t = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : -1;
-    __syncthreads();
-    sh[threadIdx.x] = max(sh[threadIdx.x], t);
-    __syncthreads();
-  }
-  int r = threadIdx.x > 0 ? sh[threadIdx.x - 1] : -1;
-  __syncthreads();
-  return r;
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *sh, uint32_t &total) {
+  return wg_excl_scan<uint32_t>(v, 0u, [](uint32_t a, uint32_t b) { return a + b; }, sh, total);
 }
 
-__global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const BlockDesc *blocks, BlockCode *codes,
+__device__ __forceinline__ int block_excl_max(int v, int *sh) {  // identity -1
+  int total;
+  return wg_excl_scan<int>(v, -1, [](int a, int b) { return max(a, b); }, sh, total);
+}
+
+constexpr int kPfxThreads = 1024;
+
+__global__ __launch_bounds__(kPfxThreads) void k_prefix(const uint32_t *d_nb, const BlockDesc *blocks, BlockCode *codes,
                                                 const uint32_t *used, const uint8_t *sel, const uint8_t *lens,
                                                 uint32_t *prefix) {
   __shared__ uint32_t w[kPrefixWords];
-  __shared__ uint32_t shu[256];
-  __shared__ int shi[256];
+  __shared__ uint32_t shu[kPfxThreads / kWave];
+  __shared__ int shi[kPfxThreads / kWave];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
   const BlockDesc B = blocks[b];
   const BlockCode C = codes[b];
   const uint32_t G = C.n_groups, nsel = C.n_sel, alpha = C.alpha;
-  for (int i = threadIdx.x; i < (int)kPrefixWords; i += 256) w[i] = 0;
+  for (int i = threadIdx.x; i < (int)kPrefixWords; i += kPfxThreads) w[i] = 0;
   __syncthreads();
   const uint32_t *u = used + b * 8;
   uint32_t nranges = 0;
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
   stage_to_lds(ssel, sel + C.sel_start, min(nsel, kMaxSelectors));
   __syncthreads();
   {
-    const uint32_t K = (nsel + 255u) / 256u;
+    const uint32_t K = (nsel + kPfxThreads - 1u) / kPfxThreads;
     const uint32_t j0 = min(nsel, threadIdx.x * K), j1 = min(nsel, j0 + K);
     int ll[kMaxGroups];
 #pragma unroll
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
       for (int g = 0; g < kMaxGroups; g++) last[g] = sj == g ? (int)j : last[g];
     }
     uint32_t tot;
-    const uint32_t base = block_excl_sum<uint32_t>(bits, shu, tot);
+    const uint32_t base = block_excl_sum(bits, shu, tot);
     uint32_t pos = o + base;
 #pragma unroll
     for (int g = 0; g < kMaxGroups; g++) last[g] = carry[g];
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
     const uint8_t *L = lens + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
     if (threadIdx.x == 0) put_bits(w, o, 5, L[0]);
     o += 5;
-    for (uint32_t t0 = 0; t0 < alpha; t0 += 256) {
+    for (uint32_t t0 = 0; t0 < alpha; t0 += kPfxThreads) {
       const uint32_t sidx = t0 + threadIdx.x;
       int d = 0;
       uint32_t nb = 0;
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
         nb = 2u * (uint32_t)abs(d) + 1u;
       }
       uint32_t tot;
-      const uint32_t off = block_excl_sum<uint32_t>(nb, shu, tot);
+      const uint32_t off = block_excl_sum(nb, shu, tot);
       if (sidx < alpha) {
         uint32_t q = o + off;
         const uint32_t pat = d > 0 ? 2u : 3u;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void k_prefix(const uint32_t *d_nb, const Bloc
   __syncthreads();
   uint32_t *dst = prefix + (size_t)b * kPrefixWords;
   const uint32_t nw = (o + 31) / 32;
-  for (uint32_t i = threadIdx.x; i < nw; i += 256) dst[i] = w[i];
+  for (uint32_t i = threadIdx.x; i < nw; i += kPfxThreads) dst[i] = w[i];
   if (threadIdx.x == 0) codes[b].prefix_bits = o;
 }
 
@@ -384,7 +389,7 @@ __global__ __launch_bounds__(256) void k_header(const FrameOut *frames, const ui
 void launch_pack_prefix(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
                         const uint32_t *used, const uint8_t *sel, const uint8_t *lens, uint32_t *prefix,
                         hipStream_t s) {
-  PCBZ_LAUNCH(k_prefix, dim3(max_blocks), dim3(256), 0, s, d_nb, blocks, codes, used, sel, lens, prefix);
+  PCBZ_LAUNCH(k_prefix, dim3(max_blocks), dim3(kPfxThreads), 0, s, d_nb, blocks, codes, used, sel, lens, prefix);
 }
 
 void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
