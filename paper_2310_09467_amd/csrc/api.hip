@@ -586,10 +586,13 @@ struct UploadItem {
 int stage_plan(pcbz_ctx *ctx, const Plan &P, const Work &w, hipStream_t s, std::vector<UploadItem> &items) {
   std::vector<uint8_t> buf;
   items.clear();
+  // each array at the offset the arena gives it (256-byte aligned, 16 bytes
+  // of slack after it, also after an empty one), so that the arrays usually
+  // reach the device in one copy
   auto add = [&](const void *src, size_t bytes, void *dst) {
-    if (!bytes || !dst) return;
     size_t off = align_up(buf.size(), 256);
-    buf.resize(off + bytes);
+    buf.resize(off + bytes + 16);
+    if (!bytes || !dst) return;
     memcpy(buf.data() + off, src, bytes);
     items.push_back({off, bytes, dst});
   };
@@ -616,6 +619,18 @@ int stage_plan(pcbz_ctx *ctx, const Plan &P, const Work &w, hipStream_t s, std::
 }
 
 int enqueue_upload(pcbz_ctx *ctx, const std::vector<UploadItem> &items, hipStream_t s) {
+  if (items.empty()) return PCBZ_OK;
+  // one copy of the whole span when every destination sits at its staging
+  // offset (the gaps between the arrays are the arena's unused slack)
+  bool one = true;
+  const uint8_t *d0 = (const uint8_t *)items[0].dst;
+  for (const UploadItem &it : items)
+    if ((const uint8_t *)it.dst < d0 || (size_t)((const uint8_t *)it.dst - d0) != it.off - items[0].off) one = false;
+  if (one) {
+    const size_t span = items.back().off + items.back().bytes - items[0].off;
+    HIPCHK(ctx, hipMemcpyAsync(items[0].dst, ctx->h_stage + items[0].off, span, hipMemcpyHostToDevice, s));
+    return PCBZ_OK;
+  }
   for (const UploadItem &it : items)
     HIPCHK(ctx, hipMemcpyAsync(it.dst, ctx->h_stage + it.off, it.bytes, hipMemcpyHostToDevice, s));
   return PCBZ_OK;
