@@ -112,17 +112,37 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
   const uint8_t *sq = seq + b * 256;
   for (uint32_t p = p0 + threadIdx.x; p < p1; p += 64) atomicMax(&lastpos[sq[L[p]]], (int)(p - p0));
   __syncthreads();
-  uint32_t cnt = 0;
-  for (int v = threadIdx.x; v < 256; v += 64) {
-    int lp = lastpos[v];
-    if (lp < 0) continue;
-    cnt++;
-    uint32_t r = 0;
-    for (int u = 0; u < 256; u++) r += lastpos[u] > lp ? 1u : 0u;
-    plist[(size_t)c * 256 + r] = (uint8_t)v;
+  // the partial list orders the chunk's symbols by last occurrence, latest
+  // first: walking the chunk backwards, it is the sequence of positions that
+  // hold the last occurrence of their symbol.  Lane l takes the 16 positions
+  // p1 - 1 - 16 l down to p1 - 16 (l + 1); a wavefront prefix count of the
+  // flagged positions gives each its place in the list.
+  constexpr uint32_t kPer = kChunk / 64;
+  const uint32_t n = p1 - p0, lane = threadIdx.x;
+  uint32_t flags = 0;
+  uint8_t sy[kPer];
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++) {
+    const uint32_t q = lane * kPer + i;
+    sy[i] = 0;
+    if (q < n) {
+      const uint32_t p = p1 - 1 - q;
+      const uint8_t v = sq[L[p]];
+      sy[i] = v;
+      if (lastpos[v] == (int)(p - p0)) flags |= 1u << i;
+    }
   }
-  for (int d = 32; d > 0; d >>= 1) cnt += __shfl_down(cnt, d);
-  if (threadIdx.x == 0) plen[c] = cnt;
+  const uint32_t cnt = (uint32_t)__popc(flags);
+  uint32_t incl = cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d);
+    if ((int)lane >= d) incl += t;
+  }
+  uint32_t r = incl - cnt;
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++)
+    if ((flags >> i) & 1u) plist[(size_t)c * 256 + r++] = sy[i];
+  if (lane == 63) plen[c] = incl;
 }
 
 // List chaining.  Folding a partial list P onto a list C gives P followed by
