@@ -228,13 +228,14 @@ constexpr int kPmThreads = 512;
 __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb, const BlockCode *codes,
                                                             uint32_t *tfreq, uint8_t *cost, uint8_t *lens,
                                                             uint32_t *code_words, int last) {
-  __shared__ uint32_t key_s[kMaxAlpha];
+  constexpr int kPadAlpha = (kMaxAlpha + 3) / 4 * 4;
+  __shared__ __align__(16) uint32_t key_s[kPadAlpha];  // padded with keys above every real one
   __shared__ uint32_t lw[kMaxAlpha];
   __shared__ uint16_t lsym[kMaxAlpha];
   __shared__ uint32_t wt[2][kMaxItems];
   __shared__ uint32_t pw[kMaxItems / 2 + 2];
   __shared__ uint8_t pk[kLevels + 1][kMaxItems];
-  __shared__ uint8_t ln[kMaxAlpha];
+  __shared__ __align__(4) uint8_t ln[kPadAlpha];
   __shared__ uint32_t nlen[kMaxCodeLen + 2], base[kMaxCodeLen + 2];
   __shared__ uint64_t pkw[kLevels + 1][2 * kPmThreads / kWave];  // package flags of each level as bit words
   __shared__ uint32_t leaves_sel[kLevels + 1];                      // leaves among each level's selected prefix
@@ -244,14 +245,20 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
   if (g >= C.n_groups) return;
   const uint32_t n = C.alpha, t = threadIdx.x;
   uint32_t *tfr = tfreq + ((size_t)b * kMaxGroups + g) * kMaxAlpha;
-  // leaves sorted by (weight, symbol): rank = number of smaller keys
-  if (t < n) key_s[t] = (max(tfr[t], 1u) << 9) | t;
+  // leaves sorted by (weight, symbol): rank = number of smaller keys,
+  // counted four keys per 16-byte LDS read (all lanes read the same words)
+  if (t < (uint32_t)kPadAlpha) key_s[t] = t < n ? (max(tfr[t], 1u) << 9) | t : 0xFFFFFFFFu;
   if (t < kMaxCodeLen + 2) nlen[t] = 0;
   __syncthreads();
   if (t < n) {
     const uint32_t key = key_s[t];
+    const uint4 *k4 = (const uint4 *)key_s;
     uint32_t r = 0;
-    for (uint32_t u = 0; u < n; u++) r += key_s[u] < key ? 1u : 0u;
+#pragma unroll 4
+    for (uint32_t u = 0; u < (n + 3) / 4; u++) {
+      const uint4 q = k4[u];
+      r += (q.x < key ? 1u : 0u) + (q.y < key ? 1u : 0u) + (q.z < key ? 1u : 0u) + (q.w < key ? 1u : 0u);
+    }
     lw[r] = key >> 9;
     lsym[r] = (uint16_t)t;
   }
@@ -292,16 +299,19 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
   // select the first 2(n-1) items at the top and follow the packages down:
   // at each level p = packages among the selected prefix, its leaves are the
   // first selc - p leaves, and the level below selects 2p items
-  if (t == 0) {
+  // (one wavefront: lane q counts the packages in bit word q of the prefix)
+  if (t < (uint32_t)kWave) {
     uint32_t selc = 2 * (n - 1);
     for (int j = 1; j <= kLevels; j++) {
       uint32_t p = 0;
-      if (j < kLevels) {
+      if (j < kLevels && t < 2 * kPmThreads / kWave) {
         const uint32_t full = selc / kWave, rest = selc % kWave;
-        for (uint32_t q = 0; q < full; q++) p += (uint32_t)__popcll(pkw[j][q]);
-        if (rest) p += (uint32_t)__popcll(pkw[j][full] & ((1ull << rest) - 1ull));
+        const uint64_t word = pkw[j][t];
+        if (t < full) p = (uint32_t)__popcll(word);
+        else if (t == full && rest) p = (uint32_t)__popcll(word & ((1ull << rest) - 1ull));
       }
-      leaves_sel[j] = selc - p;
+      for (int d = kWave / 2; d > 0; d >>= 1) p += (uint32_t)__shfl_xor((int)p, d);
+      if (t == 0) leaves_sel[j] = selc - p;
       selc = 2 * p;
     }
   }
@@ -332,9 +342,17 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
     }
     __syncthreads();
     if (t < n) {
+      // symbols before t with the same length, four lengths per LDS read
       const uint32_t l = ln[t];
+      const uint32_t *l4 = (const uint32_t *)ln;
       uint32_t r = 0;
-      for (uint32_t u = 0; u < t; u++) r += ln[u] == l ? 1u : 0u;
+#pragma unroll 4
+      for (uint32_t u = 0; u < t / 4; u++) {
+        const uint32_t x = l4[u];
+        r += ((x & 255u) == l ? 1u : 0u) + (((x >> 8) & 255u) == l ? 1u : 0u) + (((x >> 16) & 255u) == l ? 1u : 0u) +
+             ((x >> 24) == l ? 1u : 0u);
+      }
+      for (uint32_t u = t & ~3u; u < t; u++) r += ln[u] == l ? 1u : 0u;
       code_words[((size_t)b * kMaxGroups + g) * kMaxAlpha + t] = base[l] + r;
     }
   }
