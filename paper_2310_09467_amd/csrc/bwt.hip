@@ -440,14 +440,19 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
 // group that stays unresolved (its last element knows the size: slots of a
 // group are consecutive and its rank is the first slot).  A thread owns 16
 // consecutive elements (vector loads); keys next to them come from the
-// neighbouring lanes.
-__global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, const uint32_t *vals,
+// neighbouring lanes.  From the second round on, bits old_bits and up of a
+// key hold the rank the key was built from, which rank[] still holds: the
+// random rank write is skipped where the new rank equals it (the first part
+// of every group that splits).
+__global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_rnd_update(const uint64_t *keys, const uint32_t *vals,
                                                           const uint32_t *slot, const uint32_t *d_u,
                                                           const uint32_t *aggs_m, const uint32_t *blk_start,
                                                           const uint32_t *d_nb, const uint32_t *d_min_m,
-                                                          uint32_t compared, uint32_t *rank, uint32_t *sa,
-                                                          uint32_t *goffw, uint32_t *aggs_s, uint32_t *d_maxg) {
+                                                          uint32_t compared, int old_bits, uint32_t *rank,
+                                                          uint32_t *sa, uint32_t *goffw, uint32_t *aggs_s,
+                                                          uint32_t *d_maxg) {
   __shared__ uint32_t buf[kRTile + kRTile / 32];
+  __shared__ uint32_t oldr[kRTile + kRTile / 32];
   __shared__ uint32_t sh[kRThreads / kWave];
   const uint32_t U = *d_u, nb = *d_nb;
   const uint32_t nt = (U + kRTile - 1) / kRTile;
@@ -471,6 +476,11 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, 
         if (k0 + i == 0 || key[i] != pk) diff |= 1u << i;
       }
       ends = k0 + kRItems >= U || after != key[kRItems - 1];
+      // the rank each key was built from, kept in LDS (registers are the
+      // limit on this kernel's occupancy)
+#pragma unroll
+      for (int i = 0; i < kRItems; i++)
+        oldr[tpad(threadIdx.x * kRItems + i)] = old_bits ? (uint32_t)(key[i] >> old_bits) : 0xFFFFFFFFu;
     }
     load16(slot, k0, U, sl);
     load16(vals, k0, U, g);
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_update(const uint64_t *keys, 
       gw[i] = kUnresNone;
       if (k >= U) continue;
       const uint32_t nr = buf[tpad(threadIdx.x * kRItems + i)];
-      rank[g[i]] = nr;
+      if (nr != oldr[tpad(threadIdx.x * kRItems + i)]) rank[g[i]] = nr;  // rank[g] already holds the rank the key was built from
       const bool first = sl[i] == nr;  // ranks are first slots
       const bool last = k + 1 == U || (i + 1 < kRItems ? ((diff >> (i + 1)) & 1u) != 0 : ends);
       bool done = first && last;
@@ -899,7 +909,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     uint32_t *aggs_m = w.aggs, *aggs_s = w.aggs + rnd_aggs_words(n_max) / 2;
     PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot, du[u], aggs_m, w.d_maxg);
     PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot, du[u], aggs_m, blk_start,
-                d_nb, w.d_min_m, compared, w.rank, sa, w.goff, aggs_s, w.d_maxg);
+                d_nb, w.d_min_m, compared, rounds == 0 ? 0 : rbits, w.rank, sa, w.goff, aggs_s, w.d_maxg);
     PCBZ_LAUNCH(k_rnd_compact, dim3(gt), dim3(kRThreads), 0, s, vals[cur], slot, w.goff, du[u], aggs_s, vals[cur ^ 1],
                 slot2, w.gstart, w.seg_bound, du[u ^ 1]);
     u ^= 1;
