@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
     for (int it = 0; it < ITEMS; it++) {
       const uint32_t li = wfirst + (uint32_t)it * kWave + lane;
       tkey[it] = li < tn ? keys_in[base + li] : 0ull;
-      tval[it] = li < tn ? vals_in[base + li] : 0u;
+      tval[it] = li < tn ? (vals_in ? vals_in[base + li] : (uint32_t)(base + li)) : 0u;  // null: value = position
     }
     // tile-local digit counts follow from the row-scanned table: the next
     // entry of the digit's row is the successor of (digit, tile)
@@ -273,12 +273,17 @@ __device__ __forceinline__ uint32_t block_of(const uint32_t *blk_start, uint32_t
   return upper_index(blk_start, nb, g);
 }
 
+__global__ void k_iota(uint32_t *v, const uint32_t *d_n, uint32_t n_max) {
+  const uint32_t n = dev_n(d_n, n_max);
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) v[k] = k;
+}
+
 // key = (block, the first `nbytes` bytes of the rotation, cyclic), the block
 // in the bits above 8 * nbytes.  A thread builds 8 consecutive keys: when
 // their windows stay inside one block they come from one 16-byte load
 // (byte-reversed, then shifted per key), else position by position.
 __device__ __forceinline__ void bwt_init_one(const uint8_t *rle, const uint32_t *blk_start, uint32_t nb, int nbytes,
-                                             uint32_t g, uint64_t *keys, uint32_t *vals, uint32_t *slot) {
+                                             uint32_t g, uint64_t *keys) {
   const uint32_t k = block_of(blk_start, nb, g);
   const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
   uint64_t v = 0;
@@ -288,12 +293,10 @@ __device__ __forceinline__ void bwt_init_one(const uint8_t *rle, const uint32_t 
     j = j + 1 == m ? 0u : j + 1;
   }
   keys[g] = ((uint64_t)k << (8 * nbytes)) | v;
-  vals[g] = g;
-  slot[g] = g;
 }
 
 __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start, const uint32_t *d_nb,
-                           int nbytes, uint64_t *keys, uint32_t *vals, uint32_t *slot, uint32_t *d_u) {
+                           int nbytes, uint64_t *keys, uint32_t *d_u) {
   const uint32_t N = *d_N, nb = *d_nb;
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_u = N;
   // the block table in one register per lane when it fits a wavefront
@@ -326,14 +329,9 @@ __global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32
       for (int q = 0; q < 4; q++)
         kq[q] = make_uint4((uint32_t)kk[2 * q], (uint32_t)(kk[2 * q] >> 32), (uint32_t)kk[2 * q + 1],
                            (uint32_t)(kk[2 * q + 1] >> 32));
-      const uint4 g4a = make_uint4(g0, g0 + 1, g0 + 2, g0 + 3), g4b = make_uint4(g0 + 4, g0 + 5, g0 + 6, g0 + 7);
-      ((uint4 *)(vals + g0))[0] = g4a;
-      ((uint4 *)(vals + g0))[1] = g4b;
-      ((uint4 *)(slot + g0))[0] = g4a;
-      ((uint4 *)(slot + g0))[1] = g4b;
     } else {
       const uint32_t g1 = min(N, g0 + 8u);
-      for (uint32_t g = g0; g < g1; g++) bwt_init_one(rle, blk_start, nb, nbytes, g, keys, vals, slot);
+      for (uint32_t g = g0; g < g1; g++) bwt_init_one(rle, blk_start, nb, nbytes, g, keys);
     }
   }
 }
@@ -402,6 +400,15 @@ __device__ __forceinline__ void store16(uint32_t *a, uint32_t k0, uint32_t n, co
       if (k0 + i < n) a[k0 + i] = v[i];
   }
 }
+// slots of 16 consecutive list elements; a null list means slot = position
+__device__ __forceinline__ void load_slots(const uint32_t *slot, uint32_t k0, uint32_t n, uint32_t *v) {
+  if (slot) {
+    load16(slot, k0, n, v);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) v[i] = k0 + i;
+  }
+}
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src), hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
   return ((uint64_t)hi << 32) | lo;
@@ -419,7 +426,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
     uint64_t key[kRItems];
     uint32_t sl[kRItems];
     load16(keys, k0, U, key);
-    load16(slot, k0, U, sl);
+    load_slots(slot, k0, U, sl);
     uint64_t before = shfl64(key[kRItems - 1], lane - 1);
     if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
     // slots grow along the list: the last group start of the thread has the largest mark
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) 
       for (int i = 0; i < kRItems; i++)
         oldr[tpad(threadIdx.x * kRItems + i)] = old_bits ? (uint32_t)(key[i] >> old_bits) : 0xFFFFFFFFu;
     }
-    load16(slot, k0, U, sl);
+    load_slots(slot, k0, U, sl);
     load16(vals, k0, U, g);
     carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
 #pragma unroll
@@ -558,7 +565,7 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals,
       if (w[i] == kUnresNone) continue;
       const uint32_t q = buf[tpad(j)], off = w[i];
       vals2[q] = vals[k];
-      slot2[q] = slot[k];
+      slot2[q] = slot ? slot[k] : k;
       gstart2[q] = q - off;
       const uint32_t wn = k + 1 < U ? goffw[k + 1] : kUnresNone;
       if (wn == 0 || wn == kUnresNone) {  // last of its group: the next element starts another or is resolved
@@ -829,11 +836,14 @@ uint32_t grid_for(uint64_t n) {
 }
 
 template <int ITEMS>
-int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits,
+int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, bool iota_vals,
                  uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   int cur = 0;
-  if (n_max <= 1 || bits <= 0) return cur;
+  if (n_max <= 1 || bits <= 0) {
+    if (iota_vals) PCBZ_LAUNCH(k_iota, dim3(grid_for(n_max)), dim3(256), 0, s, vals[0], d_n, n_max);
+    return cur;
+  }
   const uint32_t ntiles = (n_max + TILE - 1) / TILE;
   uint32_t *totals = counts + radix_counts_words(n_max) - 256;  // after the largest count table
   (void)scan_tmp;
@@ -842,7 +852,8 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
     PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, shift, counts,
                 d_count_n);
     PCBZ_LAUNCH(k_rs_rowscan<ITEMS>, dim3(256), dim3(kRsThreads), 0, s, counts, d_n, n_max, totals);
-    PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], vals[cur], keys[cur ^ 1],
+    PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur],
+                iota_vals && shift == 0 ? nullptr : vals[cur], keys[cur ^ 1],
                 vals[cur ^ 1], d_n, n_max, shift, counts, totals);
     // a scatter pass reads and writes every 8-byte key and 4-byte value once
     trace_bytes("k_rs_scatter<ITEMS>", 24ull * n_max);
@@ -860,11 +871,12 @@ size_t rnd_aggs_words(uint32_t n_max) { return 2 * ((size_t)n_max / kRTile + 2);
 size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + 2047) / 2048 + 1); }
 
 // Sorts (keys[0], vals[0]) by the low `bits` bits of the key (n read from
-// d_n); returns the buffer index holding the result.
+// d_n); returns the buffer index holding the result.  With iota_vals the
+// values are the positions 0..n-1 and vals[0] is not read.
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
-               uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
-  if (items <= 8) return radix_sort_t<8>(keys, vals, d_n, n_max, bits, counts, d_count_n, scan_tmp, s);
-  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, counts, d_count_n, scan_tmp, s);
+               bool iota_vals, uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+  if (items <= 8) return radix_sort_t<8>(keys, vals, d_n, n_max, bits, iota_vals, counts, d_count_n, scan_tmp, s);
+  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, iota_vals, counts, d_count_n, scan_tmp, s);
 }
 
 // Prefix doubling over every block.  With `pinned_u` the unresolved count and
@@ -891,10 +903,10 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   // one (noisy 16-bit data leaves most rotations tied after 4 bytes, far
   // fewer after 7)
   const int nbytes = nb_max <= 256 ? 7 : nb_max <= 65536 ? 6 : 4;
-  PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, nbytes, keys[0], vals[0], slot,
-              du[0]);
+  PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, nbytes, keys[0], du[0]);
   PCBZ_LAUNCH(k_min_block, dim3(1), dim3(256), 0, s, blk_start, d_nb, w.d_min_m);
-  int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items,
+  // the values are the rotations, i.e. the positions: the first pass makes them
+  int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items, true,
                        w.counts, w.d_count_n, w.scan_tmp, s);
   const int rbits = bits_for(n_max - 1);
   const ptrdiff_t maxg_at = w.d_maxg - w.d_u;  // read back together with the counts
@@ -907,10 +919,12 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     // new ranks (max-scan of group-start slots), then the compaction
     const uint32_t gt = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kGridCap, (n_cur + kRTile - 1) / kRTile));
     uint32_t *aggs_m = w.aggs, *aggs_s = w.aggs + rnd_aggs_words(n_max) / 2;
-    PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot, du[u], aggs_m, w.d_maxg);
-    PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot, du[u], aggs_m, blk_start,
+    // after the first sort, list position k is suffix-array slot k
+    const uint32_t *slot_in = rounds == 0 ? nullptr : slot;
+    PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot_in, du[u], aggs_m, w.d_maxg);
+    PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot_in, du[u], aggs_m, blk_start,
                 d_nb, w.d_min_m, compared, rounds == 0 ? 0 : rbits, w.rank, sa, w.goff, aggs_s, w.d_maxg);
-    PCBZ_LAUNCH(k_rnd_compact, dim3(gt), dim3(kRThreads), 0, s, vals[cur], slot, w.goff, du[u], aggs_s, vals[cur ^ 1],
+    PCBZ_LAUNCH(k_rnd_compact, dim3(gt), dim3(kRThreads), 0, s, vals[cur], slot_in, w.goff, du[u], aggs_s, vals[cur ^ 1],
                 slot2, w.gstart, w.seg_bound, du[u ^ 1]);
     u ^= 1;
     rounds++;
@@ -942,7 +956,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
                   compared, rbits, keys[cur]);
       uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
       uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
-      if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, w.counts, w.d_count_n, w.scan_tmp, s) == 1) cur ^= 1;
+      if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, false, w.counts, w.d_count_n, w.scan_tmp, s) == 1)
+        cur ^= 1;
     }
     compared *= 2;
   }
