@@ -427,7 +427,7 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.bw.slot = A.get<uint32_t>(nr + 1);
   w.bw.slot2 = A.get<uint32_t>(nr + 1);
   w.bw.rank = A.get<uint32_t>(nr + 1);
-  w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr));
+  w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr, S));
   w.bw.seg_bound = A.get<uint32_t>(seg_bound_words((uint32_t)nr));
   w.bw.goff = A.get<uint32_t>(nr + 1);
   w.bw.gstart = A.get<uint32_t>(nr + 1);
@@ -476,7 +476,7 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.frame_len = A.get<uint64_t>(P.frames.size());
   // data bits <= 9 per symbol (a 9-bit code is always feasible), header < 20 KB
   w.max_words = (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)w.max_sym * 9 / 8 + (uint64_t)S * 20600) / 4 + S);
-  size_t scan_n = std::max<size_t>((size_t)w.max_sym + 2, radix_counts_words((uint32_t)nr));
+  size_t scan_n = std::max<size_t>((size_t)w.max_sym + 2, radix_counts_words((uint32_t)nr, S));
   w.scan_tmp = A.get<uint8_t>(scan_tmp_bytes(scan_n));
   w.scan_n = scan_n;
   w.bw.scan_tmp = w.scan_tmp;

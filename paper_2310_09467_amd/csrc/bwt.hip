@@ -50,24 +50,111 @@ __device__ __forceinline__ uint32_t dev_n(const uint32_t *d_n, uint32_t n_max) {
   return n < n_max ? n : n_max;
 }
 
+// Tiles of a sort.  Unsegmented (blk null): tile t covers [t TILE,
+// min(n, (t + 1) TILE)).  Segmented: every pass keeps each block's elements
+// inside the block's range (a stable sort within each block, so no pass is
+// spent on the block id) and tiles never straddle a block: tile t of block b
+// (tile_base[b] <= t < tile_base[b + 1]) covers TILE elements from
+// blk[b] + (t - tile_base[b]) TILE, cut at the block's end.
+struct RsSeg {
+  const uint32_t *blk;        // block starts [nb + 1], or null
+  const uint32_t *tile_base;  // first tile of each block [nb + 1]
+  const uint32_t *d_nb;
+};
+struct RsTile {
+  uint32_t base, tn, b, tb0, tb1;  // tb0, tb1: the block's first tile and the next block's
+};
+// With fewer than 64 blocks a lane holds block lane's start and first tile
+// (loaded once per workgroup), and a tile's block is one ballot.
+struct RsLanes {
+  uint32_t nb, bs, tbl;
+  bool on;
+};
+__device__ __forceinline__ RsLanes rs_lanes(const RsSeg &sg) {
+  RsLanes L{0u, 0u, 0xFFFFFFFFu, false};
+  if (!sg.blk) return L;
+  L.nb = *sg.d_nb;
+  L.on = L.nb < (uint32_t)kWave;
+  const uint32_t lane = lane_id();
+  if (L.on && lane <= L.nb) {
+    L.bs = sg.blk[lane];
+    L.tbl = lane < L.nb ? sg.tile_base[lane] : 0xFFFFFFFFu;
+  }
+  return L;
+}
+__device__ __forceinline__ uint32_t rs_tiles(const RsSeg &sg, uint32_t n, uint32_t tile_len) {
+  return sg.blk ? sg.tile_base[*sg.d_nb] : (n + tile_len - 1) / tile_len;
+}
+__device__ __forceinline__ RsTile rs_tile(const RsSeg &sg, const RsLanes &L, uint32_t n, uint32_t nt,
+                                          uint32_t tile_len, uint32_t t) {
+  if (!sg.blk) {
+    const uint32_t base = t * tile_len;
+    return {base, min(tile_len, n - base), 0u, 0u, nt};
+  }
+  uint32_t b, s0, s1, tb0, tb1;
+  if (L.on) {  // uniform: every lane holds the same t
+    b = (uint32_t)__popcll(ballot64(L.tbl <= t)) - 1u;
+    s0 = (uint32_t)__builtin_amdgcn_readlane((int)L.bs, (int)b);
+    s1 = (uint32_t)__builtin_amdgcn_readlane((int)L.bs, (int)b + 1);
+    tb0 = (uint32_t)__builtin_amdgcn_readlane((int)L.tbl, (int)b);
+    tb1 = b + 1 < L.nb ? (uint32_t)__builtin_amdgcn_readlane((int)L.tbl, (int)b + 1) : nt;
+  } else {
+    b = upper_index(sg.tile_base, L.nb, t);
+    s0 = sg.blk[b];
+    s1 = sg.blk[b + 1];
+    tb0 = sg.tile_base[b];
+    tb1 = sg.tile_base[b + 1];
+  }
+  const uint32_t base = s0 + (t - tb0) * tile_len;
+  return {base, min(tile_len, s1 - base), b, tb0, tb1};
+}
+
+// first tile of each block: exclusive scan of ceil(block length / tile_len).
+// One workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_rs_tile_base(const uint32_t *blk, const uint32_t *d_nb, uint32_t tile_len,
+                                                      uint32_t *tile_base) {
+  __shared__ uint32_t sh[256];
+  const uint32_t nb = *d_nb, t = threadIdx.x;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nb; c0 += 256) {
+    const uint32_t b = c0 + t;
+    const uint32_t v = b < nb ? (blk[b + 1] - blk[b] + tile_len - 1) / tile_len : 0u;
+    sh[t] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 256; d <<= 1) {
+      const uint32_t x = t >= d ? sh[t - d] : 0u;
+      __syncthreads();
+      sh[t] += x;
+      __syncthreads();
+    }
+    if (b < nb) tile_base[b] = carry + sh[t] - v;
+    carry += sh[255];
+    __syncthreads();
+  }
+  if (t == 0) tile_base[nb] = carry;
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, const uint32_t *d_n, uint32_t n_max,
-                                                        int shift, uint32_t *counts, uint32_t *d_count_n) {
+                                                        RsSeg sg, int shift, uint32_t *counts, uint32_t *d_count_n) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   __shared__ uint32_t h[kRsThreads / kWave][256];
   const uint32_t n = dev_n(d_n, n_max);
-  const uint32_t nt = (n + TILE - 1) / TILE;
+  const uint32_t nt = rs_tiles(sg, n, TILE);
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_count_n = 256u * nt;
   const int w = threadIdx.x / kWave;
+  const RsLanes RL = rs_lanes(sg);
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const RsTile T = rs_tile(sg, RL, n, nt, TILE, tile);
+    const uint32_t te = T.base + T.tn;
     for (int i = threadIdx.x; i < (kRsThreads / kWave) * 256; i += kRsThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     // a thread counts ITEMS consecutive keys (vector loads) and adds each run
     // of equal digits once; a digit shared by the whole wavefront (the block
     // id, the mostly-zero high bytes) is added once per wavefront
-    const uint64_t j0 = (uint64_t)tile * TILE + (uint64_t)threadIdx.x * ITEMS;
+    const uint64_t j0 = (uint64_t)T.base + (uint64_t)threadIdx.x * ITEMS;
     uint32_t dig[ITEMS];
-    if (j0 + ITEMS <= n) {
+    if (j0 + ITEMS <= te && (j0 & 1) == 0) {  // 16-byte loads need an even start
       const uint4 *q = (const uint4 *)(keys + j0);
 #pragma unroll
       for (int i = 0; i < ITEMS / 2; i++) {
@@ -75,9 +162,12 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
         dig[2 * i] = (uint32_t)((((uint64_t)t.y << 32) | t.x) >> shift) & 255u;
         dig[2 * i + 1] = (uint32_t)((((uint64_t)t.w << 32) | t.z) >> shift) & 255u;
       }
+    } else if (j0 + ITEMS <= te) {
+#pragma unroll
+      for (int i = 0; i < ITEMS; i++) dig[i] = (uint32_t)(keys[j0 + i] >> shift) & 255u;
     } else {
 #pragma unroll
-      for (int i = 0; i < ITEMS; i++) dig[i] = j0 + i < n ? (uint32_t)(keys[j0 + i] >> shift) & 255u : 256u;
+      for (int i = 0; i < ITEMS; i++) dig[i] = j0 + i < te ? (uint32_t)(keys[j0 + i] >> shift) & 255u : 256u;
     }
     uint32_t cur = dig[0], run = 0;
 #pragma unroll
@@ -114,12 +204,12 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
 // total goes to totals[digit].  One workgroup per digit.
 template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_rowscan(uint32_t *counts, const uint32_t *d_n, uint32_t n_max,
-                                                           uint32_t *totals) {
+                                                           RsSeg sg, uint32_t *totals) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   constexpr uint32_t kPer = 16;  // consecutive row entries per thread
   __shared__ uint32_t wsum[kRsThreads / kWave];
   const uint32_t n = dev_n(d_n, n_max);
-  const uint32_t nt = (n + TILE - 1) / TILE;
+  const uint32_t nt = rs_tiles(sg, n, TILE);
   uint32_t *row = counts + (size_t)blockIdx.x * nt;
   const int w = threadIdx.x / kWave, lane = lane_id();
   uint32_t carry = 0;
@@ -158,7 +248,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_rowscan(uint32_t *counts, con
 template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
                                                            uint64_t *keys_out, uint32_t *vals_out,
-                                                           const uint32_t *d_n, uint32_t n_max, int shift,
+                                                           const uint32_t *d_n, uint32_t n_max, RsSeg sg, int shift,
                                                            const uint32_t *offsets, const uint32_t *totals) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   __shared__ uint64_t skey[TILE];
@@ -167,8 +257,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
   __shared__ uint32_t lstart[256];  // start of each digit's run inside the tile
   __shared__ uint32_t wcnt[kRsThreads / kWave][256];
   __shared__ uint32_t wsum[kRsThreads / kWave];
+  __shared__ uint32_t bsum[kRsThreads / kWave];
   const uint32_t n = dev_n(d_n, n_max);
-  const uint32_t nt = (n + TILE - 1) / TILE;
+  const uint32_t nt = rs_tiles(sg, n, TILE);
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
   const uint64_t lt = lanemask_lt();
@@ -189,9 +280,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
     __syncthreads();
   }
   const uint32_t dend = dbase + totals[d0];
+  const RsLanes RL = rs_lanes(sg);
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-    const uint64_t base = (uint64_t)tile * TILE;
-    const uint32_t tn = (uint32_t)min<uint64_t>(TILE, n - base);
+    const RsTile T = rs_tile(sg, RL, n, nt, TILE, tile);
+    const uint64_t base = T.base;
+    const uint32_t tn = T.tn;
     // wavefront w holds the tile's elements [w * ITEMS * 64, (w + 1) * ITEMS * 64)
     // as ITEMS rows of 64, all loaded before the first barrier
     const uint32_t wfirst = (uint32_t)w * (kWave * ITEMS);
@@ -206,8 +299,30 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
     // tile-local digit counts follow from the row-scanned table: the next
     // entry of the digit's row is the successor of (digit, tile)
     const size_t at = (size_t)d0 * nt + tile;
-    const uint32_t here = dbase + offsets[at];
-    const uint32_t next = tile == nt - 1 ? dend : dbase + offsets[at + 1];
+    uint32_t here, next;
+    if (sg.blk) {
+      // the block's count of each digit (row entries at its first tile and
+      // after its last), their exclusive scan over the digits, and the
+      // digit's count in the block's earlier tiles
+      const uint32_t tb0 = T.tb0, tb1 = T.tb1;
+      const uint32_t c0 = offsets[(size_t)d0 * nt + tb0];
+      const uint32_t c1 = tb1 < nt ? offsets[(size_t)d0 * nt + tb1] : totals[d0];
+      const uint32_t cb = c1 - c0;
+      uint32_t bi = cb;
+      for (int dd = 1; dd < kWave; dd <<= 1) {
+        const uint32_t t = __shfl_up(bi, dd);
+        if (lane >= dd) bi += t;
+      }
+      if (lane == kWave - 1) bsum[w] = bi;
+      __syncthreads();
+      uint32_t bb = T.base - (tile - tb0) * TILE + bi - cb;  // block start + digits before
+      for (int k = 0; k < w; k++) bb += bsum[k];
+      here = bb + offsets[at] - c0;
+      next = bb + (tile + 1 < tb1 ? offsets[at + 1] - c0 : cb);
+    } else {
+      here = dbase + offsets[at];
+      next = tile == nt - 1 ? dend : dbase + offsets[at + 1];
+    }
     const uint32_t cnt = next - here;
     gbase[d0] = here;
     // exclusive scan of the 256 counts (one per thread)
@@ -837,24 +952,31 @@ uint32_t grid_for(uint64_t n) {
 
 template <int ITEMS>
 int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, bool iota_vals,
-                 uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+                 const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
+                 uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   int cur = 0;
   if (n_max <= 1 || bits <= 0) {
     if (iota_vals) PCBZ_LAUNCH(k_iota, dim3(grid_for(n_max)), dim3(256), 0, s, vals[0], d_n, n_max);
     return cur;
   }
-  const uint32_t ntiles = (n_max + TILE - 1) / TILE;
-  uint32_t *totals = counts + radix_counts_words(n_max) - 256;  // after the largest count table
+  // count table for at most ntiles tiles, then the digit totals, then the
+  // blocks' first tiles (segmented)
+  const uint32_t nseg = blk_start ? nb_max : 0u;
+  const uint32_t ntiles = (n_max + TILE - 1) / TILE + nseg;
+  uint32_t *totals = counts + (size_t)256 * (ntiles + 1);
+  RsSeg sg{blk_start, blk_start ? totals + 256 : nullptr, d_nb};
+  if (blk_start)
+    PCBZ_LAUNCH(k_rs_tile_base, dim3(1), dim3(256), 0, s, blk_start, d_nb, TILE, (uint32_t *)sg.tile_base);
   (void)scan_tmp;
   const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
   for (int shift = 0; shift < bits; shift += 8) {
-    PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, shift, counts,
+    PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, sg, shift, counts,
                 d_count_n);
-    PCBZ_LAUNCH(k_rs_rowscan<ITEMS>, dim3(256), dim3(kRsThreads), 0, s, counts, d_n, n_max, totals);
+    PCBZ_LAUNCH(k_rs_rowscan<ITEMS>, dim3(256), dim3(kRsThreads), 0, s, counts, d_n, n_max, sg, totals);
     PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur],
                 iota_vals && shift == 0 ? nullptr : vals[cur], keys[cur ^ 1],
-                vals[cur ^ 1], d_n, n_max, shift, counts, totals);
+                vals[cur ^ 1], d_n, n_max, sg, shift, counts, totals);
     // a scatter pass reads and writes every 8-byte key and 4-byte value once
     trace_bytes("k_rs_scatter<ITEMS>", 24ull * n_max);
     cur ^= 1;
@@ -868,15 +990,23 @@ size_t seg_bound_words(uint32_t n_max) { return (size_t)n_max / kSegTile + 2; }
 
 size_t rnd_aggs_words(uint32_t n_max) { return 2 * ((size_t)n_max / kRTile + 2); }
 
-size_t radix_counts_words(uint32_t n_max) { return (size_t)256 * ((n_max + 2047) / 2048 + 1); }
+size_t radix_counts_words(uint32_t n_max, uint32_t nb_max) {
+  // tiles of at least 2048 elements, one more per block when segmented;
+  // the digit totals; the blocks' first tiles
+  return (size_t)256 * ((n_max + 2047) / 2048 + nb_max + 1) + 256 + nb_max + 2;
+}
 
 // Sorts (keys[0], vals[0]) by the low `bits` bits of the key (n read from
 // d_n); returns the buffer index holding the result.  With iota_vals the
 // values are the positions 0..n-1 and vals[0] is not read.
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
-               bool iota_vals, uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
-  if (items <= 8) return radix_sort_t<8>(keys, vals, d_n, n_max, bits, iota_vals, counts, d_count_n, scan_tmp, s);
-  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, iota_vals, counts, d_count_n, scan_tmp, s);
+               bool iota_vals, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
+               uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+  if (items <= 8)
+    return radix_sort_t<8>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n,
+                           scan_tmp, s);
+  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n,
+                          scan_tmp, s);
 }
 
 // Prefix doubling over every block.  With `pinned_u` the unresolved count and
@@ -906,7 +1036,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   PCBZ_LAUNCH(k_bwt_init, dim3(g), dim3(256), 0, s, rle, d_N, blk_start, d_nb, nbytes, keys[0], du[0]);
   PCBZ_LAUNCH(k_min_block, dim3(1), dim3(256), 0, s, blk_start, d_nb, w.d_min_m);
   // the values are the rotations, i.e. the positions: the first pass makes them
-  int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes + bits_for(nb_max > 0 ? nb_max - 1 : 0), items, true,
+  // sorted block by block (segmented), so the passes cover the bytes only
+  int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes, items, true, blk_start, d_nb, nb_max,
                        w.counts, w.d_count_n, w.scan_tmp, s);
   const int rbits = bits_for(n_max - 1);
   const ptrdiff_t maxg_at = w.d_maxg - w.d_u;  // read back together with the counts
@@ -956,7 +1087,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
                   compared, rbits, keys[cur]);
       uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
       uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
-      if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, false, w.counts, w.d_count_n, w.scan_tmp, s) == 1)
+      if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, false, nullptr, nullptr, 0, w.counts, w.d_count_n,
+                     w.scan_tmp, s) == 1)
         cur ^= 1;
     }
     compared *= 2;

@@ -317,11 +317,12 @@ struct BwtWork {
   uint32_t *aggs;       // [rnd_aggs_words] tile aggregates of a doubling round's two scans
   void *scan_tmp;
 };
-size_t radix_counts_words(uint32_t n_max);
+size_t radix_counts_words(uint32_t n_max, uint32_t nb_max);
 size_t seg_bound_words(uint32_t n_max);
 size_t rnd_aggs_words(uint32_t n_max);
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
-               bool iota_vals, uint32_t *counts, uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
+               bool iota_vals, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
+               uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
             const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
             int items, uint32_t *pinned_u, uint64_t *seg_mask, uint32_t *d_left, hipStream_t s);
