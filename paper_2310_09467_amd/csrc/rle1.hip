@@ -25,56 +25,159 @@ constexpr int kCrcChunk = 64;  // bytes per thread: short table-lookup chains, m
 
 __device__ __forceinline__ uint32_t piece_len_out(uint32_t o) { return o < 3 ? 1u : (o == 3 ? 2u : 0u); }
 
-// Run-start markers, four bytes per thread: v[i] = i where a run of equal
-// bytes starts (a band start or a byte that differs from its predecessor),
-// else 0.  Loads are 4-byte words and stores 16-byte vectors, both
-// contiguous across the wavefront.
-__global__ void k_r1_starts(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N,
-                            uint32_t *v) {
-  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= N) return;
-  uint32_t b = upper_index(band_start, n_bands, (uint32_t)i0);
-  const uint32_t wd = *(const uint32_t *)(x + i0);  // the buffer has 16 bytes of slack past N
-  uint32_t prevc = i0 > 0 ? x[i0 - 1] : 0u;
-  uint32_t r[4];
+// The stage runs in three launches over tiles of 4096 positions (256 threads
+// x 16 consecutive positions; each scan takes its carry by reducing the tile
+// aggregates in front of its tile):
+//   k_r1_marks   per-tile maximum of the run-start marks (a position that
+//                starts a run is marked with itself, others with 0);
+//   k_r1_counts  max-scan of the marks = each position's run start (kept for
+//                the block cut), and per-tile sums of the output lengths;
+//   k_r1_write   exclusive scan of the output lengths = output offsets (kept
+//                for the block cut, total at off[N]) and the output bytes.
+
+// 16 bytes from p0 (16-byte aligned; the buffer has 16 bytes of slack past N)
+// and the run-start marks of those positions.
+struct R1Bytes {
+  uint32_t w[4];
+  __device__ __forceinline__ uint32_t at(int i) const { return (w[i >> 2] >> (8 * (i & 3))) & 255u; }
+};
+__device__ __forceinline__ R1Bytes r1_load(const uint8_t *x, uint32_t p0) {
+  const uint4 q = *(const uint4 *)(x + p0);
+  return R1Bytes{{q.x, q.y, q.z, q.w}};
+}
+__device__ __forceinline__ void r1_marks(const R1Bytes &z, const uint8_t *x, const uint32_t *band_start,
+                                         uint32_t n_bands, uint32_t p0, uint32_t N, uint32_t *mk) {
+  uint32_t b = upper_index(band_start, n_bands, p0);
+  uint32_t prevc = p0 > 0 ? x[p0 - 1] : 0u;
 #pragma unroll
-  for (uint32_t k = 0; k < 4; k++) {
-    const uint32_t i = (uint32_t)i0 + k;
-    while (b + 1 < n_bands && band_start[b + 1] <= i) b++;  // bands can be shorter than 4 bytes
-    const uint32_t c = (wd >> (8 * k)) & 255u;
-    const bool start = i == band_start[b] || c != prevc;
-    r[k] = start ? i : 0u;
+  for (int i = 0; i < kTItems; i++) {
+    const uint32_t p = p0 + i;
+    while (b + 1 < n_bands && band_start[b + 1] <= p) b++;  // bands can be shorter than 16 bytes
+    const uint32_t c = z.at(i);
+    mk[i] = p < N && (p == band_start[b] || c != prevc) ? p : 0u;
     prevc = c;
   }
-  if (i0 + 4 <= N) {
-    *(uint4 *)(v + i0) = make_uint4(r[0], r[1], r[2], r[3]);
-  } else {
-    for (uint32_t k = 0; k < 4 && i0 + k < N; k++) v[i0 + k] = r[k];
+}
+
+__global__ __launch_bounds__(kTThreads) void k_r1_marks(const uint32_t *band_start, uint32_t n_bands,
+                                                        const uint8_t *x, uint32_t N, uint32_t *aggs_m) {
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t p0 = tile * kTTile + threadIdx.x * kTItems;
+    uint32_t m = 0;
+    if (p0 < N) {
+      uint32_t mk[kTItems];
+      r1_marks(r1_load(x, p0), x, band_start, n_bands, p0, N, mk);
+#pragma unroll
+      for (int i = 0; i < kTItems; i++) m = max(m, mk[i]);
+    }
+    m = block_reduce<true>(m, sh);
+    if (threadIdx.x == 0) aggs_m[tile] = m;
   }
 }
 
-__global__ void k_r1_len(const uint32_t *runstart, uint32_t N, uint32_t *len) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (uint64_t)gridDim.x * blockDim.x)
-    len[i] = piece_len_out((uint32_t)((i - runstart[i]) % 255u));
+__global__ __launch_bounds__(kTThreads) void k_r1_counts(const uint32_t *band_start, uint32_t n_bands,
+                                                         const uint8_t *x, uint32_t N, const uint32_t *aggs_m,
+                                                         uint32_t *runstart, uint32_t *aggs_s) {
+  __shared__ uint32_t buf[kTPad];
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t p0 = tile * kTTile + threadIdx.x * kTItems;
+    uint32_t mk[kTItems];
+    if (p0 < N) {
+      r1_marks(r1_load(x, p0), x, band_start, n_bands, p0, N, mk);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++) mk[i] = 0;
+    }
+    carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) buf[tpad(threadIdx.x * kTItems + i)] = mk[i];
+    __syncthreads();
+    tile_scan<true, true>(buf, carry, sh);
+    uint32_t rs[kTItems], cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) {
+      rs[i] = buf[tpad(threadIdx.x * kTItems + i)];
+      if (p0 + i < N) cnt += piece_len_out((p0 + i - rs[i]) % 255u);
+    }
+    if (p0 + kTItems <= N) {
+      uint4 *o = (uint4 *)(runstart + p0);
+#pragma unroll
+      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(rs[4 * q], rs[4 * q + 1], rs[4 * q + 2], rs[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (p0 + i < N) runstart[p0 + i] = rs[i];
+    }
+    cnt = block_reduce<false>(cnt, sh);
+    if (threadIdx.x == 0) aggs_s[tile] = cnt;
+  }
 }
 
-__global__ void k_r1_write(const uint32_t *band_start, uint32_t n_bands, uint32_t N, const uint8_t *x,
-                           const uint32_t *runstart, const uint32_t *off, uint8_t *rle) {
-  for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < N; gi += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = (uint32_t)gi;
-    const uint32_t o = (i - runstart[i]) % 255u;
-    if (o > 3) continue;
-    const uint8_t c = x[i];
-    const uint32_t q = off[i];
-    rle[q] = c;
-    if (o == 3) {
-      uint32_t b = upper_index(band_start, n_bands, i);
-      uint32_t bend = b + 1 < n_bands ? band_start[b + 1] : N;
-      uint32_t lim = min(bend, i + 252u);
-      uint32_t j = i + 1;
-      while (j < lim && x[j] == c) j++;
-      rle[q + 1] = (uint8_t)(j - i - 1);
+__global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_start, uint32_t n_bands,
+                                                        const uint8_t *x, uint32_t N, const uint32_t *runstart,
+                                                        const uint32_t *aggs_s, uint32_t *off, uint8_t *rle) {
+  __shared__ uint32_t buf[kTPad];
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t p0 = tile * kTTile + threadIdx.x * kTItems;
+    uint32_t o[kTItems];  // offset inside the run's 255-byte piece (above 3: no output)
+    R1Bytes z{{0u, 0u, 0u, 0u}};
+    if (p0 + kTItems <= N) {
+      const uint4 *q = (const uint4 *)(runstart + p0);
+#pragma unroll
+      for (int k = 0; k < kTItems / 4; k++) {
+        const uint4 r = q[k];
+        o[4 * k] = (p0 + 4 * k - r.x) % 255u;
+        o[4 * k + 1] = (p0 + 4 * k + 1 - r.y) % 255u;
+        o[4 * k + 2] = (p0 + 4 * k + 2 - r.z) % 255u;
+        o[4 * k + 3] = (p0 + 4 * k + 3 - r.w) % 255u;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++) o[i] = p0 + i < N ? (p0 + i - runstart[p0 + i]) % 255u : 255u;
     }
+    if (p0 < N) z = r1_load(x, p0);
+    carry = tile_carry<false>(aggs_s, counted, tile, carry, sh);
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) buf[tpad(threadIdx.x * kTItems + i)] = p0 + i < N ? piece_len_out(o[i]) : 0u;
+    __syncthreads();
+    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
+    uint32_t q[kTItems];
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) q[i] = buf[tpad(threadIdx.x * kTItems + i)];
+    if (p0 + kTItems <= N) {
+      uint4 *d = (uint4 *)(off + p0);
+#pragma unroll
+      for (int k = 0; k < kTItems / 4; k++) d[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (p0 + i < N) off[p0 + i] = q[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) {
+      const uint32_t p = p0 + i;
+      if (p >= N || o[i] > 3) continue;
+      const uint32_t c = z.at(i);
+      rle[q[i]] = (uint8_t)c;
+      if (o[i] == 3) {  // the piece's count byte: equal bytes after the fourth, at most 251, inside the band
+        const uint32_t b = upper_index(band_start, n_bands, p);
+        const uint32_t bend = b + 1 < n_bands ? band_start[b + 1] : N;
+        const uint32_t lim = min(bend, p + 252u);
+        uint32_t j = p + 1;
+        while (j < lim && x[j] == c) j++;
+        rle[q[i] + 1] = (uint8_t)(j - p - 1);
+      }
+    }
+    if (tile == nt - 1 && threadIdx.x == 0) off[N] = carry + total;
+    __syncthreads();
   }
 }
 
@@ -280,13 +383,15 @@ __global__ void k_crc_final(BlockDesc *blocks, const uint32_t *d_n_blocks, const
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
                    uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s) {
   if (!N) return;
-  uint32_t thr = (N + 3) / 4;
-  PCBZ_LAUNCH(k_r1_starts, dim3((thr + 255) / 256), dim3(256), 0, s, band_start, n_bands, x, N, runstart);
-  scan_inclusive_max_u32(runstart, runstart, nullptr, N, scan_tmp, s);
-  uint32_t grid = std::min<uint32_t>((N + 255) / 256, 8192);
-  PCBZ_LAUNCH(k_r1_len, dim3(grid), dim3(256), 0, s, runstart, N, len);
-  scan_exclusive_u32(len, off, nullptr, N, scan_tmp, off + N, s);
-  PCBZ_LAUNCH(k_r1_write, dim3(grid), dim3(256), 0, s, band_start, n_bands, N, x, runstart, off, rle);
+  (void)scan_tmp;
+  // the per-position length array is not needed: it holds the two scans'
+  // tile aggregates (2 * (tiles + 1) <= N + 5 words)
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  uint32_t *aggs_m = len, *aggs_s = len + nt + 1;
+  const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, nt));
+  PCBZ_LAUNCH(k_r1_marks, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, aggs_m);
+  PCBZ_LAUNCH(k_r1_counts, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, aggs_m, runstart, aggs_s);
+  PCBZ_LAUNCH(k_r1_write, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, runstart, aggs_s, off, rle);
 }
 
 void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
