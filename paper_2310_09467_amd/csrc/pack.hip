@@ -218,15 +218,106 @@ __global__ void k_blk_sym_start(const uint32_t *d_nb, const BlockCode *codes, ui
   if (b == 0 && nb == 0) blk_sym_start[0] = 0;
 }
 
-__global__ void k_sym_bits(const uint16_t *sym, const uint32_t *d_n_sym, const uint32_t *d_nb,
-                           const uint32_t *blk_sym_start, const BlockCode *codes, const uint8_t *sel,
-                           const uint8_t *lens, uint32_t *bits) {
+// Bit offsets of the coded symbols: the code length of every symbol (its
+// block's table for its group of 50), exclusively scanned over all blocks.
+// Two launches over tiles of 4096 symbols (256 threads x 16 consecutive): the
+// tile sums, then the scan from a carry summed from the sums in front of the
+// tile; sym_off[n_sym] receives the total.
+__device__ __forceinline__ void sym_lens16(const uint16_t *sym, uint32_t nsym, uint32_t k0, TileBlocks tb,
+                                           const BlockCode *codes, const uint8_t *sel, const uint8_t *lens,
+                                           uint32_t *bits) {
+  uint16_t sy[kTItems];
+  if (k0 + kTItems <= nsym) {
+    const uint4 *q = (const uint4 *)(sym + k0);
+#pragma unroll
+    for (int j = 0; j < kTItems / 8; j++) {
+      const uint4 t = q[j];
+      sy[8 * j + 0] = (uint16_t)(t.x & 0xFFFFu);
+      sy[8 * j + 1] = (uint16_t)(t.x >> 16);
+      sy[8 * j + 2] = (uint16_t)(t.y & 0xFFFFu);
+      sy[8 * j + 3] = (uint16_t)(t.y >> 16);
+      sy[8 * j + 4] = (uint16_t)(t.z & 0xFFFFu);
+      sy[8 * j + 5] = (uint16_t)(t.z >> 16);
+      sy[8 * j + 6] = (uint16_t)(t.w & 0xFFFFu);
+      sy[8 * j + 7] = (uint16_t)(t.w >> 16);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) sy[i] = k0 + i < nsym ? sym[k0 + i] : (uint16_t)0;
+  }
+  uint32_t cb = 0xFFFFFFFFu, ss = 0, sstart = 0;
+#pragma unroll
+  for (int i = 0; i < kTItems; i++) {
+    const uint32_t k = k0 + i;
+    uint32_t v = 0;
+    if (k < nsym) {
+      uint32_t s0, e0;
+      const uint32_t b = tb.find(k, s0, e0);
+      if (b != cb) {
+        cb = b;
+        ss = codes[b].sel_start;
+        sstart = s0;
+      }
+      const uint32_t t = sel[ss + (k - sstart) / kGroupSize];
+      v = lens[((size_t)b * kMaxGroups + t) * kMaxAlpha + sy[i]];
+    }
+    bits[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kTThreads) void k_sym_sums(const uint16_t *sym, const uint32_t *d_n_sym,
+                                                        const uint32_t *d_nb, const uint32_t *blk_sym_start,
+                                                        const BlockCode *codes, const uint8_t *sel,
+                                                        const uint8_t *lens, uint32_t *aggs) {
+  __shared__ uint32_t sh[kTThreads / kWave];
   const uint32_t nsym = *d_n_sym, nb = *d_nb;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nsym; k += gridDim.x * blockDim.x) {
-    const uint32_t b = upper_index(blk_sym_start, nb, k);
-    const uint32_t local = k - blk_sym_start[b];
-    const uint32_t t = sel[codes[b].sel_start + local / kGroupSize];
-    bits[k] = lens[((size_t)b * kMaxGroups + t) * kMaxAlpha + sym[k]];
+  const uint32_t nt = (nsym + kTTile - 1) / kTTile;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const TileBlocks tb(blk_sym_start, nb, tile * kTTile);
+    uint32_t bits[kTItems], cnt = 0;
+    sym_lens16(sym, nsym, tile * kTTile + threadIdx.x * kTItems, tb, codes, sel, lens, bits);
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) cnt += bits[i];
+    cnt = block_reduce<false>(cnt, sh);
+    if (threadIdx.x == 0) aggs[tile] = cnt;
+  }
+}
+
+__global__ __launch_bounds__(kTThreads) void k_sym_offs(const uint16_t *sym, const uint32_t *d_n_sym,
+                                                        const uint32_t *d_nb, const uint32_t *blk_sym_start,
+                                                        const BlockCode *codes, const uint8_t *sel,
+                                                        const uint8_t *lens, const uint32_t *aggs,
+                                                        uint32_t *sym_off) {
+  __shared__ uint32_t buf[kTPad];
+  __shared__ uint32_t sh[kTThreads / kWave];
+  const uint32_t nsym = *d_n_sym, nb = *d_nb;
+  const uint32_t nt = (nsym + kTTile - 1) / kTTile;
+  if (nt == 0 && blockIdx.x == 0 && threadIdx.x == 0) sym_off[0] = 0;
+  uint32_t carry = 0, counted = 0;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const uint32_t k0 = tile * kTTile + threadIdx.x * kTItems;
+    const TileBlocks tb(blk_sym_start, nb, tile * kTTile);
+    uint32_t bits[kTItems];
+    sym_lens16(sym, nsym, k0, tb, codes, sel, lens, bits);
+    carry = tile_carry<false>(aggs, counted, tile, carry, sh);
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) buf[tpad(threadIdx.x * kTItems + i)] = bits[i];
+    __syncthreads();
+    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
+    uint32_t q[kTItems];
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) q[i] = buf[tpad(threadIdx.x * kTItems + i)];
+    if (k0 + kTItems <= nsym) {
+      uint4 *d = (uint4 *)(sym_off + k0);
+#pragma unroll
+      for (int j = 0; j < kTItems / 4; j++) d[j] = make_uint4(q[4 * j], q[4 * j + 1], q[4 * j + 2], q[4 * j + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (k0 + i < nsym) sym_off[k0 + i] = q[i];
+    }
+    if (tile == nt - 1 && threadIdx.x == 0) sym_off[nsym] = carry + total;
+    __syncthreads();
   }
 }
 
@@ -400,11 +491,13 @@ void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *bl
                   uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
                   hipEvent_t prefix_ready, hipStream_t s) {
   PCBZ_LAUNCH(k_blk_sym_start, dim3((max_blocks + 256) / 256), dim3(256), 0, s, d_nb, codes, blk_sym_start);
-  const uint32_t g = std::min<uint32_t>((max_sym + 255) / 256 + 1, 16384);
-  PCBZ_LAUNCH(k_sym_bits, dim3(g), dim3(256), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
-                     sym_bits);
-  // exclusive scan over n_sym + 1 entries so that sym_off[n_sym] is the total
-  scan_exclusive_u32(sym_bits, sym_off, nullptr, max_sym + 1, scan_tmp, nullptr, s);
+  // sym_bits holds the tile sums (tiles + 1 <= max_sym + 1 words)
+  (void)scan_tmp;
+  const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (max_sym + kTTile - 1) / kTTile));
+  PCBZ_LAUNCH(k_sym_sums, dim3(gt), dim3(kTThreads), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
+              sym_bits);
+  PCBZ_LAUNCH(k_sym_offs, dim3(gt), dim3(kTThreads), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
+              sym_bits, sym_off);
   if (prefix_ready) (void)hipStreamWaitEvent(s, prefix_ready, 0);
   PCBZ_LAUNCH(k_layout, dim3(1), dim3(64), 0, s, d_nb, blocks, codes, sym_off, blk_sym_start, frames, n_frames,
                      bands, band_len, frame_len, word_start, d_words);

@@ -193,6 +193,39 @@ __device__ __forceinline__ uint32_t upper_index(const T *a, uint32_t n, T key) {
   return lo;
 }
 
+// The blocks a tile touches: the first one's bounds are kept in registers,
+// positions past it (tiles that cross a block end) search forward.
+struct TileBlocks {
+  const uint32_t *blk_start;
+  uint32_t nb, b0, s0, e0;
+  __device__ __forceinline__ TileBlocks(const uint32_t *bs, uint32_t n, uint32_t base) : blk_start(bs), nb(n) {
+    if (n < (uint32_t)kWave) {  // one load per lane instead of a chain of dependent ones
+      const int lane = lane_id();
+      const uint32_t mine = (uint32_t)lane <= n ? bs[lane] : 0xFFFFFFFFu;
+      b0 = (uint32_t)__popcll(ballot64((uint32_t)lane < n && mine <= base)) - 1u;
+      s0 = (uint32_t)__shfl((int)mine, (int)b0);
+      e0 = (uint32_t)__shfl((int)mine, (int)b0 + 1);
+    } else {
+      b0 = upper_index(bs, n, base);
+      s0 = bs[b0];
+      e0 = bs[b0 + 1];
+    }
+  }
+  // block of p (p >= the tile base), with its start and end
+  __device__ __forceinline__ uint32_t find(uint32_t p, uint32_t &s, uint32_t &e) const {
+    if (p < e0) {
+      s = s0;
+      e = e0;
+      return b0;
+    }
+    uint32_t b = b0;
+    while (b + 1 < nb && blk_start[b + 1] <= p) b++;
+    s = blk_start[b];
+    e = blk_start[b + 1];
+    return b;
+  }
+};
+
 // Copies n elements from global memory into LDS with the whole workgroup,
 // keeping 16 loads in flight per thread (a plain strided loop waits for each
 // load before the next).
