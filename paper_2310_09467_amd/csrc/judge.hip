@@ -200,7 +200,9 @@ __global__ __launch_bounds__(1024) void k_judge_pairs(const JudgeTask *tasks, co
 // pairs at bucket boundaries.  One workgroup per task, one thread per byte
 // value; pairs are counted in a 16-bit LDS histogram (at most 256 per tile
 // boundary plus 255 bucket boundaries per bin) and flushed once.
-__global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, const uint16_t *tile_first,
+constexpr int kFixThreads = 1024;
+
+__global__ __launch_bounds__(kFixThreads) void k_judge_fixup(const JudgeTask *tasks, const uint16_t *tile_first,
                                                      const uint16_t *tile_last, uint32_t *hist_g,
                                                      const uint8_t *forced) {
   __shared__ uint32_t lh[32768];
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
   const uint32_t ntile = (T.n + kJTile - 1) / kJTile;
   uint32_t *H = hist_g + (size_t)blockIdx.x * 65536;
   const bool use_lds = ntile <= 200;  // keeps every 16-bit LDS bin below 65536
-  for (int i = threadIdx.x; i < 32768; i += 256) lh[i] = 0;
+  for (int i = threadIdx.x; i < 32768; i += kFixThreads) lh[i] = 0;
   __syncthreads();
   auto add = [&](uint32_t q) {
     if (use_lds)
@@ -221,7 +223,9 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
   };
   uint32_t last = kNone16, first_ever = kNone16;
   constexpr uint32_t kBatch = 16;  // independent loads in flight per step
-  for (uint32_t s0 = 0; s0 < ntile; s0 += kBatch) {
+  // threads 0..255 follow the chain of byte c = thread; all threads clear
+  // and flush the histogram
+  for (uint32_t s0 = 0; c < 256 && s0 < ntile; s0 += kBatch) {
     uint32_t f[kBatch], l[kBatch];
 #pragma unroll
     for (uint32_t k = 0; k < kBatch; k++) {
@@ -239,10 +243,12 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
       last = l[k];
     }
   }
-  fe[c] = (uint16_t)first_ever;
-  le[c] = (uint16_t)last;
+  if (c < 256) {
+    fe[c] = (uint16_t)first_ever;
+    le[c] = (uint16_t)last;
+  }
   __syncthreads();
-  if (last != kNone16) {
+  if (c < 256 && last != kNone16) {
     for (uint32_t c2 = c + 1; c2 < 256; c2++) {
       if (fe[c2] != kNone16) {
         add((last << 8) | fe[c2]);
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(256) void k_judge_fixup(const JudgeTask *tasks, con
   }
   __syncthreads();
   if (use_lds) {
-    for (int i = threadIdx.x; i < 32768; i += 256) {
+    for (int i = threadIdx.x; i < 32768; i += kFixThreads) {
       const uint32_t v = lh[i];
       if (v & 0xFFFFu) atomicAdd(&H[2 * i], v & 0xFFFFu);
       if (v >> 16) atomicAdd(&H[2 * i + 1], v >> 16);
@@ -380,7 +386,7 @@ void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *til
   if (!n_tasks) return;
   PCBZ_LAUNCH(k_judge_pairs, dim3(n_tiles), dim3(1024), 0, s, tasks, tile_task, tile_local, cb, seg_first,
                      seg_last, hist, forced);
-  PCBZ_LAUNCH(k_judge_fixup, dim3(n_tasks), dim3(256), 0, s, tasks, seg_first, seg_last, hist, forced);
+  PCBZ_LAUNCH(k_judge_fixup, dim3(n_tasks), dim3(kFixThreads), 0, s, tasks, seg_first, seg_last, hist, forced);
   PCBZ_LAUNCH(k_judge_score, dim3(64, n_tasks), dim3(256), 0, s, hist, tq, score, tasks, forced);
 }
 
