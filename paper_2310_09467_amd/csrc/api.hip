@@ -692,7 +692,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   launch_gather2(w.band_start, nbands, w.cb, w.choice, w.chosen, P.ntot, s);
   trace_stage("rle1");
   // first run-length stage, block cuts, CRCs
-  launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, s);
+  launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, w.ctr + 3, s);
   launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
               w.blk_raw_start, w.blk_rle_start, w.crc_chunk_base, w.ctr + 1, w.ctr + 2, s);
   // the block CRCs run beside the suffix sort (only the header bits need them)
@@ -706,12 +706,12 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   uint32_t nb = w.max_blocks, nrle = w.n_rle_max;
   const uint32_t *d_nrle = w.r1off + N;
   if (eager) {
+    // counters: [1] blocks, [3] run-length output bytes, [8] slot overflow
     HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->h_small + 16, d_nrle, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (ctx->h_small[8]) return fail(ctx, PCBZ_EDEVICE, "block slot overflow");
     nb = ctx->h_small[1];
-    nrle = ctx->h_small[16];
+    nrle = ctx->h_small[3];
   }
   // suffix sort of every block
   trace_stage("bwt");
@@ -817,7 +817,7 @@ int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, 
   uint32_t ctr[16];
   if ((st = read_results(ctx, P, w, s, lens, ctr))) return st;
   ctx->last_raw = P.ntot;
-  ctx->last_rle = ctx->h_small[16];
+  ctx->last_rle = ctr[3];
   ctx->last_blocks = ctr[1];
   ctx->last_rounds = (uint32_t)rounds;
   ctx->last_graph = 0;
@@ -991,6 +991,7 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
   uint32_t ctr[16];
   if ((st = read_results(ctx, P, w, s, lens, ctr))) return st;
   ctx->last_raw = P.ntot;
+  ctx->last_rle = ctr[3];
   ctx->last_blocks = ctr[1];
   ctx->last_rounds = (uint32_t)tu.rounds;
   ctx->last_graph = 1;

@@ -321,8 +321,9 @@ void launch_validate_forced(const BandDesc *bands, uint32_t n_bands, uint8_t *fo
 void launch_gather_forced(const FrameOut *frames, uint32_t n_frames, uint8_t *forced, hipStream_t s);
 
 // rle1.hip
+// d_total (may be null) also receives the output length, off[N]
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
-                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s);
+                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, uint32_t *d_total, hipStream_t s);
 void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
                  const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
                  uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,

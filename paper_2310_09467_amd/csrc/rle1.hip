@@ -120,7 +120,8 @@ __global__ __launch_bounds__(kTThreads) void k_r1_counts(const uint32_t *band_st
 
 __global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_start, uint32_t n_bands,
                                                         const uint8_t *x, uint32_t N, const uint32_t *runstart,
-                                                        const uint32_t *aggs_s, uint32_t *off, uint8_t *rle) {
+                                                        const uint32_t *aggs_s, uint32_t *off, uint8_t *rle,
+                                                        uint32_t *d_total) {
   __shared__ uint32_t buf[kTPad];
   __shared__ uint32_t sh[kTThreads / kWave];
   const uint32_t nt = (N + kTTile - 1) / kTTile;
@@ -176,7 +177,10 @@ __global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_sta
         rle[q[i] + 1] = (uint8_t)(j - p - 1);
       }
     }
-    if (tile == nt - 1 && threadIdx.x == 0) off[N] = carry + total;
+    if (tile == nt - 1 && threadIdx.x == 0) {
+      off[N] = carry + total;
+      if (d_total) *d_total = carry + total;
+    }
     __syncthreads();
   }
 }
@@ -381,7 +385,7 @@ __global__ void k_crc_final(BlockDesc *blocks, const uint32_t *d_n_blocks, const
 }  // namespace
 
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
-                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, hipStream_t s) {
+                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, uint32_t *d_total, hipStream_t s) {
   if (!N) return;
   (void)scan_tmp;
   // the per-position length array is not needed: it holds the two scans'
@@ -391,7 +395,8 @@ void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *
   const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, nt));
   PCBZ_LAUNCH(k_r1_marks, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, aggs_m);
   PCBZ_LAUNCH(k_r1_counts, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, aggs_m, runstart, aggs_s);
-  PCBZ_LAUNCH(k_r1_write, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, runstart, aggs_s, off, rle);
+  PCBZ_LAUNCH(k_r1_write, dim3(gt), dim3(kTThreads), 0, s, band_start, n_bands, x, N, runstart, aggs_s, off, rle,
+              d_total);
 }
 
 void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
