@@ -87,10 +87,10 @@ __global__ void k_sel_bases(const uint32_t *d_nb, BlockCode *codes, uint32_t *gr
   *d_n_groups = acc;
 }
 
-// One workgroup per 128 selector groups, four lanes per group (each sums
+// One workgroup per 64 selector groups, four lanes per group (each sums
 // the costs of every fourth symbol; the lanes then combine their sums).
 constexpr int kSelLanes = 4;
-constexpr int kSelGroups = 128;
+constexpr int kSelGroups = 64;
 constexpr int kSelThreads = kSelGroups * kSelLanes;
 
 __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym, const uint32_t *d_nb,
