@@ -925,15 +925,45 @@ __global__ void k_min_block(const uint32_t *blk_start, const uint32_t *d_nb, uin
   if (threadIdx.x == 0) *d_min_m = red[0];
 }
 
-__global__ void k_bwt_emit(const uint32_t *sa, const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start,
-                           const uint32_t *d_nb, uint8_t *L, BlockCode *codes) {
+// L[j] = the byte before rotation sa[j] (cyclic in its block); the slot of
+// each block's rotation 0 is its orig_ptr.  Tiles of 4096 positions, 16
+// consecutive per thread: one vector load of sa, the block from the tile's
+// block table, 16 independent byte gathers in flight, one 16-byte store.
+__global__ __launch_bounds__(kTThreads) void k_bwt_emit(const uint32_t *sa, const uint8_t *rle, const uint32_t *d_N,
+                                                        const uint32_t *blk_start, const uint32_t *d_nb, uint8_t *L,
+                                                        BlockCode *codes) {
   const uint32_t N = *d_N, nb = *d_nb;
-  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
-    const uint32_t g = sa[j];
-    const uint32_t b = block_of(blk_start, nb, j);
-    const uint32_t s = blk_start[b], e = blk_start[b + 1];
-    L[j] = rle[g == s ? e - 1 : g - 1];
-    if (g == s) codes[b].orig_ptr = j - s;
+  const uint32_t nt = (N + kTTile - 1) / kTTile;
+  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    const TileBlocks tb(blk_start, nb, tile * kTTile);
+    const uint32_t j0 = tile * kTTile + threadIdx.x * kTItems;
+    uint32_t g[kTItems], src[kTItems];
+    load16(sa, j0, N, g);
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) {
+      const uint32_t j = j0 + i;
+      src[i] = 0;
+      if (j < N) {
+        uint32_t s, e;
+        const uint32_t b = tb.find(j, s, e);
+        src[i] = g[i] == s ? e - 1 : g[i] - 1;
+        if (g[i] == s) codes[b].orig_ptr = j - s;
+      }
+    }
+    uint32_t c[kTItems];
+#pragma unroll
+    for (int i = 0; i < kTItems; i++) c[i] = j0 + i < N ? rle[src[i]] : 0u;
+    if (j0 + kTItems <= N) {
+      uint32_t wv[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        wv[q] = c[4 * q] | (c[4 * q + 1] << 8) | (c[4 * q + 2] << 16) | (c[4 * q + 3] << 24);
+      *(uint4 *)(L + j0) = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kTItems; i++)
+        if (j0 + i < N) L[j0 + i] = (uint8_t)c[i];
+    }
   }
 }
 
@@ -1095,7 +1125,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   }
   if (d_left) PCBZ_LAUNCH(k_bwt_left, dim3(1), dim3(1), 0, s, du[u], w.d_fail, d_left);
   if (seg_mask && pinned_u) *seg_mask = mask_out;
-  PCBZ_LAUNCH(k_bwt_emit, dim3(g), dim3(256), 0, s, sa, rle, d_N, blk_start, d_nb, L, codes);
+  PCBZ_LAUNCH(k_bwt_emit, dim3(std::max<uint32_t>(1, std::min<uint32_t>(kGridCap, (n_max + kTTile - 1) / kTTile))),
+              dim3(kTThreads), 0, s, sa, rle, d_N, blk_start, d_nb, L, codes);
   return rounds;
 }
 
