@@ -375,8 +375,6 @@ struct Work {
   uint32_t *tfreq, *code_words, *group_base;
   uint32_t *prefix, *sym_bits, *sym_off, *blk_sym_start, *word_start, *band_len;
   uint64_t *frame_len;
-  void *scan_tmp;
-  size_t scan_n;  // elements the scan state is sized for
   float *feat, *logits;  // selector features [band][64][64][4] and logits [band][4]
   // sizes
   uint32_t max_blocks, n_rle_max, max_chunks, max_sym, max_groups, max_words;
@@ -476,10 +474,6 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.frame_len = A.get<uint64_t>(P.frames.size());
   // data bits <= 9 per symbol (a 9-bit code is always feasible), header < 20 KB
   w.max_words = (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, ((uint64_t)w.max_sym * 9 / 8 + (uint64_t)S * 20600) / 4 + S);
-  size_t scan_n = std::max<size_t>((size_t)w.max_sym + 2, radix_counts_words((uint32_t)nr, S));
-  w.scan_tmp = A.get<uint8_t>(scan_tmp_bytes(scan_n));
-  w.scan_n = scan_n;
-  w.bw.scan_tmp = w.scan_tmp;
   return A.off;
 }
 
@@ -692,7 +686,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   launch_gather2(w.band_start, nbands, w.cb, w.choice, w.chosen, P.ntot, s);
   trace_stage("rle1");
   // first run-length stage, block cuts, CRCs
-  launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.scan_tmp, w.rle, w.ctr + 3, s);
+  launch_rle1_2(w.band_start, nbands, w.chosen, N, w.runstart, w.r1len, w.r1off, w.rle, w.ctr + 3, s);
   launch_cut2(w.bands, nbands, w.band_start, N, w.runstart, w.r1off, w.slots, w.slot_count, w.ctr + 8, w.blocks,
               w.blk_raw_start, w.blk_rle_start, w.crc_chunk_base, w.ctr + 1, w.ctr + 2, s);
   // the block CRCs run beside the suffix sort (only the header bits need them)
@@ -740,7 +734,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   launch_pack_prefix(w.ctr + 1, nb, w.blocks, w.codes, w.mw.used, w.sel, w.lens, w.prefix, cs);
   if (ctx->side) HIPCHK(ctx, hipEventRecord(ctx->fev[2], cs));
   launch_pack2(w.ctr + 1, nb, w.blocks, w.codes, w.sel, w.lens, w.code_words, w.sym, w.ctr + 5, max_sym, w.prefix,
-               w.sym_bits, w.sym_off, w.blk_sym_start, w.scan_tmp, w.frames, (uint32_t)P.frames.size(), w.bands,
+               w.sym_bits, w.sym_off, w.blk_sym_start, w.frames, (uint32_t)P.frames.size(), w.bands,
                w.choice, w.band_len, w.frame_len, w.word_start, w.ctr + 7, max_words, ctx->side ? ctx->fev[2] : nullptr,
                s);
   trace_stage(nullptr);

@@ -466,7 +466,7 @@ constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-t
 //                  counts of the elements that stay unresolved;
 //   k_rnd_compact  exclusive scan of those flags and the compaction.
 // Each scan takes its carry by reducing the tile aggregates in front of its
-// tile itself (see scan.hip for why there is no look-back).
+// tile itself (no look-back: see the tile-scan helpers).
 constexpr int kRThreads = kTThreads;
 constexpr int kRItems = kTItems;
 constexpr uint32_t kRTile = kTTile;
@@ -983,7 +983,7 @@ uint32_t grid_for(uint64_t n) {
 template <int ITEMS>
 int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, bool iota_vals,
                  const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
-                 uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+                 uint32_t *d_count_n, hipStream_t s) {
   constexpr uint32_t TILE = kRsThreads * ITEMS;
   int cur = 0;
   if (n_max <= 1 || bits <= 0) {
@@ -998,7 +998,6 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
   RsSeg sg{blk_start, blk_start ? totals + 256 : nullptr, d_nb};
   if (blk_start)
     PCBZ_LAUNCH(k_rs_tile_base, dim3(1), dim3(256), 0, s, blk_start, d_nb, TILE, (uint32_t *)sg.tile_base);
-  (void)scan_tmp;
   const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
   for (int shift = 0; shift < bits; shift += 8) {
     PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, sg, shift, counts,
@@ -1031,12 +1030,10 @@ size_t radix_counts_words(uint32_t n_max, uint32_t nb_max) {
 // values are the positions 0..n-1 and vals[0] is not read.
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
                bool iota_vals, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
-               uint32_t *d_count_n, void *scan_tmp, hipStream_t s) {
+               uint32_t *d_count_n, hipStream_t s) {
   if (items <= 8)
-    return radix_sort_t<8>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n,
-                           scan_tmp, s);
-  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n,
-                          scan_tmp, s);
+    return radix_sort_t<8>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n, s);
+  return radix_sort_t<16>(keys, vals, d_n, n_max, bits, iota_vals, blk_start, d_nb, nb_max, counts, d_count_n, s);
 }
 
 // Prefix doubling over every block.  With `pinned_u` the unresolved count and
@@ -1068,7 +1065,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   // the values are the rotations, i.e. the positions: the first pass makes them
   // sorted block by block (segmented), so the passes cover the bytes only
   int cur = radix_sort(keys, vals, du[0], n_max, 8 * nbytes, items, true, blk_start, d_nb, nb_max,
-                       w.counts, w.d_count_n, w.scan_tmp, s);
+                       w.counts, w.d_count_n, s);
   const int rbits = bits_for(n_max - 1);
   const ptrdiff_t maxg_at = w.d_maxg - w.d_u;  // read back together with the counts
   int u = 0;  // which count slot holds the current unresolved count
@@ -1118,7 +1115,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
       uint64_t *kk[2] = {keys[cur], keys[cur ^ 1]};
       uint32_t *vv[2] = {vals[cur], vals[cur ^ 1]};
       if (radix_sort(kk, vv, du[u], n_cur, 2 * rbits, items, false, nullptr, nullptr, 0, w.counts, w.d_count_n,
-                     w.scan_tmp, s) == 1)
+                     s) == 1)
         cur ^= 1;
     }
     compared *= 2;

@@ -486,13 +486,12 @@ void launch_pack_prefix(const uint32_t *d_nb, uint32_t max_blocks, const BlockDe
 void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
                   const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words, const uint16_t *sym,
                   const uint32_t *d_n_sym, uint32_t max_sym, const uint32_t *prefix, uint32_t *sym_bits,
-                  uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp, const FrameOut *frames,
+                  uint32_t *sym_off, uint32_t *blk_sym_start, const FrameOut *frames,
                   uint32_t n_frames, const BandDesc *bands, const uint8_t *choice, uint32_t *band_len,
                   uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
                   hipEvent_t prefix_ready, hipStream_t s) {
   PCBZ_LAUNCH(k_blk_sym_start, dim3((max_blocks + 256) / 256), dim3(256), 0, s, d_nb, codes, blk_sym_start);
   // sym_bits holds the tile sums (tiles + 1 <= max_sym + 1 words)
-  (void)scan_tmp;
   const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (max_sym + kTTile - 1) / kTTile));
   PCBZ_LAUNCH(k_sym_sums, dim3(gt), dim3(kTThreads), 0, s, sym, d_n_sym, d_nb, blk_sym_start, codes, sel, lens,
               sym_bits);

@@ -112,7 +112,11 @@ __device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) {
 // Building blocks of the fused scans (a scan whose input is computed on the
 // fly and whose consumer runs in the same kernel): tiles of 4096 elements,
 // 256 threads x 16; the carry of a tile is the reduction of the tile
-// aggregates in front of it, which each workgroup sums itself.
+// aggregates in front of it, which each workgroup sums itself.  (A single
+// pass with decoupled look-back measured slower: device-scope status polls
+// across the XCDs cost about a microsecond each.)  Sums wrap mod 2^32, so
+// differences of prefix values inside any segment whose own total stays
+// below 2^32 are exact.
 constexpr int kTThreads = 256;
 constexpr int kTItems = 16;
 constexpr uint32_t kTTile = kTThreads * kTItems;
@@ -291,14 +295,7 @@ struct FrameOut {
   uint32_t band_base;  // first band of this frame in the band table
 };
 
-// scan.hip: device-wide scans over n elements (n read from d_n when non-null,
-// capped by n_max).  `tmp` needs scan_tmp_bytes(n_max) bytes.  In-place is
-// allowed.
-size_t scan_tmp_bytes(size_t n_max);
-void scan_exclusive_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
-                        uint32_t *d_total, hipStream_t s);
-void scan_inclusive_max_u32(const uint32_t *in, uint32_t *out, const uint32_t *d_n, uint32_t n_max, void *tmp,
-                            hipStream_t s);
+// fill.hip
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);  // one word, device to device, as a kernel
 
@@ -323,7 +320,7 @@ void launch_gather_forced(const FrameOut *frames, uint32_t n_frames, uint8_t *fo
 // rle1.hip
 // d_total (may be null) also receives the output length, off[N]
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
-                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, uint32_t *d_total, hipStream_t s);
+                   uint32_t *len, uint32_t *off, uint8_t *rle, uint32_t *d_total, hipStream_t s);
 void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
                  const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
                  uint32_t *err, BlockDesc *blocks, uint32_t *blk_raw_start, uint32_t *blk_rle_start,
@@ -349,14 +346,13 @@ struct BwtWork {
   uint32_t *goff;       // [N+1] position of each element inside its group (all ones: resolved)
   uint32_t *gstart;     // [N+1] compact position of each unresolved element's group start
   uint32_t *aggs;       // [rnd_aggs_words] tile aggregates of a doubling round's two scans
-  void *scan_tmp;
 };
 size_t radix_counts_words(uint32_t n_max, uint32_t nb_max);
 size_t seg_bound_words(uint32_t n_max);
 size_t rnd_aggs_words(uint32_t n_max);
 int radix_sort(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint32_t n_max, int bits, int items,
                bool iota_vals, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t nb_max, uint32_t *counts,
-               uint32_t *d_count_n, void *scan_tmp, hipStream_t s);
+               uint32_t *d_count_n, hipStream_t s);
 int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint32_t *d_nb, uint32_t nb_max,
             const uint32_t *blk_start, BwtWork w, uint32_t *sa, uint8_t *L, BlockCode *codes, int max_rounds,
             int items, uint32_t *pinned_u, uint64_t *seg_mask, uint32_t *d_left, hipStream_t s);
@@ -401,7 +397,7 @@ void launch_pack_prefix(const uint32_t *d_nb, uint32_t max_blocks, const BlockDe
 void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *blocks, BlockCode *codes,
                   const uint8_t *sel, const uint8_t *lens, const uint32_t *code_words, const uint16_t *sym,
                   const uint32_t *d_n_sym, uint32_t max_sym, const uint32_t *prefix, uint32_t *sym_bits,
-                  uint32_t *sym_off, uint32_t *blk_sym_start, void *scan_tmp, const FrameOut *frames,
+                  uint32_t *sym_off, uint32_t *blk_sym_start, const FrameOut *frames,
                   uint32_t n_frames, const BandDesc *bands, const uint8_t *choice, uint32_t *band_len,
                   uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
                   hipEvent_t prefix_ready, hipStream_t s);

@@ -385,9 +385,8 @@ __global__ void k_crc_final(BlockDesc *blocks, const uint32_t *d_n_blocks, const
 }  // namespace
 
 void launch_rle1_2(const uint32_t *band_start, uint32_t n_bands, const uint8_t *x, uint32_t N, uint32_t *runstart,
-                   uint32_t *len, uint32_t *off, void *scan_tmp, uint8_t *rle, uint32_t *d_total, hipStream_t s) {
+                   uint32_t *len, uint32_t *off, uint8_t *rle, uint32_t *d_total, hipStream_t s) {
   if (!N) return;
-  (void)scan_tmp;
   // the per-position length array is not needed: it holds the two scans'
   // tile aggregates (2 * (tiles + 1) <= N + 5 words)
   const uint32_t nt = (N + kTTile - 1) / kTTile;
