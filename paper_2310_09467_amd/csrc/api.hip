@@ -643,8 +643,7 @@ void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
                 0xFu, s);
   trace_stage("judge");
   if (!P.tasks.empty()) {
-    fill_u32(w.hist, 0, (size_t)P.tasks.size() * 65536, s);
-    fill_u32((uint32_t *)w.score, 0, P.tasks.size() * 2, s);
+    // the caller has cleared w.hist and w.score
     launch_judge2(w.tasks, (uint32_t)P.tasks.size(), w.tile_task, w.tile_local, (uint32_t)P.tile_task.size(), w.cb,
                   w.seg_first, w.seg_last, w.hist, ctx->d_tq, w.score, forced, s);
   }
@@ -666,7 +665,19 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
   const uint32_t N = (uint32_t)P.ntot;
   const bool eager = tu.rounds == 0;
   trace_stage("arrange");
-  fill_u32(w.ctr, 0, 64, s);
+  {
+    // every buffer the call accumulates into, cleared by one launch: the
+    // counters, the judge's pair histograms and scores, the block CRC
+    // accumulators and the symbol and table counts
+    ZeroSpans z;
+    z.add(w.ctr, 64);
+    z.add(w.hist, P.tasks.size() * 65536);
+    z.add(w.score, P.tasks.size() * 2);
+    z.add(w.crc_acc, w.max_blocks);
+    z.add(w.freq, (size_t)w.max_blocks * kMaxAlpha);
+    z.add(w.tfreq, (size_t)w.max_blocks * kMaxGroups * kMaxAlpha);
+    zero_spans(z, s);
+  }
   if (P.use_forced()) {
     launch_gather_forced(w.frames, (uint32_t)P.frames.size(), w.forced, s);
     launch_validate_forced(w.bands, nbands, w.forced, w.ctr, s);
@@ -1106,6 +1117,10 @@ int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, c
   std::vector<UploadItem> items;
   if ((st = stage_plan(ctx, P, w, s, items))) return st;
   if ((st = enqueue_upload(ctx, items, s))) return st;
+  ZeroSpans z;
+  z.add(w.hist, P.tasks.size() * 65536);
+  z.add(w.score, P.tasks.size() * 2);
+  zero_spans(z, s);
   enqueue_judge(ctx, P, w, s);
   launch_choose2(w.bands, (uint32_t)P.bands.size(), w.task_of, w.score, w.tasks, nullptr, d_choice, d_entropy,
                  d_score, s);

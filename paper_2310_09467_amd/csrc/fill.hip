@@ -10,6 +10,12 @@ __global__ void k_fill(uint32_t *p, uint32_t v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+__global__ void k_zero_spans(ZeroSpans z) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int k = 0; k < z.count; k++)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < z.n[k]; i += stride) z.p[k][i] = 0;
+}
+
 }  // namespace
 
 void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
@@ -21,6 +27,15 @@ void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   PCBZ_LAUNCH(k_fill, dim3((uint32_t)blocks), dim3(256), 0, s, p, v, n);
+}
+
+void zero_spans(const ZeroSpans &z, hipStream_t s) {
+  size_t most = 0;
+  for (int k = 0; k < z.count; k++) most = z.n[k] > most ? z.n[k] : most;
+  if (most == 0) return;
+  size_t blocks = (most + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  PCBZ_LAUNCH(k_zero_spans, dim3((uint32_t)blocks), dim3(256), 0, s, z);
 }
 
 }  // namespace pcbz

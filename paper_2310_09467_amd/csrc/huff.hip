@@ -363,7 +363,6 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
 void launch_huff2(const uint16_t *sym, const uint32_t *d_nb, uint32_t max_blocks, uint32_t max_groups,
                   BlockCode *codes, const uint32_t *freq, uint8_t *cost, uint32_t *tfreq, uint32_t *group_base,
                   uint32_t *d_n_groups, uint8_t *sel, uint8_t *lens, uint32_t *code_words, hipStream_t s) {
-  fill_u32(tfreq, 0, (size_t)max_blocks * kMaxGroups * kMaxAlpha, s);
   PCBZ_LAUNCH(k_tab_init, dim3(max_blocks), dim3(256), 0, s, d_nb, codes, freq, cost);
   PCBZ_LAUNCH(k_sel_bases, dim3(1), dim3(64), 0, s, d_nb, codes, group_base, d_n_groups);
   for (int it = 0; it < 4; it++) {

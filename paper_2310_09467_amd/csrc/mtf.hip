@@ -599,7 +599,6 @@ __global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const ui
 void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32_t *blk_start, const uint32_t *d_nb, uint32_t max_blocks,
                  uint32_t max_chunks, MtfWork w, BlockCode *codes, uint16_t *sym, uint32_t *freq,
                  uint32_t *d_n_sym, hipStream_t s) {
-  fill_u32(freq, 0, (size_t)max_blocks * kMaxAlpha, s);
   PCBZ_LAUNCH(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
   const uint32_t *cb = w.chunk_block;
   PCBZ_LAUNCH(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used_chunk);

@@ -296,6 +296,20 @@ struct FrameOut {
 };
 
 // fill.hip
+// Word ranges cleared by one launch.
+struct ZeroSpans {
+  uint32_t *p[8];
+  size_t n[8];
+  int count = 0;
+  void add(void *ptr, size_t words) {
+    if (ptr && words && count < 8) {
+      p[count] = (uint32_t *)ptr;
+      n[count] = words;
+      count++;
+    }
+  }
+};
+void zero_spans(const ZeroSpans &z, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);  // one word, device to device, as a kernel
 

@@ -411,7 +411,6 @@ void launch_cut2(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_s
 void launch_crc2(const uint8_t *x, uint32_t N, BlockDesc *blocks, const uint32_t *d_n_blocks, uint32_t max_blocks,
                  const uint32_t *blk_raw_start, const uint32_t *xpow_chunk, const uint32_t *xpow_byte,
                  const uint32_t *xpow2, uint32_t *crc_acc, hipStream_t s) {
-  fill_u32(crc_acc, 0, max_blocks, s);
   const uint32_t chunks = (N + kCrcChunk - 1) / kCrcChunk;
   const uint32_t grid = (chunks + 255) / 256;  // one chunk per thread
   if (!grid) return;
