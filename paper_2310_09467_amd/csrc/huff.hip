@@ -28,6 +28,7 @@ constexpr int kMaxItems = 2 * kMaxAlpha + 4;
 __global__ __launch_bounds__(256) void k_tab_init(const uint32_t *d_nb, BlockCode *codes, const uint32_t *freq,
                                                   uint8_t *cost) {
   __shared__ uint32_t f[kMaxAlpha];
+  __shared__ uint64_t P[kMaxAlpha];  // running sums of f
   __shared__ uint32_t lo[kMaxGroups], hi[kMaxGroups];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
@@ -40,28 +41,35 @@ __global__ __launch_bounds__(256) void k_tab_init(const uint32_t *d_nb, BlockCod
   if (threadIdx.x == 0) {
     codes[b].n_groups = G;
     codes[b].n_sel = (nmtf + kGroupSize - 1) / kGroupSize;
+    // group g takes symbols from `start` until its count times the groups
+    // left reaches the remaining count, keeping one symbol for each later
+    // group.  With the running sums P (non-decreasing) that end is found by
+    // binary search instead of a symbol-by-symbol walk.
+    uint64_t run = 0;
+#pragma unroll 8
+    for (uint32_t s = 0; s < alpha; s++) {
+      run += f[s];
+      P[s] = run;
+    }
     uint64_t remaining = nmtf;
     uint32_t start = 0;
     for (uint32_t g = 0; g < G; g++) {
       const uint32_t left = G - g;
-      uint64_t acc = 0;
+      const uint64_t before = start > 0 ? P[start - 1] : 0ull;
       uint32_t end;
       if (g == G - 1) {
         end = alpha - 1;
-        for (uint32_t s = start; s <= end; s++) acc += f[s];
       } else {
-        uint32_t s = start;
-        for (;;) {
-          acc += f[s];
-          if (acc * left >= remaining) break;
-          if (alpha - 1 - s == left - 1) break;
-          s++;
+        uint32_t a = start, z = alpha - 1;  // first s in [start, alpha - 1] with (P[s] - before) * left >= remaining
+        while (a < z) {
+          const uint32_t mid = (a + z) >> 1;
+          if ((P[mid] - before) * left >= remaining) z = mid; else a = mid + 1;
         }
-        end = s;
+        end = min(a, alpha - left);
       }
       lo[g] = start;
       hi[g] = end;
-      remaining -= acc;
+      remaining -= P[end] - before;
       start = end + 1;
     }
   }
