@@ -77,6 +77,8 @@ def lib():
             "orc_mtf_rle2": (sz, [vp, sz, vp, vp, vp]),
             "orc_package_merge": (None, [vp, i32, i32, vp]),
             "orc_canonical_codes": (None, [vp, i32, vp]),
+            "orc_huff_init_ranges": (None, [vp, i32, i32, u64, vp]),
+            "orc_huff_select": (None, [vp, sz, vp, i32, vp]),
             "orc_huff_tables": (i32, [vp, sz, i32, vp, vp, vp, vp]),
             "orc_block_stream": (i32, [vp, sz, u32, u32, vp, sz, vp]),
             "orc_band_streams": (i32, [vp, sz, u32, vp, sz, vp, vp]),
@@ -250,6 +252,26 @@ def canonical_codes(lens):
     code = np.zeros(lens.size, np.uint32)
     lib().orc_canonical_codes(_P(lens), lens.size, _P(code))
     return code
+
+
+def huff_init_ranges(freq, G):
+    """Last symbol of each of the G initial table ranges (E11)."""
+    freq = np.ascontiguousarray(freq, np.uint32)
+    end = np.zeros(G, np.int32)
+    lib().orc_huff_init_ranges(_P(freq), freq.size, G, int(freq.astype(np.uint64).sum()), _P(end))
+    return end
+
+
+def huff_select(sym, cost):
+    """Table per group of 50 symbols for cost tables cost[G][alpha] (E12 a)."""
+    sym = np.ascontiguousarray(sym, np.uint16)
+    cost = np.asarray(cost, np.uint32)
+    G = cost.shape[0]
+    c = np.zeros((G, 258), np.uint32)
+    c[:, : cost.shape[1]] = cost
+    sel = np.zeros((sym.size + 49) // 50, np.uint8)
+    lib().orc_huff_select(_P(sym), sym.size, _P(c), G, _P(sel))
+    return sel
 
 
 def huff_tables(sym, alpha):

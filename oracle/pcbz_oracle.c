@@ -533,26 +533,21 @@ void orc_canonical_codes(const uint8_t *len, int n, uint32_t *code) {
   }
 }
 
-/* E9..E12: table count by symbol count, initial tables from contiguous
- * ranges of equal cumulative frequency, then four rounds of (choose the
- * cheapest table per group of 50 symbols, count, rebuild lengths). */
-int orc_huff_tables(const uint16_t *sym, size_t n_mtf, int alpha, int *n_groups, uint32_t *n_sel, uint8_t *sel,
-                    uint8_t *len) {
-  uint32_t freq[258], cost[6][258], tf[6][258], w[258];
-  size_t i, g_i, nsel = (n_mtf + 49) / 50;
-  int G, g, s, it, start = 0;
-  uint64_t remaining = n_mtf;
-  G = n_mtf < 200 ? 2 : n_mtf < 800 ? 3 : n_mtf < 2400 ? 4 : n_mtf < 6000 ? 5 : 6;
-  if (G > alpha) G = alpha;
-  memset(freq, 0, sizeof(freq));
-  for (i = 0; i < n_mtf; i++) freq[sym[i]]++;
-  /* E11 */
+/* E11: the initial partition of the alphabet 0..alpha-1 into G contiguous
+ * ranges.  Range g takes symbols from where range g-1 stopped and closes at
+ * the first symbol where its running count reaches the remaining total
+ * divided by the ranges left (acc * left >= remaining, in integers), or
+ * earlier if every later range still needs one symbol of its own; the last
+ * range takes the rest.  end[g] receives the last symbol of range g. */
+void orc_huff_init_ranges(const uint32_t *freq, int alpha, int G, uint64_t total, int *end) {
+  uint64_t remaining = total;
+  int g, s, start = 0;
   for (g = 0; g < G; g++) {
-    int left = G - g, end;
+    int left = G - g;
     uint64_t acc = 0;
     if (g == G - 1) {
-      end = alpha - 1;
-      for (s = start; s <= end; s++) acc += freq[s];
+      end[g] = alpha - 1;
+      for (s = start; s <= alpha - 1; s++) acc += freq[s];
     } else {
       s = start;
       for (;;) {
@@ -561,34 +556,60 @@ int orc_huff_tables(const uint16_t *sym, size_t n_mtf, int alpha, int *n_groups,
         if (alpha - 1 - s == left - 1) break;
         s++;
       }
-      end = s;
+      end[g] = s;
     }
-    for (s = 0; s < alpha; s++) cost[g][s] = (s >= start && s <= end) ? 0 : 1;
     remaining -= acc;
-    start = end + 1;
+    start = end[g] + 1;
   }
+}
+
+/* E12 (a): for each group of 50 symbols (the last one shorter) the table
+ * with the smallest summed cost; equal sums go to the lowest table. */
+void orc_huff_select(const uint16_t *sym, size_t n_mtf, const uint32_t *cost /* [G][258] */, int G,
+                     uint8_t *sel) {
+  size_t i, g_i, nsel = (n_mtf + 49) / 50;
+  int g;
+  for (g_i = 0; g_i < nsel; g_i++) {
+    size_t lo = g_i * 50, hi = lo + 50 < n_mtf ? lo + 50 : n_mtf;
+    uint64_t best_c = 0;
+    int best = 0;
+    for (g = 0; g < G; g++) {
+      uint64_t c = 0;
+      for (i = lo; i < hi; i++) c += cost[g * 258 + sym[i]];
+      if (g == 0 || c < best_c) {
+        best_c = c;
+        best = g;
+      }
+    }
+    sel[g_i] = (uint8_t)best;
+  }
+}
+
+/* E9..E12: table count by symbol count, initial tables from contiguous
+ * ranges of equal cumulative frequency, then four rounds of (choose the
+ * cheapest table per group of 50 symbols, count, rebuild lengths). */
+int orc_huff_tables(const uint16_t *sym, size_t n_mtf, int alpha, int *n_groups, uint32_t *n_sel, uint8_t *sel,
+                    uint8_t *len) {
+  uint32_t freq[258], cost[6 * 258], tf[6][258], w[258];
+  size_t i, nsel = (n_mtf + 49) / 50;
+  int G, g, s, it, end[6], start;
+  G = n_mtf < 200 ? 2 : n_mtf < 800 ? 3 : n_mtf < 2400 ? 4 : n_mtf < 6000 ? 5 : 6;
+  if (G > alpha) G = alpha;
+  memset(freq, 0, sizeof(freq));
+  for (i = 0; i < n_mtf; i++) freq[sym[i]]++;
+  /* E11: cost 0 inside a table's initial range, 1 outside */
+  orc_huff_init_ranges(freq, alpha, G, n_mtf, end);
+  for (g = 0, start = 0; g < G; start = end[g] + 1, g++)
+    for (s = 0; s < 258; s++) cost[g * 258 + s] = (s >= start && s <= end[g]) ? 0 : 1;
   /* E12 */
   for (it = 0; it < 4; it++) {
-    for (g_i = 0; g_i < nsel; g_i++) {
-      size_t lo = g_i * 50, hi = lo + 50 < n_mtf ? lo + 50 : n_mtf;
-      uint64_t best_c = 0;
-      int best = 0;
-      for (g = 0; g < G; g++) {
-        uint64_t c = 0;
-        for (i = lo; i < hi; i++) c += cost[g][sym[i]];
-        if (g == 0 || c < best_c) {
-          best_c = c;
-          best = g;
-        }
-      }
-      sel[g_i] = (uint8_t)best;
-    }
+    orc_huff_select(sym, n_mtf, cost, G, sel);
     memset(tf, 0, sizeof(tf));
     for (i = 0; i < n_mtf; i++) tf[sel[i / 50]][sym[i]]++;
     for (g = 0; g < G; g++) {
       for (s = 0; s < alpha; s++) w[s] = tf[g][s] > 0 ? tf[g][s] : 1;
       orc_package_merge(w, alpha, 17, len + g * 258);
-      for (s = 0; s < alpha; s++) cost[g][s] = len[g * 258 + s];
+      for (s = 0; s < alpha; s++) cost[g * 258 + s] = len[g * 258 + s];
     }
   }
   *n_groups = G;

@@ -60,6 +60,8 @@ void orc_bwt(const uint8_t *blk, size_t m, uint32_t *sa, uint8_t *L, uint32_t *o
 size_t orc_mtf_rle2(const uint8_t *L, size_t m, uint16_t *sym, uint32_t *freq, uint32_t *n_in_use);
 void orc_package_merge(const uint32_t *w, int n, int limit, uint8_t *len);
 void orc_canonical_codes(const uint8_t *len, int n, uint32_t *code);
+void orc_huff_init_ranges(const uint32_t *freq, int alpha, int G, uint64_t total, int *end /* [G] */);
+void orc_huff_select(const uint16_t *sym, size_t n_mtf, const uint32_t *cost /* [G*258] */, int G, uint8_t *sel);
 int orc_huff_tables(const uint16_t *sym, size_t n_mtf, int alpha, int *n_groups, uint32_t *n_sel, uint8_t *sel,
                     uint8_t *len /* [6*258] */);
 int orc_block_stream(const uint8_t *rle, size_t m, uint32_t block_crc, uint32_t level, uint8_t *out, size_t cap,

@@ -306,3 +306,54 @@ def test_ratio_close_to_bzip2_9(orc):
     s, _ = orc.band_streams(raw, 9)
     ref = len(bz2.compress(raw.tobytes(), 9))
     assert len(s) < 1.05 * ref
+
+
+# ------------------------------------------------------------------ hand-derived table and stream pins
+# These fix the choices that several valid outputs leave open (every
+# selector vector decodes, optimal code lengths are not unique), so that a
+# plausible slip -- a strict comparison in the initial ranges, a tie going to
+# a later table, packages before leaves on equal weight, another start value
+# for the code lengths -- changes a value below.
+@pytest.mark.parametrize("case", GOLD["huff_init_ranges"]["cases"])
+def test_huff_initial_ranges_hand_cases(orc, case):
+    assert orc.huff_init_ranges(case["freq"], case["G"]).tolist() == case["end"]
+
+
+def test_huff_select_tie_goes_to_lowest_table(orc):
+    g = GOLD["huff_select_tie"]
+    assert orc.huff_select(g["sym"], g["cost"]).tolist() == g["sel"]
+
+
+def _groups_to_sym(groups):
+    if isinstance(groups, str):  # the clamp case: ten groups of s0, six of s1, four of s2
+        return np.array([0] * 500 + [1] * 300 + [2] * 200, np.uint16)
+    return np.array([s for grp in groups for s, c in grp for _ in range(c)], np.uint16)
+
+
+@pytest.mark.parametrize("case", GOLD["huff_tables"]["cases"])
+def test_huff_tables_hand_cases(orc, case):
+    sym = _groups_to_sym(case["groups"])
+    G, sel, lens = orc.huff_tables(sym, case["alpha"])
+    assert G == case["G"]
+    assert sel.tolist() == case["sel"]
+    assert lens.tolist() == case["len"]
+
+
+@pytest.mark.parametrize("case", GOLD["package_merge_ties"]["cases"])
+def test_package_merge_tie_order(orc, case):
+    w = np.array(case["w"], np.uint32)
+    ln = orc.package_merge(w, case["limit"])
+    assert ln.tolist() == case["len"]
+    assert int((w.astype(np.int64) * ln).sum()) == opt_cost_exhaustive(case["w"], case["limit"])
+
+
+def test_stream_of_aaa_hand_derived(orc):
+    g = GOLD["stream_aaa"]
+    raw = np.frombuffer(g["block"].encode(), np.uint8)
+    crc = _rev32(zlib.crc32(_REV8[raw].tobytes()) & 0xFFFFFFFF)
+    bits = "".join(format(crc if v == "crc" else v, f"0{n}b") for _, n, v in g["fields"])
+    bits += "0" * (-len(bits) % 8)
+    want = int(bits, 2).to_bytes(len(bits) // 8, "big")
+    got = orc.block_stream(raw, crc, g["level"])
+    assert got == want
+    assert bz2.decompress(got) == raw.tobytes()
