@@ -375,7 +375,7 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
         t_sel = timed(single, 5)
         judged = ctx.selector_stats()
         sel_bytes = sum(lens)
-        t_bsel = timed(lambda: ctx.compress_batch_into(dev, None, bprm, outs), 5)
+        t_bsel = timed(lambda: ctx.compress_batch_into(dev, None, bprm, outs, sel, tau), 5)
         ctx.set_selector(None)
         t_plain = timed(single, 5)
         exh = sum(len(b) for b in blobs)

@@ -22,7 +22,9 @@
  * A context is not thread-safe: use one per host thread.
  *
  * Errors are returned as pcbz_status codes; no exception or abort crosses the
- * ABI.  pcbz_last_error() describes the last failure of a context.
+ * ABI.  pcbz_last_error() describes the last failure of a context.  Entry
+ * points declare an int result holding a pcbz_status value: C leaves the
+ * width of an enum to the compiler, an int keeps the ABI fixed.
  */
 #ifndef PCBZ_H
 #define PCBZ_H
@@ -54,6 +56,7 @@ typedef struct {
 } pcbz_params;
 
 typedef struct pcbz_ctx pcbz_ctx;
+typedef struct pcbz_selector pcbz_selector; /* learned arrangement selector (below) */
 
 /* Creates a context on HIP device `hip_device`.  hbm_budget_bytes caps the
  * device workspace (0 = no cap).  Returns PCBZ_EDEVICE if the device cannot
@@ -62,8 +65,12 @@ int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes);
 void pcbz_destroy(pcbz_ctx *ctx);
 const char *pcbz_last_error(const pcbz_ctx *ctx);
 
-/* Band plan (bands of R = max(1, floor((100000*level-19)/(2*pitch*W))) lens
- * rows) and an upper bound on the container size. */
+/* Band plan: the frame is cut into blocks before bzip2 coding (Sec. 2.1.3,
+ * where the paper's blocks follow the thread count); here a band is
+ * R = max(1, floor((100000*level-19)/(2*pitch*W))) whole lens rows, so that
+ * every arrangement of a band holds the same pixels and fits one bzip2 block.
+ * Host only: writes the band count and an upper bound on the container size
+ * (either pointer may be NULL).  PCBZ_EINVAL for invalid parameters. */
 int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound);
 
 /* Entropy judgement only (Sec. 2.1.2, Eq. 1).  Writes d_choice[n_bands] (the
@@ -74,8 +81,14 @@ int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound)
 int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
                uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream);
 
-/* Compresses one frame into a PCBZ container in d_out (device).  With
- * d_forced_choice (device, n_bands ids) the judgement is skipped.  The call
+/* The compression pipeline of Fig. 1c and Fig. 2a: arrangements (Sec. 2.1.1),
+ * entropy judgement per band (Sec. 2.1.2), bzip2 coding of the chosen
+ * arrangement (Sec. 2.1.3) and the header with one 8-bit arrangement id per
+ * band (Sec. 2.1.4).  Compresses one frame into a PCBZ container in d_out
+ * (device, out_cap bytes, written only when the container fits: otherwise
+ * PCBZ_ENOSPC with the required size in *out_len).  With d_forced_choice
+ * (device, n_bands ids) the judgement is skipped.  When a selector is set on
+ * the context (pcbz_set_selector) confident bands skip the judgement.  The call
  * synchronises `stream` and writes the container length to *out_len (host).
  * d_choice_out (device, may be NULL) receives the per-band ids used.
  * Container: "PCBZ", u8 version 1, u8 level, u16 pitch, u32 H, u32 W,
@@ -86,22 +99,35 @@ int pcbz_compress(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame
                   const uint8_t *d_forced_choice, uint8_t *d_out, size_t out_cap, size_t *out_len,
                   uint8_t *d_choice_out, void *stream);
 
-/* Compresses n frames of possibly different shapes in one pass over all of
- * their blocks.  Arrays are host arrays of n entries; d_prevs and
- * d_forced may be NULL or hold NULL entries.  lens (host) receives each
- * container length; each frame's bytes equal pcbz_compress of that frame
- * alone.  Returns the first error; frames whose container exceeds caps[i]
- * get PCBZ_ENOSPC with lens[i] set to the required size. */
+/* The pipeline of pcbz_compress for n frames of possibly different shapes in
+ * one pass over all of their blocks (the paper codes blocks in parallel,
+ * Sec. 2.1.3).  Arrays are host arrays of n entries; d_prevs and d_forced
+ * may be NULL or hold NULL entries.  sel (NULL: every band is judged) and
+ * min_conf apply to this call only, in place of any selector set on the
+ * context; a band whose predicted probability reaches min_conf (>= 0) skips
+ * the judgement.  lens (host) receives each container length; each frame's
+ * bytes equal pcbz_compress of that frame alone with the same selector.
+ * Returns the first error; frames whose container exceeds caps[i] get
+ * PCBZ_ENOSPC with lens[i] set to the required size. */
 int pcbz_compress_batch(pcbz_ctx *ctx, uint32_t n, const pcbz_params *prm, const uint16_t *const *d_frames,
-                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced, uint8_t *const *d_outs,
-                        const size_t *caps, size_t *lens, void *stream);
+                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced,
+                        const pcbz_selector *sel, float min_conf, uint8_t *const *d_outs, const size_t *caps,
+                        size_t *lens, void *stream);
 
-/* Reads a container header (host memory). */
+/* Unpacks the header of a container in host memory (Sec. 2.1.4: the 8-bit
+ * arrangement id is stored in the header; Fig. 2b: decompression starts by
+ * reading it): frame geometry, level and candidate flags into *out, band
+ * count into *n_bands (may be NULL).  PCBZ_EDATA for a bad magic, version
+ * or length. */
 int pcbz_peek(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands);
 
-/* Decompresses a container held in host memory into d_out (device,
- * out_elems >= H*W).  d_prev is required when a band uses PCBZ_VIEW_DT.
- * Every block CRC is checked (PCBZ_EDATA on mismatch). */
+/* The decompression pipeline of Fig. 1c and Fig. 2b: unpack the header,
+ * decode each band's bzip2 streams, invert the arrangement named by the
+ * band's id (Sec. 2.1, last paragraph before 2.1.1).  Decompresses a
+ * container held in host memory into d_out (device, out_elems >= H*W, else
+ * PCBZ_ENOSPC).  d_prev is required when a band uses PCBZ_VIEW_DT
+ * (PCBZ_ENEEDPREV).  Every block CRC is checked (PCBZ_EDATA on mismatch or
+ * any malformed field).  Synchronises `stream`. */
 int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
                     size_t out_elems, void *stream);
 
@@ -151,7 +177,6 @@ int pcbz_trace_read(pcbz_ctx *ctx, char *names, size_t name_stride, double *ms, 
  * that device but not used by two calls at once.  Unset it from every
  * context (pcbz_set_selector(ctx, NULL, 0)) before pcbz_selector_free.
  * ------------------------------------------------------------------------ */
-typedef struct pcbz_selector pcbz_selector;
 
 size_t pcbz_selector_num_params(void);
 /* params: host FP32 array of pcbz_selector_num_params() values or NULL
@@ -178,6 +203,23 @@ int pcbz_selector_forward(pcbz_selector *sel, const float *d_feat, uint32_t n, f
  * be NULL). */
 int pcbz_selector_gradients(pcbz_selector *sel, const float *d_feat, const uint8_t *d_label, uint32_t n,
                             const float *class_w4, float *d_grad, float *loss, void *stream);
+/* Copies one tensor of the last pcbz_selector_gradients (or train_step) call
+ * on `sel` to host memory, so that the kernels can be checked layer by layer.
+ * n = that call's sample count; bytes must equal the tensor's size.
+ *   which 0..4  bf16 bits, layer inputs as rounded for the products: 0 the
+ *               normalised features [n][64][64][4], 1 conv1 output
+ *               [n][32][32][32], 2 conv2 output [n][16][16][32], 3 conv3
+ *               output [n][2048] (= FC4 input, flattened (y, x, c)), 4 FC4
+ *               output [n][64];
+ *   which 5..8  FP32 pre-activations (products plus bias, before ReLU):
+ *               5 conv1 [n*1024][32], 6 conv2 [n*256][32], 7 conv3
+ *               [n*64][32], 8 FC4 [n][64];
+ *   which 9, 10 FP32 logits [n][4] and dloss/dlogits [n][4];
+ *   which 11..15 bf16 bits of dloss/dpre after the ReLU mask, as fed to the
+ *               gradient products: 11 FC5 [n][4], 12 FC4 [n][64], 13 conv3
+ *               [n*64][32], 14 conv2 [n*256][32], 15 conv1 [n*1024][32].
+ * PCBZ_EINVAL for an unknown `which`, a wrong size or no call yet. */
+int pcbz_selector_inspect(const pcbz_selector *sel, int which, void *host, size_t bytes);
 /* One AdamW step (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay)
  * on the gradient of the batch. */
 int pcbz_selector_train_step(pcbz_selector *sel, const float *d_feat, const uint8_t *d_label, uint32_t n,
@@ -186,9 +228,11 @@ int pcbz_selector_train_step(pcbz_selector *sel, const float *d_feat, const uint
  * C[M][N] (FP32) = A[M][K] x B[K][N], A and B row-major bfloat16 bits. */
 int pcbz_gemm_bf16(int M, int N, int K, const uint16_t *d_a, const uint16_t *d_b, float *d_c, void *stream);
 
-/* Makes pcbz_compress / pcbz_compress_batch consult `sel` (NULL: judge every
- * band).  min_conf > 1 judges every band; 0 trusts every prediction.  Bands
- * of frames with a caller-forced array keep the caller's ids. */
+/* Makes pcbz_compress consult `sel` (NULL: judge every band); the
+ * single-frame call has no selector argument, so the context carries it
+ * (pcbz_compress_batch takes its selector as an argument instead).
+ * min_conf > 1 judges every band; 0 trusts every prediction.  Bands of
+ * frames with a caller-forced array keep the caller's ids. */
 int pcbz_set_selector(pcbz_ctx *ctx, pcbz_selector *sel, float min_conf);
 /* Bands seen by the selector in the last compress call and how many of
  * them were judged (fell below min_conf). */
@@ -246,7 +290,10 @@ typedef struct {
 
 int pcbz_server_create(int hip_device, size_t hbm_budget, uint32_t n_workers, size_t max_batch_bytes,
                        const pcbz_selector *sel, float min_conf, pcbz_server **out);
-/* Returns PCBZ_ENOMEM if the frame can never fit the pool. */
+/* Returns PCBZ_ENOMEM if the frame can never fit the pool, PCBZ_ENEEDPREV if
+ * the temporal arrangement is its only candidate and its camera has sent no
+ * earlier frame of this shape.  A frame that fails once batched (a device
+ * error, say) gets its own status in its result; the others complete. */
 int pcbz_server_submit(pcbz_server *srv, const pcbz_params *prm, const uint16_t *host_frame, uint32_t camera,
                        uint64_t tag);
 /* Up to max finished results; waits up to timeout_ms (-1: until one is

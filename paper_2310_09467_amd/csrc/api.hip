@@ -155,6 +155,8 @@ struct pcbz_ctx {
   std::vector<pcbz::TuneRec> tune;
   std::string tune_path;
   int eager_items = 8;
+  int tune_rounds = 0;          // round budget the tuner gives graphs (0: the eager call's rounds + 1)
+  int tune_failed_replays = 0;  // the last tuning saw a replay that did not reproduce the eager bytes
   // learned arrangement selector (optional): confident bands skip the judge
   pcbz_selector *sel = nullptr;
   float min_conf = 1.f;
@@ -951,10 +953,13 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
     if ((st = prepare(ctx, fin, P, w))) return st;
     std::vector<UploadItem> items;
     const int choices[2] = {8, 16};
+    // the replays write into the caller's output buffers: after one that did
+    // not reproduce the eager result those bytes are rewritten before returning
+    bool outs_stale = false;
     for (int c : choices) {
       Tuning tu;
       tu.radix_items = c;
-      tu.rounds = r.rounds;
+      tu.rounds = ctx->tune_rounds > 0 ? ctx->tune_rounds : r.rounds;
       tu.seg_mask = r.seg_mask;
       if ((st = stage_plan(ctx, P, w, s, items))) return st;
       GraphEntry *g = nullptr;
@@ -968,12 +973,23 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
       if ((st = launch_graph(ctx, g, s, nullptr))) return st;
       if ((st = read_results(ctx, P, w, s, l2, ctr))) return st;
       const double ms = ms_since(t0);
-      if (ctr[9] != 0 || l2 != lens) continue;  // schedule did not reproduce the eager result
+      if (ctr[9] != 0 || l2 != lens) {  // schedule did not reproduce the eager result
+        outs_stale = true;
+        continue;
+      }
+      outs_stale = false;  // this replay rewrote every output with the eager bytes
       if (ms < best) {
         best = ms;
         r.items = c;
         r.ms = ms;
+        r.rounds = tu.rounds;
       }
+    }
+    if (r.items == 0) r.rounds = (int)ctx->last_rounds + 1;
+    ctx->tune_failed_replays = 0;
+    if (outs_stale) {
+      ctx->tune_failed_replays = 1;
+      if ((st = run_compress(ctx, fin, s, le, {}))) return st;
     }
     ctx->tune.push_back(r);
     save_tuning(ctx);
@@ -1051,6 +1067,8 @@ int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
   if (tp) c->tune_path = tp;
   const char *ri = getenv("PCBZ_RADIX_ITEMS");  // radix tile of eager calls: 8 or 16
   if (ri && (atoi(ri) == 8 || atoi(ri) == 16)) c->eager_items = atoi(ri);
+  const char *tr = getenv("PCBZ_TUNE_ROUNDS");  // fixed round budget for tuned graphs (1..40)
+  if (tr && atoi(tr) >= 1 && atoi(tr) <= 40) c->tune_rounds = atoi(tr);
   load_tuning(c);
   *out = c;
   return PCBZ_OK;
@@ -1143,18 +1161,26 @@ int pcbz_compress(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame
 }
 
 int pcbz_compress_batch(pcbz_ctx *ctx, uint32_t n, const pcbz_params *prm, const uint16_t *const *d_frames,
-                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced, uint8_t *const *d_outs,
-                        const size_t *caps, size_t *lens, void *stream) {
+                        const uint16_t *const *d_prevs, const uint8_t *const *d_forced, const pcbz_selector *sel,
+                        float min_conf, uint8_t *const *d_outs, const size_t *caps, size_t *lens, void *stream) {
   if (!ctx || !prm || !d_frames || !d_outs || !caps || !lens) return fail(ctx, PCBZ_EINVAL, "null argument");
+  if (sel && !(min_conf >= 0.f)) return fail(ctx, PCBZ_EINVAL, "min_conf must be >= 0");
   if (n == 0) return PCBZ_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   std::vector<FrameIn> fin(n);
   for (uint32_t i = 0; i < n; i++)
     fin[i] = FrameIn{prm[i], d_frames[i], d_prevs ? d_prevs[i] : nullptr, d_forced ? d_forced[i] : nullptr, d_outs[i],
                      caps[i]};
+  // the call's selector replaces the context's (pcbz_set_selector) for its duration
+  pcbz_selector *const ctx_sel = ctx->sel;
+  const float ctx_conf = ctx->min_conf;
+  ctx->sel = const_cast<pcbz_selector *>(sel);
+  ctx->min_conf = sel ? min_conf : 1.f;
   std::vector<size_t> out;
   int st = (!ctx->use_graphs || getenv("PCBZ_NO_GRAPH")) ? run_compress(ctx, fin, (hipStream_t)stream, out, {})
                                                        : run_compress_graph(ctx, fin, (hipStream_t)stream, out);
+  ctx->sel = ctx_sel;
+  ctx->min_conf = ctx_conf;
   for (uint32_t i = 0; i < n && i < out.size(); i++) lens[i] = out[i];
   return st;
 }

@@ -946,7 +946,10 @@ __global__ __launch_bounds__(kTThreads) void k_bwt_emit(const uint32_t *sa, cons
       if (j < N) {
         uint32_t s, e;
         const uint32_t b = tb.find(j, s, e);
-        src[i] = g[i] == s ? e - 1 : g[i] - 1;
+        // a slot left unresolved by a capped round budget (the call is then
+        // redone) may hold any value: keep the read inside the block
+        const uint32_t gi = g[i] >= s && g[i] < e ? g[i] : s;
+        src[i] = gi == s ? e - 1 : gi - 1;
         if (g[i] == s) codes[b].orig_ptr = j - s;
       }
     }

@@ -468,7 +468,20 @@ struct SelWork {
   float *acc = nullptr, *pre1 = nullptr, *pre2 = nullptr, *pre3 = nullptr, *pre4 = nullptr, *logits = nullptr,
         *dlog = nullptr, *dx = nullptr, *dcol = nullptr, *split = nullptr, *loss = nullptr, *cw = nullptr;
   uint32_t *err = nullptr;
+  uint32_t last_n = 0;  // samples of the last gradients call (0: none yet)
 };
+
+// The backward pass keeps each layer's bf16 gradient (dL/dpre after the ReLU
+// mask) in its own slice of g16, so a finished call can be inspected layer by
+// layer: per sample 4 (FC5), 64 (FC4), 64x32 (conv3), 256x32 (conv2),
+// 1024x32 (conv1) values.
+constexpr long kG16Sample = 4 + 64 + 2048 + 8192 + 32768;
+inline uint16_t *g16_layer(const SelWork &w, int layer, long n) {
+  long off = 0;
+  const long per[6] = {0, 32768, 8192, 2048, 64, 4};  // by layer 1..5
+  for (int l = 5; l > layer; l--) off += per[l] * n;
+  return w.g16 + off;
+}
 
 }  // namespace pcbz
 
@@ -517,7 +530,7 @@ int ensure_work(pcbz_selector *S, uint32_t n) {
   A(dalloc(&w.col3, N * 64 * 288));
   A(dalloc(&w.x3, N * 2048));
   A(dalloc(&w.x4, N * 64));
-  A(dalloc(&w.g16, N * 1024 * 32));
+  A(dalloc(&w.g16, N * kG16Sample));
   A(dalloc(&w.acc, N * 1024 * 32));
   A(dalloc(&w.pre1, N * 1024 * 32));
   A(dalloc(&w.pre2, N * 256 * 32));
@@ -583,26 +596,27 @@ void conv_backward(int n, int H, int C, const uint16_t *col, const uint16_t *g16
 void backward(pcbz_selector *S, uint32_t n, hipStream_t s) {
   SelWork &w = S->w;
   float *g = S->g;
+  uint16_t *g5 = g16_layer(w, 5, n), *g4 = g16_layer(w, 4, n), *g3 = g16_layer(w, 3, n), *g2 = g16_layer(w, 2, n),
+           *g1 = g16_layer(w, 1, n);
   // FC 64 -> 4 (no activation)
-  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 4)), dim3(256), 0, s, w.dlog, (const float *)nullptr, (long)n * 4,
-              w.g16);
-  gemm_bf16(4, 64, (int)n, w.g16, 1, 4, w.x4, 64, 1, g + kW5, 64, 1, w.split, s);
-  PCBZ_LAUNCH(k_bias_grad, dim3(4), dim3(256), 0, s, w.g16, (long)n, 4, g + kB5);
-  gemm_bf16((int)n, 64, 4, w.g16, 4, 1, S->p16 + kW5, 64, 1, w.dx, 64, 1, nullptr, s);
+  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 4)), dim3(256), 0, s, w.dlog, (const float *)nullptr, (long)n * 4, g5);
+  gemm_bf16(4, 64, (int)n, g5, 1, 4, w.x4, 64, 1, g + kW5, 64, 1, w.split, s);
+  PCBZ_LAUNCH(k_bias_grad, dim3(4), dim3(256), 0, s, g5, (long)n, 4, g + kB5);
+  gemm_bf16((int)n, 64, 4, g5, 4, 1, S->p16 + kW5, 64, 1, w.dx, 64, 1, nullptr, s);
   // FC 2048 -> 64, ReLU
-  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 64)), dim3(256), 0, s, w.dx, w.pre4, (long)n * 64, w.g16);
-  gemm_bf16(64, 2048, (int)n, w.g16, 1, 64, w.x3, 2048, 1, g + kW4, 2048, 1, w.split, s);
-  PCBZ_LAUNCH(k_bias_grad, dim3(64), dim3(256), 0, s, w.g16, (long)n, 64, g + kB4);
-  gemm_bf16((int)n, 2048, 64, w.g16, 64, 1, S->p16 + kW4, 2048, 1, w.dx, 2048, 1, nullptr, s);
+  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 64)), dim3(256), 0, s, w.dx, w.pre4, (long)n * 64, g4);
+  gemm_bf16(64, 2048, (int)n, g4, 1, 64, w.x3, 2048, 1, g + kW4, 2048, 1, w.split, s);
+  PCBZ_LAUNCH(k_bias_grad, dim3(64), dim3(256), 0, s, g4, (long)n, 64, g + kB4);
+  gemm_bf16((int)n, 2048, 64, g4, 64, 1, S->p16 + kW4, 2048, 1, w.dx, 2048, 1, nullptr, s);
   // conv3 (16 -> 8), input x2
-  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 2048)), dim3(256), 0, s, w.dx, w.pre3, (long)n * 2048, w.g16);
-  conv_backward((int)n, 16, 32, w.col3, w.g16, S->p16 + kW3, g + kW3, g + kB3, w.dcol, w.dx, w.split, s);
+  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 2048)), dim3(256), 0, s, w.dx, w.pre3, (long)n * 2048, g3);
+  conv_backward((int)n, 16, 32, w.col3, g3, S->p16 + kW3, g + kW3, g + kB3, w.dcol, w.dx, w.split, s);
   // conv2 (32 -> 16), input x1
-  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 8192)), dim3(256), 0, s, w.dx, w.pre2, (long)n * 8192, w.g16);
-  conv_backward((int)n, 32, 32, w.col2, w.g16, S->p16 + kW2, g + kW2, g + kB2, w.dcol, w.dx, w.split, s);
+  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 8192)), dim3(256), 0, s, w.dx, w.pre2, (long)n * 8192, g2);
+  conv_backward((int)n, 32, 32, w.col2, g2, S->p16 + kW2, g + kW2, g + kB2, w.dcol, w.dx, w.split, s);
   // conv1 (64 -> 32), input x0: no input gradient
-  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 32768)), dim3(256), 0, s, w.dx, w.pre1, (long)n * 32768, w.g16);
-  conv_backward((int)n, 64, 4, w.col1, w.g16, S->p16 + kW1, g + kW1, g + kB1, w.dcol, (float *)nullptr, w.split, s);
+  PCBZ_LAUNCH(k_relu_grad, dim3(grid1((long)n * 32768)), dim3(256), 0, s, w.dx, w.pre1, (long)n * 32768, g1);
+  conv_backward((int)n, 64, 4, w.col1, g1, S->p16 + kW1, g + kW1, g + kB1, w.dcol, (float *)nullptr, w.split, s);
 }
 
 int upload_params(pcbz_selector *S, const float *host) {
@@ -750,6 +764,7 @@ int pcbz_selector_gradients(pcbz_selector *S, const float *d_feat, const uint8_t
       hipMemcpy(S->w.cw, class_w4 ? class_w4 : one, 4 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(S->w.err, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
     return PCBZ_EDEVICE;
+  S->w.last_n = 0;
   forward(S, d_feat, n, s);
   PCBZ_LAUNCH(k_softmax_ce, dim3(1), dim3(256), 0, s, S->w.logits, d_label, S->w.cw, (int)n, S->w.dlog, S->w.loss,
               S->w.err);
@@ -763,7 +778,43 @@ int pcbz_selector_gradients(pcbz_selector *S, const float *d_feat, const uint8_t
       hipMemcpy(&h_err, S->w.err, sizeof h_err, hipMemcpyDeviceToHost) != hipSuccess)
     return PCBZ_EDEVICE;
   if (loss) *loss = h_loss;
+  S->w.last_n = n;
   return h_err ? PCBZ_EINVAL : PCBZ_OK;
+}
+
+int pcbz_selector_inspect(const pcbz_selector *S, int which, void *host, size_t bytes) {
+  if (!S || !host || S->w.last_n == 0) return PCBZ_EINVAL;
+  const SelWork &w = S->w;
+  const long n = w.last_n;
+  const void *src = nullptr;
+  long count = 0;
+  size_t elem = 2;
+  switch (which) {
+    case 0: src = w.x0, count = n * 16384; break;
+    case 1: src = w.x1, count = n * 32768; break;
+    case 2: src = w.x2, count = n * 8192; break;
+    case 3: src = w.x3, count = n * 2048; break;
+    case 4: src = w.x4, count = n * 64; break;
+    case 5: src = w.pre1, count = n * 32768, elem = 4; break;
+    case 6: src = w.pre2, count = n * 8192, elem = 4; break;
+    case 7: src = w.pre3, count = n * 2048, elem = 4; break;
+    case 8: src = w.pre4, count = n * 64, elem = 4; break;
+    case 9: src = w.logits, count = n * 4, elem = 4; break;
+    case 10: src = w.dlog, count = n * 4, elem = 4; break;
+    case 11: case 12: case 13: case 14: case 15: {
+      const int layer = 16 - which;  // 11 -> FC5 ... 15 -> conv1
+      const long per[6] = {0, 32768, 8192, 2048, 64, 4};
+      src = g16_layer(w, layer, n);
+      count = per[layer] * n;
+      break;
+    }
+    default: return PCBZ_EINVAL;
+  }
+  if (bytes != (size_t)count * elem) return PCBZ_EINVAL;
+  if (hipSetDevice(S->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host, src, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return PCBZ_EDEVICE;
+  return PCBZ_OK;
 }
 
 int pcbz_selector_train_step(pcbz_selector *S, const float *d_feat, const uint8_t *d_label, uint32_t n,

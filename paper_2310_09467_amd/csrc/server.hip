@@ -151,6 +151,7 @@ struct pcbz_server {
   std::vector<pcbz_selector *> sels;
   size_t max_batch_bytes = 0;
   uint32_t max_batch_frames = 64;
+  float min_conf = 1.f;
   bool stop = false;
   uint32_t in_flight = 0;  // frames inside worker calls
   uint64_t submitted = 0, completed = 0, batches = 0, batched_frames = 0;
@@ -251,10 +252,23 @@ void worker_main(pcbz_server *s, int wi) {
       s->in_flight += (uint32_t)batch.size();
     }
     const double t0 = now_ms();
-    // run what is admitted; on a workspace shortfall, split the batch
+    // frames whose upload failed keep their status and stay out of the call
+    std::vector<std::shared_ptr<Job>> failed;
+    {
+      std::vector<std::shared_ptr<Job>> ok;
+      for (auto &j : batch) (j->status == PCBZ_OK ? ok : failed).push_back(j);
+      if (!failed.empty()) {
+        finish(s, failed);
+        batch.swap(ok);
+      }
+    }
+    // run what is admitted; on a workspace shortfall, split the batch; when a
+    // call of several frames fails otherwise, run them one by one so that
+    // each frame gets its own status
     size_t k0 = 0;
+    bool singly = false;
     while (k0 < batch.size()) {
-      size_t k1 = batch.size();
+      size_t k1 = singly ? k0 + 1 : batch.size();
       int rc = PCBZ_OK;
       for (;;) {
         const uint32_t n = (uint32_t)(k1 - k0);
@@ -272,10 +286,16 @@ void worker_main(pcbz_server *s, int wi) {
           outs[i] = j.out->p;
           caps[i] = j.cap;
         }
-        rc = pcbz_compress_batch(ctx, n, prm.data(), fr.data(), pv.data(), nullptr, outs.data(), caps.data(),
+        rc = pcbz_compress_batch(ctx, n, prm.data(), fr.data(), pv.data(), nullptr,
+                                 s->sels.empty() ? nullptr : s->sels[wi], s->min_conf, outs.data(), caps.data(),
                                  lens.data(), st);
         if (rc == PCBZ_ENOMEM && n > 1) {
           k1 = k0 + n / 2;
+          continue;
+        }
+        if (rc != PCBZ_OK && n > 1) {
+          singly = true;
+          k1 = k0 + 1;
           continue;
         }
         size_t tot = 0;
@@ -310,6 +330,7 @@ void worker_main(pcbz_server *s, int wi) {
       k0 = k1;
     }
     const double t1 = now_ms();
+    if (batch.empty()) continue;
     std::lock_guard<std::mutex> lk(s->mu);
     uint64_t raw = 0;
     for (auto &j : batch) raw += j->raw;
@@ -333,9 +354,11 @@ int pcbz_server_create(int hip_device, size_t hbm_budget, uint32_t n_workers, si
   if (hipSetDevice(hip_device) != hipSuccess) return PCBZ_EDEVICE;
   pcbz_server *s = new pcbz_server();
   s->device = hip_device;
+  s->min_conf = min_conf;
   // an eighth of the budget holds frames, outputs and camera state (about
   // 2.3 bytes per input byte); the rest is split between the workers'
   // workspaces (about 100 bytes per input byte of a batch)
+  if (sel && !(min_conf >= 0.f)) return PCBZ_EINVAL;
   const size_t pool = hbm_budget / 8;
   const size_t per_ws = (hbm_budget - pool) / n_workers;
   s->max_batch_bytes = max_batch_bytes ? max_batch_bytes : per_ws / 128;
@@ -373,7 +396,6 @@ int pcbz_server_create(int hip_device, size_t hbm_budget, uint32_t n_workers, si
         return rc;
       }
       s->sels.push_back(ws);
-      pcbz_set_selector(c, ws, min_conf);
     }
   }
   for (uint32_t w = 0; w < n_workers; w++) s->workers.emplace_back(worker_main, s, (int)w);
@@ -402,6 +424,9 @@ int pcbz_server_submit(pcbz_server *s, const pcbz_params *prm, const uint16_t *h
   std::shared_ptr<Job> old;
   auto it = s->last.find(key);
   if (it != s->last.end()) old = it->second;
+  // the first frame of a camera and shape has no previous frame: it is coded
+  // without the temporal candidate, so it needs another one
+  if (!old && (prm->cand_mask & 7u) == 0) return PCBZ_ENEEDPREV;
   if ((prm->cand_mask & 8u) && old) {
     j->prev_job = old;
     old->prev_refs++;
@@ -493,7 +518,6 @@ void pcbz_server_destroy(pcbz_server *s) {
     (void)hipStreamSynchronize(s->upload);
     (void)hipStreamDestroy(s->upload);
   }
-  for (size_t i = 0; i < s->ctxs.size(); i++) pcbz_set_selector(s->ctxs[i], nullptr, 0.f);
   for (pcbz_selector *w : s->sels) pcbz_selector_free(w);
   for (pcbz_ctx *c : s->ctxs) pcbz_destroy(c);
   s->done.clear();

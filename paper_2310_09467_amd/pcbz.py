@@ -25,7 +25,8 @@ EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_
            "pcbz_selector_get_params", "pcbz_selector_set_params", "pcbz_selector_save", "pcbz_selector_load",
            "pcbz_features", "pcbz_selector_forward", "pcbz_selector_gradients", "pcbz_selector_train_step",
            "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats", "pcbz_set_graphs", "pcbz_server_create",
-           "pcbz_server_submit", "pcbz_server_poll", "pcbz_server_stats", "pcbz_server_destroy")
+           "pcbz_server_submit", "pcbz_server_poll", "pcbz_server_stats", "pcbz_server_destroy",
+           "pcbz_selector_inspect")
 
 
 class PcbzError(RuntimeError):
@@ -79,7 +80,7 @@ def load():
             "pcbz_plan": (i32, [pp, vp, vp]),
             "pcbz_judge": (i32, [vp, pp, vp, vp, vp, vp, vp, vp]),
             "pcbz_compress": (i32, [vp, pp, vp, vp, vp, vp, sz, vp, vp, vp]),
-            "pcbz_compress_batch": (i32, [vp, u32, pp, vp, vp, vp, vp, vp, vp, vp]),
+            "pcbz_compress_batch": (i32, [vp, u32, pp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp]),
             "pcbz_peek": (i32, [vp, sz, pp, vp]),
             "pcbz_decompress": (i32, [vp, vp, sz, vp, vp, sz, vp]),
             "pcbz_last_stats": (i32, [vp, vp, vp, vp, vp]),
@@ -97,6 +98,7 @@ def load():
             "pcbz_selector_gradients": (i32, [vp, vp, vp, u32, vp, vp, vp, vp]),
             "pcbz_selector_train_step": (i32, [vp, vp, vp, u32, vp, ctypes.c_float, ctypes.c_float, vp, vp]),
             "pcbz_gemm_bf16": (i32, [i32, i32, i32, vp, vp, vp, vp]),
+            "pcbz_selector_inspect": (i32, [vp, i32, vp, sz]),
             "pcbz_set_selector": (i32, [vp, vp, ctypes.c_float]),
             "pcbz_selector_stats": (i32, [vp, vp, vp]),
             "pcbz_set_graphs": (i32, [vp, i32]),
@@ -233,8 +235,10 @@ class Context:
             return blob, choice.cpu().numpy()
         return blob
 
-    def compress_batch(self, frames, prevs=None, params=None, forced=None):
-        """Compresses several frames in one pass; returns a list of containers (bytes)."""
+    def compress_batch(self, frames, prevs=None, params=None, forced=None, selector=None, min_conf=0.9):
+        """Compresses several frames in one pass; returns a list of containers
+        (bytes).  `selector` (a Selector, or None for the exhaustive judgement)
+        and min_conf apply to this call only."""
         torch = _torch()
         n = len(frames)
         fs = [to_device(f) for f in frames]
@@ -258,14 +262,17 @@ class Context:
         d_outs = VP(*[o.data_ptr() for o in outs])
         d_forced = None if fcs is None else VP(*[0 if c is None else c.data_ptr() for c in fcs])
         lens = (ctypes.c_size_t * n)()
-        st = load().pcbz_compress_batch(self._h, n, prm, d_frames, d_prevs, d_forced, d_outs, caps, lens, _stream())
+        st = load().pcbz_compress_batch(self._h, n, prm, d_frames, d_prevs, d_forced,
+                                        None if selector is None else selector._h, float(min_conf), d_outs, caps,
+                                        lens, _stream())
         if st:
             self._err(st, "compress_batch")
         return [outs[i][: lens[i]].cpu().numpy().tobytes() for i in range(n)]
 
-    def compress_batch_into(self, dev_frames, dev_prevs, params, outs):
+    def compress_batch_into(self, dev_frames, dev_prevs, params, outs, selector=None, min_conf=0.9):
         """Device-level batch call: device int16 frames (and prevs or None),
-        Params list, device uint8 output tensors.  Returns the lengths."""
+        Params list, device uint8 output tensors, optional Selector.  Returns
+        the lengths."""
         n = len(dev_frames)
         prm = (Params * n)(*params)
         VP = ctypes.c_void_p * n
@@ -273,6 +280,7 @@ class Context:
         lens = (ctypes.c_size_t * n)()
         d_prevs = None if dev_prevs is None else VP(*[0 if p is None else p.data_ptr() for p in dev_prevs])
         st = load().pcbz_compress_batch(self._h, n, prm, VP(*[f.data_ptr() for f in dev_frames]), d_prevs, None,
+                                        None if selector is None else selector._h, float(min_conf),
                                         VP(*[o.data_ptr() for o in outs]), caps, lens, _stream())
         if st:
             self._err(st, "compress_batch")
@@ -450,6 +458,30 @@ class Selector:
         if st:
             raise PcbzError(st, "selector_gradients")
         return g, loss.value
+
+    # (name, dtype, per-sample shape) of pcbz_selector_inspect's tensors, by index
+    INSPECT = (("x0", "bf16", (64, 64, 4)), ("x1", "bf16", (32, 32, 32)), ("x2", "bf16", (16, 16, 32)),
+               ("x3", "bf16", (2048,)), ("x4", "bf16", (64,)), ("pre1", "f32", (1024, 32)),
+               ("pre2", "f32", (256, 32)), ("pre3", "f32", (64, 32)), ("pre4", "f32", (64,)),
+               ("logits", "f32", (4,)), ("dlogits", "f32", (4,)), ("g5", "bf16", (4,)), ("g4", "bf16", (64,)),
+               ("g3", "bf16", (64, 32)), ("g2", "bf16", (256, 32)), ("g1", "bf16", (1024, 32)))
+
+    def inspect(self, name, n):
+        """A tensor of the last gradients call (n samples) as a numpy array:
+        bf16 tensors come back as float32 values, FP32 ones as they are."""
+        which = [nm for nm, _, _ in self.INSPECT].index(name)
+        _, kind, shape = self.INSPECT[which]
+        count = n * int(np.prod(shape))
+        if kind == "bf16":
+            buf = np.empty(count, np.uint16)
+        else:
+            buf = np.empty(count, np.float32)
+        st = load().pcbz_selector_inspect(self._h, which, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes)
+        if st:
+            raise PcbzError(st, "selector_inspect")
+        if kind == "bf16":
+            buf = (buf.astype(np.uint32) << 16).view(np.float32)
+        return buf.reshape((n,) + shape)
 
     def train_step(self, feat, labels, class_w=None, lr=1e-3, weight_decay=1e-4):
         """One AdamW step; returns the batch loss before the step."""

@@ -128,3 +128,23 @@ def test_batch_modes_agree(orc):
     with pytest.raises(pcbz.PcbzError):
         ctx.set_graphs(3)
     ctx.close()
+
+
+def test_tuning_replay_that_fails_leaves_correct_bytes(orc, tmp_path):
+    """When a schedule tried by the autotuner does not reproduce the eager
+    result (here: a round budget of one doubling round, too few for the data),
+    the caller's buffers still end up holding the right containers."""
+    from paper_2310_09467_amd import pcbz, synth
+
+    os.environ["PCBZ_TUNE_ROUNDS"] = "1"
+    try:
+        ctx = pcbz.Context(0)
+    finally:
+        del os.environ["PCBZ_TUNE_ROUNDS"]
+    frames = [synth.config1_frame(3), synth.config1_frame(4)]
+    params = [(15, 1, 0x3)] * 2
+    ref = [orc.compress(f, None, p, lv, m)[0] for f, (p, lv, m) in zip(frames, params)]
+    assert ctx.compress_batch(frames, None, params) == ref  # the tuning call
+    assert ctx.last_stats()["bwt_rounds"] > 1  # so a one-round graph cannot reproduce it
+    assert ctx.compress_batch(frames, None, params) == ref  # the tuned choice (eager)
+    ctx.close()

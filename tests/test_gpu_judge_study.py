@@ -1,6 +1,7 @@
-"""GPU check of the judge-fidelity study: per-band lengths read from the
-container header add up to the container, the smallest candidate is never
-larger than the judged one, and the study's figures are in range."""
+"""GPU check of the judge-fidelity study against the oracle: the judged ids and
+entropies equal the oracle's judgement, every per-candidate band size equals
+the band length in the oracle's container coded with that candidate forced,
+and the study's summary follows from those sizes."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,7 @@ from paper_2310_09467_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-def test_judge_study_small():
+def test_judge_study_small(orc):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -20,15 +21,27 @@ def test_judge_study_small():
     big, _ = synth.beads_frame(450, 300, 40, 300.0, seed=13)
     rows = []
     for f, lv in ((frame, 1), (big, 2)):
-        blob = ctx.compress(f, None, 15, lv, 0x7)
-        lens = judge_study.band_lengths(blob)
-        nb = pcbz.plan(*f.shape, 15, lv, 0x7)[0]
-        assert len(lens) == nb
-        assert 20 + 5 * nb + sum(ln for _, ln in lens) == len(blob)
-        rows.append(judge_study.study_frame(ctx, f, None, 15, lv, 0x7))
+        row = judge_study.study_frame(ctx, f, None, 15, lv, 0x7)
+        choice, ent, sizes, ids = row
+        oc, _, oh = orc.judge(f, None, 15, lv, 0x7)
+        np.testing.assert_array_equal(choice, oc)
+        for c in ids:
+            np.testing.assert_allclose(ent[:, c], oh[:, c], rtol=0, atol=1e-9)
+            blob, _ = orc.compress(f, None, 15, lv, 0x7, forced_choice=np.full(len(oc), c, np.uint8))
+            info = orc.peek(blob)
+            np.testing.assert_array_equal(sizes[:, c], info["band_len"])
+            assert (info["ids"] == c).all()
+        rows.append(row)
+    s = judge_study.summarize(rows)
+    # the summary recomputed from the oracle-checked sizes by hand
+    n = agree = 0
+    judged = best = 0
     for choice, ent, sizes, ids in rows:
         for b in range(len(choice)):
-            assert min(sizes[b, c] for c in ids) <= sizes[b, int(choice[b])]
-    s = judge_study.summarize(rows)
-    assert 0.0 <= s["agreement"] <= 1.0 and s["judge_regret"] >= 0.0
-    assert 0.0 <= s["pairwise_order_agreement"] <= 1.0
+            c_best = min(ids, key=lambda c: (sizes[b, c], c))
+            agree += int(choice[b]) == c_best
+            judged += sizes[b, int(choice[b])]
+            best += sizes[b, c_best]
+            n += 1
+    assert s["bands"] == n and s["agreement"] == agree / n
+    assert s["judge_regret"] == judged / best - 1.0

@@ -33,6 +33,34 @@ def test_header_declares_binding_exports():
     assert declared_functions() == sorted(pcbz.EXPORTS)
 
 
+def declared_params():
+    """{name: [parameter declarations]} from the header."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(pcbz_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", text):
+        args = " ".join(m.group(2).split())
+        out[m.group(1)] = [] if args in ("", "void") else [a.strip() for a in args.split(",")]
+    return out
+
+
+def test_binding_argument_counts_match_header(lib):
+    decl = declared_params()
+    assert sorted(decl) == declared_functions()
+    for name, params in decl.items():
+        assert len(getattr(lib, name).argtypes) == len(params), name
+
+
+def test_batch_call_takes_selector_arguments():
+    """The batch call of the boundary takes the selector and its confidence
+    threshold as arguments, after the per-frame inputs and before the outputs."""
+    params = declared_params()["pcbz_compress_batch"]
+    names = [re.findall(r"[A-Za-z_0-9]+$", p)[0] for p in params]
+    assert names == ["ctx", "n", "prm", "d_frames", "d_prevs", "d_forced", "sel", "min_conf", "d_outs", "caps",
+                     "lens", "stream"]
+    assert params[6] == "const pcbz_selector *sel" and params[7] == "float min_conf"
+
+
 def test_library_exports_every_declared_symbol(lib):
     for name in declared_functions():
         assert hasattr(lib, name), name
