@@ -50,7 +50,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="k_rs_scatter<ITEMS>")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="serving leg length (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving leg length (0: skip)")
+    ap.add_argument("--series-frames", type=int, default=64,
+                    help="frames of the vessel time-series batch leg (0: skip)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / selector / serving legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain device-to-device copies of 256 MiB (counter calibration) and exit")
@@ -338,6 +340,60 @@ def timed(fn, reps):
     return (time.perf_counter() - t) / reps
 
 
+def series_leg(ctx, pcbz, torch, n_frames, sel_path):
+    """The vessel time series as one batch: n_frames frames of mixed size
+    (2040 x 2040, 1020 x 1020, 2040 x 1020), temporal candidate against frame
+    i - 3, all four candidates, level 9; every band of every frame in one
+    pcbz_compress_batch call.  Timed as captured-graph replays (the autotuned
+    schedule), as eager calls, and with the learned selector."""
+    from paper_2310_09467_amd import synth
+
+    log(f"time-series leg: rendering {n_frames} vessel frames")
+    series = synth.vessel_series(n_frames)
+    frames = [f for f, _ in series]
+    dev = [pcbz.to_device(f) for f in frames]
+    dprev = [None if p is None else dev[p] for _, p in series]
+    prms, outs = [], []
+    for f, (_, p) in zip(frames, series):
+        h, w = f.shape
+        mask = 0x7 if p is None else 0xF
+        prms.append(pcbz.Params(h, w, PITCH, LEVEL, mask))
+        outs.append(torch.empty(pcbz.plan(h, w, PITCH, LEVEL, mask)[1], dtype=torch.uint8, device="cuda"))
+    raw = sum(2 * f.size for f in frames)
+    log("time-series leg: tuning")
+    ctx.set_graphs(1)
+    ctx.compress_batch_into(dev, dprev, prms, outs)  # tunes the schedule, captures
+    t_graph = timed(lambda: ctx.compress_batch_into(dev, dprev, prms, outs), 3)
+    lens = ctx.compress_batch_into(dev, dprev, prms, outs)
+    ref = [outs[i][: lens[i]].cpu().numpy().tobytes() for i in range(len(frames))]
+    ctx.set_graphs(0)
+    t_eager = timed(lambda: ctx.compress_batch_into(dev, dprev, prms, outs), 3)
+    lens_e = ctx.compress_batch_into(dev, dprev, prms, outs)
+    same = lens_e == lens and all(outs[i][: lens[i]].cpu().numpy().tobytes() == ref[i] for i in range(len(frames)))
+    ctx.set_graphs(1)
+    out = {"frames": len(frames), "raw_mb": round(raw / 1e6, 2),
+           "bands": int(sum(pcbz.plan(p.h, p.w, PITCH, LEVEL, p.cand_mask)[0] for p in prms)),
+           "value": round(raw / t_graph / 1e6, 2), "unit": "MB/s", "eager_mb_s": round(raw / t_eager / 1e6, 2),
+           "ratio": round(raw / sum(lens), 4), "graph_equals_eager": same}
+    if os.path.exists(sel_path):
+        sel = pcbz.Selector.load_file(ctx, sel_path)
+        tau = 0.9
+        rep_path = sel_path.replace(".bin", "_report.json")
+        if os.path.exists(rep_path):
+            with open(rep_path) as fh:
+                tau = float(json.load(fh)["picked"]["min_conf"])
+        log("time-series leg: selector")
+        ctx.compress_batch_into(dev, dprev, prms, outs, sel, tau)
+        t_sel = timed(lambda: ctx.compress_batch_into(dev, dprev, prms, outs, sel, tau), 3)
+        lens_s = ctx.compress_batch_into(dev, dprev, prms, outs, sel, tau)
+        out.update({"selector_mb_s": round(raw / t_sel / 1e6, 2), "selector_min_conf": tau,
+                    "selector_regret": round(sum(lens_s) / sum(lens) - 1.0, 6)})
+        sel.close()
+    del dev, outs
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
     """Batched, selector and serving legs on the same frames."""
     raw = 2 * H * W * len(frames)
@@ -384,6 +440,8 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
                            "plain_single_mb_s": round(raw / t_plain / 1e6, 2),
                            "regret": round(sel_bytes / exh - 1.0, 6),
                            "bands_judged_last_frame": list(judged)}
+    if args.series_frames > 0:
+        res["time_series"] = series_leg(ctx, pcbz, torch, args.series_frames, path)
     if args.serve_seconds > 0:
         log("serving leg")
         seqs = cameras.render_sequences()
@@ -397,7 +455,7 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
         summ = cameras.summarize(results, events, src, pool, t0)
         st = srv.stats()
         srv.close()
-        ver = cameras.verify(results, src, pool, seqs, 48, sel, 0.9)
+        ver = cameras.verify(results, src, pool, seqs, None, sel, 0.9)
         res["serving"] = {"cameras": 4, "rate_per_camera": 50.0, "seconds": args.serve_seconds, "frames": summ["frames"],
                           "throughput_mb_s": round(summ["throughput_mb_s"], 2),
                           "offered_mb_s": round(summ["offered_mb_s"], 2),
@@ -407,6 +465,7 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
                           "overlap_frac": round(st["overlap_ms"] / max(st["busy_ms"], 1e-9), 3),
                           "mean_batch": round(st["batched_frames"] / max(st["batches"], 1), 2),
                           "equal_alone": f"{ver['equal_alone']}/{ver['checked']}",
+                          "distinct_frames_checked": ver["distinct"],
                           "selector_regret_checked": round(ver["regret"], 6)}
     return res
 

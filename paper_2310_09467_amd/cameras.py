@@ -161,36 +161,37 @@ def summarize(results, events, src, pool, t0):
                            "max": float(lat.max())}}
 
 
-def verify(results, src, pool, seqs, n_check, selector=None, min_conf=1.01):
-    """Re-compresses the first n_check results alone (same previous frame and
-    selector) and compares bytes; also returns the size regret of those
-    frames against judging every band."""
+def verify(results, src, pool, seqs, n_check=None, selector=None, min_conf=1.01):
+    """Compares served containers with the same frame compressed alone (same
+    previous frame and selector).  Served frames repeat (pool entries), so
+    each distinct (frame, previous frame) is compressed once and every result
+    that shares it is compared; n_check (None: all) limits the results
+    compared.  Also returns the size regret of the compared frames against
+    judging every band."""
     ctx = pcbz.Context(0)
-    if selector is not None:
-        ctx.set_selector(selector, min_conf)
-    ok, served, exhaustive = 0, 0, 0
-    tags = sorted(results)[:n_check]
+    tags = sorted(results) if n_check is None else sorted(results)[:n_check]
+    alone, exhaustive = {}, {}
+    ok, served, exh = 0, 0, 0
     for tag in tags:
         r = results[tag]
-        content, si, k = src[tag]
-        h, w = SIZES[si]
-        frame = np.ascontiguousarray(seqs[content][k][:h, :w])
-        prev = None
-        if r["prev_tag"] is not None:
-            pc, psi, pk = src[r["prev_tag"]]
-            prev = np.ascontiguousarray(seqs[pc][pk][:h, :w])
-        mask = 0xF if prev is not None else 0x7
-        alone = ctx.compress(frame, prev, PITCH, LEVEL, mask)
-        ok += alone == r["data"]
-        served += len(r["data"])
-        if selector is not None:
+        psrc = None if r["prev_tag"] is None else src[r["prev_tag"]]
+        key = (src[tag], psrc)
+        if key not in alone:
+            content, si, k = src[tag]
+            h, w = SIZES[si]
+            frame = np.ascontiguousarray(seqs[content][k][:h, :w])
+            prev = None if psrc is None else np.ascontiguousarray(seqs[psrc[0]][psrc[2]][:h, :w])
+            mask = 0xF if prev is not None else 0x7
+            ctx.set_selector(selector, min_conf) if selector is not None else ctx.set_selector(None)
+            alone[key] = ctx.compress(frame, prev, PITCH, LEVEL, mask)
             ctx.set_selector(None)
-            exhaustive += len(ctx.compress(frame, prev, PITCH, LEVEL, mask))
-            ctx.set_selector(selector, min_conf)
-        else:
-            exhaustive += len(alone)
-    ctx.set_selector(None)
-    return {"checked": len(tags), "equal_alone": ok, "regret": served / max(exhaustive, 1) - 1.0}
+            exhaustive[key] = len(ctx.compress(frame, prev, PITCH, LEVEL, mask)) if selector is not None \
+                else len(alone[key])
+        ok += alone[key] == r["data"]
+        served += len(r["data"])
+        exh += exhaustive[key]
+    ctx.close()
+    return {"checked": len(tags), "equal_alone": ok, "distinct": len(alone), "regret": served / max(exh, 1) - 1.0}
 
 
 def main():
@@ -203,7 +204,8 @@ def main():
     ap.add_argument("--selector", default=DEFAULT_SELECTOR, help="selector file, or 'none'")
     ap.add_argument("--min-conf", type=float, default=0.9)
     ap.add_argument("--no-temporal", action="store_true")
-    ap.add_argument("--verify", type=int, default=64, help="results re-compressed alone and compared")
+    ap.add_argument("--verify", type=int, default=-1,
+                    help="results compared with their frame compressed alone (-1: all, 0: none)")
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
 
@@ -232,7 +234,7 @@ def main():
                      "selector": None if sel is None else os.path.basename(args.selector),
                      "min_conf": args.min_conf, "temporal": not args.no_temporal}
     if args.verify:
-        rep["verify"] = verify(res, src, pool, seqs, args.verify, sel, args.min_conf)
+        rep["verify"] = verify(res, src, pool, seqs, None if args.verify < 0 else args.verify, sel, args.min_conf)
     out = json.dumps(rep, indent=1)
     if args.report:
         with open(args.report, "w") as fh:
