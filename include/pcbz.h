@@ -81,6 +81,24 @@ int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound)
 int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
                uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream);
 
+/* pcbz_judge for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same outputs as pcbz_judge, but the workspace (plan
+ * tables, candidate bytes, pair histograms, scores) is a fixed 48 MiB device
+ * array and the Tq table a fixed 900,002-entry array, each held once per
+ * device from the first pcbz_create on that device until the process ends.
+ * The call allocates nothing (no hipMalloc, hipHostMalloc or hipFree): the
+ * caller passes the frame and the outputs.  A frame whose workspace exceeds
+ * 48 MiB (about one 2040 x 2040 frame with four candidates) gets
+ * PCBZ_ENOMEM and nothing is written.  The plan tables are copied from
+ * pageable host memory and the call synchronises `stream` once, after that
+ * copy.  Every call on a device shares its one workspace, which keeps the last
+ * call's contents (the accumulators are cleared by each call): calls that can
+ * overlap on one device, from any context, stream or thread, race and must be
+ * serialised by the caller. */
+int pcbz_judge_noalloc(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                       uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream);
+
 /* The compression pipeline of Fig. 1c and Fig. 2a: arrangements (Sec. 2.1.1),
  * entropy judgement per band (Sec. 2.1.2), bzip2 coding of the chosen
  * arrangement (Sec. 2.1.3) and the header with one 8-bit arrangement id per

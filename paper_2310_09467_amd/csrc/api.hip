@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -162,6 +163,7 @@ struct pcbz_ctx {
   float min_conf = 1.f;
   int use_graphs = 1;  // pcbz_compress_batch: 0 eager, 1 graphs where faster, 2 graphs
   uint32_t last_sel_bands = 0, last_sel_fallback = 0;
+  std::string fixed_err;  // why the fixed workspace could not be set up (empty: it is)
 };
 
 namespace {
@@ -498,6 +500,13 @@ int ensure_arena(pcbz_ctx *ctx, size_t need) {
   return PCBZ_OK;
 }
 
+// The judge's fixed-point table Tq(c) = round(c * log2(c) * 2^20), Tq(0) =
+// Tq(1) = 0 (the summand of the pair entropy, Sec. 2.1.2, Eq. 1), computed
+// on the host in double so that the decision never depends on device math.
+void fill_tq(int64_t *t, size_t n) {
+  for (size_t c = 0; c < n; c++) t[c] = c < 2 ? 0 : (int64_t)llround((double)c * log2((double)c) * 1048576.0);
+}
+
 int ensure_tables(pcbz_ctx *ctx, uint32_t band_n_max) {
   if (!ctx->d_xpow2) {
     uint32_t x[64];
@@ -529,7 +538,7 @@ int ensure_tables(pcbz_ctx *ctx, uint32_t band_n_max) {
   if (need_tq > ctx->tq_n) {
     const size_t n = std::max<size_t>(need_tq, 900002);
     std::vector<int64_t> t(n);
-    for (size_t c = 0; c < n; c++) t[c] = c < 2 ? 0 : (int64_t)llround((double)c * log2((double)c) * 1048576.0);
+    fill_tq(t.data(), n);
     if (ctx->d_tq) HIPCHK(ctx, hipFree(ctx->d_tq));
     HIPCHK(ctx, hipMalloc((void **)&ctx->d_tq, n * sizeof(int64_t)));
     HIPCHK(ctx, hipMemcpy(ctx->d_tq, t.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -638,7 +647,7 @@ int ensure_small(pcbz_ctx *ctx) {
 }
 
 // Judge stages shared by pcbz_judge and the compress path.
-void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
+void enqueue_judge(const int64_t *tq, const Plan &P, Work &w, hipStream_t s) {
   const uint8_t *forced = P.use_forced() ? w.forced : nullptr;
   trace_stage("arrange");
   launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
@@ -647,7 +656,7 @@ void enqueue_judge(pcbz_ctx *ctx, const Plan &P, Work &w, hipStream_t s) {
   if (!P.tasks.empty()) {
     // the caller has cleared w.hist and w.score
     launch_judge2(w.tasks, (uint32_t)P.tasks.size(), w.tile_task, w.tile_local, (uint32_t)P.tile_task.size(), w.cb,
-                  w.seg_first, w.seg_last, w.hist, ctx->d_tq, w.score, forced, s);
+                  w.seg_first, w.seg_last, w.hist, tq, w.score, forced, s);
   }
 }
 
@@ -692,7 +701,7 @@ int enqueue_compress(pcbz_ctx *ctx, const Plan &P, Work &w, const Tuning &tu, hi
     if (st) return fail(ctx, st, "selector forward failed");
     launch_select(w.logits, nbands, w.bands, ctx->min_conf, w.forced, w.ctr + 14, s);
   }
-  enqueue_judge(ctx, P, w, s);
+  enqueue_judge(ctx->d_tq, P, w, s);
   launch_choose2(w.bands, nbands, w.task_of, w.score, w.tasks, P.use_forced() ? w.forced : nullptr, w.choice, nullptr,
                  nullptr, s);
   trace_stage("gather");
@@ -1035,6 +1044,46 @@ int run_compress_graph(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream
 
 int pcbz::context_device(const pcbz_ctx *ctx) { return ctx->device; }
 
+// ---------------------------------------------------------------- fixed workspace
+// pcbz_judge_noalloc takes its workspace (plan tables, candidate bytes, pair
+// histograms, segment tables, scores) from `scratch` and its Tq table from
+// `tq_fixed` instead of the context's arena.  Each device holds one copy of
+// both for as long as the process runs; in host code their names are only
+// stand-ins, so the device addresses come from hipGetSymbolAddress, once per
+// device, while pcbz_create sets that device up.
+namespace {
+constexpr size_t kScratchBytes = 48ull << 20;  // the judge of one 2040 x 2040 frame, 4 candidates: ~44 MB
+constexpr size_t kTqFixed = 900002;            // pair counts of any band up to the level-9 block limit
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+static __device__ __align__(256) int64_t tq_fixed[kTqFixed];
+
+namespace {
+std::mutex g_fixed_mu;
+uint8_t *g_scratch_ptr[kMaxDevices];
+int64_t *g_tq_fixed_ptr[kMaxDevices];
+
+// Device addresses of the fixed workspace and Tq table of the current device
+// (which is `dev`), filling the table on the device's first use.
+int setup_fixed(pcbz_ctx *ctx, int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ctx, PCBZ_EDEVICE, "device %d has no fixed workspace", dev);
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (g_scratch_ptr[dev] && g_tq_fixed_ptr[dev]) return PCBZ_OK;
+  void *ps = nullptr, *pt = nullptr;
+  HIPCHK(ctx, hipGetSymbolAddress(&ps, HIP_SYMBOL(scratch)));
+  HIPCHK(ctx, hipGetSymbolAddress(&pt, HIP_SYMBOL(tq_fixed)));
+  if (!ps || !pt) return fail(ctx, PCBZ_EDEVICE, "no device address for the fixed workspace");
+  std::vector<int64_t> t(kTqFixed);
+  fill_tq(t.data(), kTqFixed);
+  HIPCHK(ctx, hipMemcpy(pt, t.data(), kTqFixed * sizeof(int64_t), hipMemcpyHostToDevice));
+  g_tq_fixed_ptr[dev] = (int64_t *)pt;
+  g_scratch_ptr[dev] = (uint8_t *)ps;
+  return PCBZ_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
@@ -1063,6 +1112,9 @@ int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
       (void)hipStreamDestroy(c->side);
       c->side = nullptr;
     }
+  // the fixed workspace of pcbz_judge_noalloc; a failure here only disables
+  // that entry point (it then reports the error)
+  if (setup_fixed(c, hip_device) != PCBZ_OK) c->fixed_err = c->err;
   const char *tp = getenv("PCBZ_TUNE_CACHE");
   if (tp) c->tune_path = tp;
   const char *ri = getenv("PCBZ_RADIX_ITEMS");  // radix tile of eager calls: 8 or 16
@@ -1139,7 +1191,62 @@ int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, c
   z.add(w.hist, P.tasks.size() * 65536);
   z.add(w.score, P.tasks.size() * 2);
   zero_spans(z, s);
-  enqueue_judge(ctx, P, w, s);
+  enqueue_judge(ctx->d_tq, P, w, s);
+  launch_choose2(w.bands, (uint32_t)P.bands.size(), w.task_of, w.score, w.tasks, nullptr, d_choice, d_entropy,
+                 d_score, s);
+  trace_stage(nullptr);
+  HIPCHK(ctx, hipGetLastError());
+  return PCBZ_OK;
+}
+
+int pcbz_judge_noalloc(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
+                       uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream) {
+  if (!ctx || !prm || !d_frame || !d_choice) return fail(ctx, PCBZ_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  const int dev = ctx->device;
+  if (!ctx->fixed_err.empty()) return fail(ctx, PCBZ_EDEVICE, "fixed workspace unavailable: %s", ctx->fixed_err.c_str());
+  uint8_t *const base = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+  const int64_t *const tq = (dev >= 0 && dev < kMaxDevices) ? g_tq_fixed_ptr[dev] : nullptr;
+  if (!base || !tq) return fail(ctx, PCBZ_EDEVICE, "fixed workspace of device %d not set up", dev);
+  std::vector<FrameIn> fin(1);
+  fin[0] = FrameIn{*prm, d_frame, d_prev, nullptr, nullptr, 0};
+  Plan P;
+  int st = build_plan(ctx, fin, true, P);
+  if (st) return st;
+  if ((size_t)P.band_n_max + 2 > kTqFixed)
+    return fail(ctx, PCBZ_EINVAL, "band of %u bytes exceeds the fixed Tq table (%zu entries)", P.band_n_max, kTqFixed);
+  Work w{};
+  Arena meas{nullptr};
+  const size_t need = layout(meas, P, false, w);
+  if (need > kScratchBytes)
+    return fail(ctx, PCBZ_ENOMEM, "pcbz_judge_noalloc needs %zu bytes of workspace; its fixed workspace holds %zu",
+                need, kScratchBytes);
+  Arena A{base};
+  layout(A, P, false, w);
+  // plan tables from pageable host memory, in stream order after earlier work
+  // on `stream` (which may still read the workspace); the stream is
+  // synchronised before the host buffer goes away
+  auto put = [&](const void *src, size_t bytes, void *dst) -> int {
+    if (!bytes || !dst) return PCBZ_OK;
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return PCBZ_OK;
+  };
+  if ((st = put(P.bands.data(), P.bands.size() * sizeof(BandDesc), w.bands)) ||
+      (st = put(P.rows.data(), P.rows.size() * sizeof(RowItem), w.rows)) ||
+      (st = put(P.tasks.data(), P.tasks.size() * sizeof(JudgeTask), w.tasks)) ||
+      (st = put(P.tile_task.data(), P.tile_task.size() * sizeof(uint32_t), w.tile_task)) ||
+      (st = put(P.tile_local.data(), P.tile_local.size() * sizeof(uint32_t), w.tile_local)) ||
+      (st = put(P.task_of.data(), P.task_of.size() * sizeof(int32_t), w.task_of)) ||
+      (st = put(P.band_start.data(), P.band_start.size() * sizeof(uint32_t), w.band_start)) ||
+      (st = put(P.frames.data(), P.frames.size() * sizeof(FrameOut), w.frames)))
+    return st;
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  ZeroSpans z;  // the workspace keeps the previous call's contents
+  z.add(w.hist, P.tasks.size() * 65536);
+  z.add(w.score, P.tasks.size() * 2);
+  zero_spans(z, s);
+  enqueue_judge(tq, P, w, s);
   launch_choose2(w.bands, (uint32_t)P.bands.size(), w.task_of, w.score, w.tasks, nullptr, d_choice, d_entropy,
                  d_score, s);
   trace_stage(nullptr);

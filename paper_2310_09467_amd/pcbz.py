@@ -26,7 +26,7 @@ EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_
            "pcbz_features", "pcbz_selector_forward", "pcbz_selector_gradients", "pcbz_selector_train_step",
            "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats", "pcbz_set_graphs", "pcbz_server_create",
            "pcbz_server_submit", "pcbz_server_poll", "pcbz_server_stats", "pcbz_server_destroy",
-           "pcbz_selector_inspect")
+           "pcbz_selector_inspect", "pcbz_judge_noalloc")
 
 
 class PcbzError(RuntimeError):
@@ -79,6 +79,7 @@ def load():
             "pcbz_last_error": (ctypes.c_char_p, [vp]),
             "pcbz_plan": (i32, [pp, vp, vp]),
             "pcbz_judge": (i32, [vp, pp, vp, vp, vp, vp, vp, vp]),
+            "pcbz_judge_noalloc": (i32, [vp, pp, vp, vp, vp, vp, vp, vp]),
             "pcbz_compress": (i32, [vp, pp, vp, vp, vp, vp, sz, vp, vp, vp]),
             "pcbz_compress_batch": (i32, [vp, u32, pp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp]),
             "pcbz_peek": (i32, [vp, sz, pp, vp]),
@@ -188,8 +189,10 @@ class Context:
         msg = load().pcbz_last_error(self._h)
         raise PcbzError(st, f"{what}: {msg.decode() if msg else ''}")
 
-    def judge(self, frame, prev=None, pitch=15, level=9, cand_mask=0x7):
-        """Returns (choice uint8[n_bands], entropy float64[n_bands,4], score int64[n_bands,4]) on the device."""
+    def judge(self, frame, prev=None, pitch=15, level=9, cand_mask=0x7, noalloc=False):
+        """Returns (choice uint8[n_bands], entropy float64[n_bands,4], score int64[n_bands,4]) on the device.
+
+        noalloc=True calls pcbz_judge_noalloc (fixed device workspace)."""
         torch = _torch()
         f = to_device(frame)
         pv = None if prev is None else to_device(prev)
@@ -198,12 +201,15 @@ class Context:
         choice = torch.empty(nb, dtype=torch.uint8, device=f.device)
         ent = torch.empty(nb * 4, dtype=torch.float64, device=f.device)
         score = torch.empty(nb * 4, dtype=torch.int64, device=f.device)
-        p = Params(h, w, pitch, level, cand_mask)
-        st = load().pcbz_judge(self._h, ctypes.byref(p), _ptr(f), _ptr(pv), _ptr(choice), _ptr(ent), _ptr(score),
-                               _stream())
-        if st:
-            self._err(st, "judge")
+        self.judge_into(f, pv, Params(h, w, pitch, level, cand_mask), choice, ent, score, noalloc)
         return choice, ent.view(nb, 4), score.view(nb, 4)
+
+    def judge_into(self, f, pv, p, choice, ent=None, score=None, noalloc=False):
+        """Device-level judge: f/pv device tensors, outputs preallocated device tensors."""
+        fn = load().pcbz_judge_noalloc if noalloc else load().pcbz_judge
+        st = fn(self._h, ctypes.byref(p), _ptr(f), _ptr(pv), _ptr(choice), _ptr(ent), _ptr(score), _stream())
+        if st:
+            self._err(st, "judge_noalloc" if noalloc else "judge")
 
     def compress_into(self, f, pv, p, out, forced=None, choice_out=None):
         """Device-level call: f/pv device int16 tensors, out device uint8 tensor.  Returns the length."""
