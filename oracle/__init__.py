@@ -22,6 +22,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 OK, EINVAL, ENOSPC, EDATA, ENEEDPREV, ENOMEM = 0, -1, -2, -3, -4, -5
 RASTER, VIEW, VIEW_DX, VIEW_DT = 0, 1, 2, 3
 INT64_MIN = -(2**63)
+NCAND = 16  # arrangement ids 0..15 (4..15: the predictor family)
+PRED_FIRST = 4
 
 
 def build(force: bool = True) -> str:
@@ -85,6 +87,8 @@ def lib():
             "orc_container_header_bytes": (sz, [u32]),
             "orc_compress": (i32, [pp, vp, vp, vp, vp, sz, vp, vp]),
             "orc_peek": (i32, [vp, sz, pp, vp, vp, vp]),
+            "orc_zigzag16": (ctypes.c_uint16, [ctypes.c_uint16]),
+            "orc_unzigzag16": (ctypes.c_uint16, [ctypes.c_uint16]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -149,6 +153,14 @@ def unarrange(arranged, frame_shape, band, cid, prev=None, pitch=15, level=9, in
     return frame
 
 
+def zigzag16(r):
+    return int(lib().orc_zigzag16(int(r) & 0xFFFF))
+
+
+def unzigzag16(z):
+    return int(lib().orc_unzigzag16(int(z) & 0xFFFF))
+
+
 def to_bytes(v):
     v = np.ascontiguousarray(v, np.uint16).ravel()
     out = np.zeros(2 * v.size, np.uint8)
@@ -195,11 +207,11 @@ def judge(frame, prev=None, pitch=15, level=9, cand_mask=0x7):
     _, nb = plan(h, w, pitch, level, cand_mask)
     p = params(h, w, pitch, level, cand_mask)
     choice = np.zeros(nb, np.uint8)
-    S = np.zeros(nb * 4, np.int64)
-    H = np.zeros(nb * 4, np.float64)
+    S = np.zeros(nb * NCAND, np.int64)
+    H = np.zeros(nb * NCAND, np.float64)
     pr = None if prev is None else np.ascontiguousarray(prev, np.uint16)
     _check(lib().orc_judge(ctypes.byref(p), _P(frame), _P(pr), _P(choice), _P(S), _P(H)), "judge")
-    return choice, S.reshape(nb, 4), H.reshape(nb, 4)
+    return choice, S.reshape(nb, NCAND), H.reshape(nb, NCAND)
 
 
 # ---------------------------------------------------------------- bzip2 stages
@@ -335,3 +347,22 @@ def peek(blob):
     k = int(nb[0])
     return dict(h=p.h, w=p.w, pitch=p.pitch, level=p.level, n_bands=k, ids=ids[:k].copy(),
                 band_len=bl[:k].astype(np.int64))
+
+
+def decompress(blob, prev=None):
+    """Decode a container (test infrastructure): each band's streams with the
+    stock bz2 decoder, then the inverse arrangement named by the band's id
+    (orc_unarrange).  Returns the frame."""
+    import bz2
+
+    info = peek(blob)
+    h, w, pitch, level, nb = info["h"], info["w"], info["pitch"], info["level"], info["n_bands"]
+    frame = np.zeros((h, w), np.uint16)
+    pos = header_bytes(nb)
+    for b in range(nb):
+        ln = int(info["band_len"][b])
+        data = bz2.decompress(bytes(blob[pos:pos + ln]))
+        unarrange(np.frombuffer(data, "<u2"), (h, w), b, int(info["ids"][b]), prev, pitch, level, into=frame)
+        pos += ln
+    return frame
+

@@ -46,7 +46,7 @@ int orc_check_params(const orc_params *p) {
   if (p->pitch == 0 || p->pitch > 65535 || p->h == 0 || p->w == 0) return ORC_EINVAL;
   if (p->h % p->pitch || p->w % p->pitch) return ORC_EINVAL;
   if (p->level < 1 || p->level > 9) return ORC_EINVAL;
-  if (p->cand_mask == 0 || (p->cand_mask & ~0xFu)) return ORC_EINVAL;
+  if (p->cand_mask == 0 || (p->cand_mask & ~0xFFFFu)) return ORC_EINVAL;
   plan_raw(p, &R, &nb);
   if (nb > 65535) return ORC_EINVAL;
   return ORC_OK;
@@ -93,6 +93,83 @@ static uint16_t dx_pred(const uint16_t *img, uint32_t s, uint32_t t, uint32_t Nt
   return 0;
 }
 
+/* The predictor family of Sec. 2.1.1 and Fig. 3b/3c.  X is predicted from
+ * three causal neighbours A, B, C; the paper's Fig. 1b names three choices of
+ * them (the figure itself is missing, the text describes them):
+ *   domain 0, neighbouring pixels (the paper's spatial continuity): A the
+ *     pixel to the left, B the pixel above, C the pixel above-left;
+ *   domain 1, neighbouring microlenses (angular continuity): A, B, C the
+ *     same pixel in the lens to the left, above, above-left;
+ *   domain 2, phase space (both): A the same pixel in the lens to the left,
+ *     B the pixel above inside the same lens, C the pixel above inside the
+ *     lens to the left.
+ * The functions are the four multi-neighbour predictors of lossless JPEG:
+ * A + B - C, A + floor((B - C) / 2), B + floor((A - C) / 2),
+ * floor((A + B) / 2), in exact integers.  Neighbours must lie in the band:
+ * with only A the prediction is A, with only B it is B, with neither 0.  The
+ * residual X - prediction is taken mod 2^16 as a signed 16-bit value and
+ * mapped onto 0..65535 as 0, -1, 1, -2, 2, ... -> 0, 1, 2, 3, 4, ... (the
+ * "positive interval" map of Fig. 3b).  The residual image keeps the band's
+ * raster order (the predicted image of Sec. 2.1.2). */
+static int32_t pred_fn(int f, int32_t A, int32_t B, int32_t C) {
+  int32_t d;
+  switch (f) {
+    case 0: return A + B - C;
+    case 1: d = B - C; return A + (d >= 0 ? d / 2 : -((-d + 1) / 2));
+    case 2: d = A - C; return B + (d >= 0 ? d / 2 : -((-d + 1) / 2));
+    default: return (A + B) / 2;
+  }
+}
+
+/* Neighbours of band pixel (yy, x) for a domain; *has receives bit 0 for A,
+ * bit 1 for B (C exists when both do). */
+static void pred_neighbours(const uint16_t *band, uint32_t W, uint32_t pitch, int domain, uint32_t yy, uint32_t x,
+                            int32_t *A, int32_t *B, int32_t *C, int *has) {
+  uint32_t dxa, dyb;  /* offsets of A (left) and B (up) */
+  int ha, hb;
+  if (domain == 0) {
+    dxa = 1;
+    dyb = 1;
+    ha = x >= 1;
+    hb = yy >= 1;
+  } else if (domain == 1) {
+    dxa = pitch;
+    dyb = pitch;
+    ha = x >= pitch;
+    hb = yy >= pitch;
+  } else {
+    dxa = pitch;
+    dyb = 1;
+    ha = x >= pitch;
+    hb = (yy % pitch) >= 1;
+  }
+  *has = (ha ? 1 : 0) | (hb ? 2 : 0);
+  *A = ha ? band[(size_t)yy * W + x - dxa] : 0;
+  *B = hb ? band[(size_t)(yy - dyb) * W + x] : 0;
+  *C = (ha && hb) ? band[(size_t)(yy - dyb) * W + x - dxa] : 0;
+}
+
+static int32_t predict(const uint16_t *band, uint32_t W, uint32_t pitch, int id, uint32_t yy, uint32_t x) {
+  const int k = id - ORC_PRED_FIRST, domain = k / 4, f = k % 4;
+  int32_t A, B, C;
+  int has;
+  pred_neighbours(band, W, pitch, domain, yy, x, &A, &B, &C, &has);
+  if (has == 3) return pred_fn(f, A, B, C);
+  if (has == 1) return A;
+  if (has == 2) return B;
+  return 0;
+}
+
+/* 16-bit residual -> 0..65535: 0, -1, 1, -2, ... -> 0, 1, 2, 3, ... */
+uint16_t orc_zigzag16(uint16_t r) {
+  int32_t v = (int16_t)r;
+  return (uint16_t)(v >= 0 ? 2 * v : -2 * v - 1);
+}
+uint16_t orc_unzigzag16(uint16_t z) {
+  int32_t v = (z & 1u) ? -(int32_t)((z + 1u) / 2u) : (int32_t)(z / 2u);
+  return (uint16_t)v;
+}
+
 int orc_arrange(const orc_params *p, uint32_t band, int id, const uint16_t *frame, const uint16_t *prev,
                 uint16_t *out) {
   uint32_t y0l, Rb, pitch = p->pitch, W = p->w, Nt, yy, x;
@@ -103,6 +180,15 @@ int orc_arrange(const orc_params *p, uint32_t band, int id, const uint16_t *fram
   if (id == ORC_VIEW_DT && !prev) return ORC_ENEEDPREV;
   Nt = W / pitch;
   npix = (size_t)Rb * pitch * W;
+  if (id >= ORC_PRED_FIRST) {
+    const uint16_t *bandpx = frame + (size_t)y0l * pitch * W;
+    for (yy = 0; yy < Rb * pitch; yy++)
+      for (x = 0; x < W; x++) {
+        int32_t pr = predict(bandpx, W, pitch, id, yy, x);
+        out[(size_t)yy * W + x] = orc_zigzag16((uint16_t)((int32_t)bandpx[(size_t)yy * W + x] - pr));
+      }
+    return ORC_OK;
+  }
   for (yy = 0; yy < Rb * pitch; yy++) {
     size_t y = (size_t)y0l * pitch + yy;
     for (x = 0; x < W; x++) {
@@ -141,6 +227,16 @@ int orc_unarrange(const orc_params *p, uint32_t band, int id, const uint16_t *ar
   if (id == ORC_VIEW_DT && !prev) return ORC_ENEEDPREV;
   Nt = W / pitch;
   npix = (size_t)Rb * pitch * W;
+  if (id >= ORC_PRED_FIRST) {
+    /* raster scan: every neighbour of (yy, x) precedes it */
+    uint16_t *bandpx = frame + (size_t)y0l * pitch * W;
+    for (yy = 0; yy < Rb * pitch; yy++)
+      for (x = 0; x < W; x++) {
+        int32_t pr = predict(bandpx, W, pitch, id, yy, x);
+        bandpx[(size_t)yy * W + x] = (uint16_t)(pr + (int16_t)orc_unzigzag16(arranged[(size_t)yy * W + x]));
+      }
+    return ORC_OK;
+  }
   a = (uint16_t *)malloc(npix * sizeof(uint16_t));
   if (!a) return ORC_ENOMEM;
   memcpy(a, arranged, npix * sizeof(uint16_t));
@@ -266,15 +362,15 @@ int orc_judge(const orc_params *p, const uint16_t *frame, const uint16_t *prev, 
     for (id = 0; id < ORC_NCAND; id++) {
       int64_t s;
       if (!(p->cand_mask & (1u << id))) {
-        if (S) S[b * 4 + id] = INT64_MIN;
-        if (H) H[b * 4 + id] = NAN;
+        if (S) S[b * ORC_NCAND + id] = INT64_MIN;
+        if (H) H[b * ORC_NCAND + id] = NAN;
         continue;
       }
       orc_arrange(p, b, id, frame, prev, arr);
       orc_to_bytes(arr, npix, bytes);
       s = orc_band_score(bytes, n);
-      if (S) S[b * 4 + id] = s;
-      if (H) H[b * 4 + id] = orc_entropy_bits(s, n);
+      if (S) S[b * ORC_NCAND + id] = s;
+      if (H) H[b * ORC_NCAND + id] = orc_entropy_bits(s, n);
       if (best < 0 || s > bestS) {
         best = id;
         bestS = s;

@@ -25,7 +25,11 @@ extern "C" {
 #endif
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOSPC = -2, ORC_EDATA = -3, ORC_ENEEDPREV = -4, ORC_ENOMEM = -5 };
-enum { ORC_RASTER = 0, ORC_VIEW = 1, ORC_VIEW_DX = 2, ORC_VIEW_DT = 3, ORC_NCAND = 4 };
+enum { ORC_RASTER = 0, ORC_VIEW = 1, ORC_VIEW_DX = 2, ORC_VIEW_DT = 3, ORC_NCAND = 16 };
+/* ids 4..15: the multi-neighbour predictor family, id = 4 + 4 * domain + function
+ * (domain 0 pixel neighbours, 1 lens neighbours, 2 phase space; function 0
+ * A+B-C, 1 A+floor((B-C)/2), 2 B+floor((A-C)/2), 3 floor((A+B)/2)). */
+enum { ORC_PRED_FIRST = 4 };
 
 typedef struct {
   uint32_t h, w, pitch, level, cand_mask;
@@ -38,6 +42,10 @@ int orc_plan(const orc_params *p, uint32_t *rows_per_band, uint32_t *n_bands);
 int orc_band_geometry(const orc_params *p, uint32_t band, uint32_t *first_lens_row, uint32_t *lens_rows);
 int orc_arrange(const orc_params *p, uint32_t band, int id, const uint16_t *frame, const uint16_t *prev,
                 uint16_t *out);
+/* The map of 16-bit residuals onto 0..65535 used by the predictor family
+ * (0, -1, 1, -2, ... -> 0, 1, 2, 3, ...) and its inverse. */
+uint16_t orc_zigzag16(uint16_t r);
+uint16_t orc_unzigzag16(uint16_t z);
 int orc_unarrange(const orc_params *p, uint32_t band, int id, const uint16_t *arranged, const uint16_t *prev,
                   uint16_t *frame);
 void orc_to_bytes(const uint16_t *v, size_t count, uint8_t *out);

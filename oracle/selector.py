@@ -253,6 +253,8 @@ def predict(logits, cand_mask, min_conf):
     z = np.asarray(logits, np.float64)
     ids = [c for c in range(N_CLASSES) if (cand_mask >> c) & 1]
     out = np.full(len(z), 0xFF, np.uint8)
+    if cand_mask >> N_CLASSES:  # ids beyond the network's classes: every band is judged
+        return out
     for b, row in enumerate(z):
         best = max(ids, key=lambda c: (row[c], -c))
         p = 1.0 / np.exp(row[ids] - row[best]).sum()

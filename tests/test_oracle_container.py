@@ -102,3 +102,17 @@ def test_peek_rejects_damage(orc):
         with pytest.raises(orc.OracleError) as e:
             orc.peek(bad)
         assert e.value.code == orc.EDATA
+
+
+def test_oracle_decompress_roundtrip(orc):
+    """The oracle's decoder (stock bz2 per band, then the inverse
+    arrangement) gives back the frame for every arrangement id."""
+    from paper_2310_09467_amd import synth
+
+    f, pos = synth.beads_frame(90, 60, 20, 300.0, 5)
+    prev, _ = synth.beads_frame(90, 60, 20, 300.0, 6, positions=pos)
+    nb = orc.plan(90, 60, 15, 1)[1]
+    for cid in range(4):
+        blob, _ = orc.compress(f, prev, 15, 1, 0xF, forced_choice=np.full(nb, cid, np.uint8))
+        np.testing.assert_array_equal(orc.decompress(blob, prev), f)
+

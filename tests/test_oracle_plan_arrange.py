@@ -30,7 +30,7 @@ def test_band_plan_closed_form(orc, case):
 
 @pytest.mark.parametrize("h,w,pitch,level,mask", [
     (224, 225, 15, 9, 7), (225, 224, 15, 9, 7), (225, 225, 15, 0, 7), (225, 225, 15, 10, 7),
-    (225, 225, 15, 9, 0), (225, 225, 15, 9, 16), (0, 225, 15, 9, 7), (225, 225, 0, 9, 7)])
+    (225, 225, 15, 9, 0), (225, 225, 15, 9, 1 << 16), (0, 225, 15, 9, 7), (225, 225, 0, 9, 7)])
 def test_plan_rejects(orc, h, w, pitch, level, mask):
     with pytest.raises(orc.OracleError) as e:
         orc.plan(h, w, pitch, level, mask)
