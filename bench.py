@@ -56,9 +56,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / selector / serving legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain device-to-device copies of 256 MiB (counter calibration) and exit")
+    ap.add_argument("--decode-only", type=int, default=0, metavar="K",
+                    help="compress the three frames once, decompress each K times on the GPU and exit (profiling)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.decode_only:
+        decode_only(args.decode_only)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -315,6 +320,28 @@ def measured_traffic(kernel):
     return None
 
 
+def decode_only(reps):
+    """The benchmark's three containers decoded reps times each (for profilers)."""
+    import torch
+
+    from paper_2310_09467_amd import pcbz, synth
+
+    frames = [synth.config2_frame(p) for p in PEAKS]
+    ctx = pcbz.Context(0)
+    blobs = [ctx.compress(f, None, PITCH, LEVEL, MASK) for f in frames]
+    dev = [torch.from_numpy(np.frombuffer(b, np.uint8).copy()).cuda() for b in blobs]
+    outs = [torch.empty((H, W), dtype=torch.int16, device="cuda") for _ in frames]
+    t = time.perf_counter()
+    for _ in range(reps):
+        for i in range(len(frames)):
+            ctx.decompress_batch_into([dev[i]], [len(blobs[i])], None, [outs[i]])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ok = all(np.array_equal(pcbz.as_uint16(o), f) for o, f in zip(outs, frames))
+    print(json.dumps({"decoded_frames": reps * len(frames), "mb_s": round(2 * H * W * len(frames) * reps / dt / 1e6, 2),
+                      "equal": ok}), flush=True)
+
+
 def calibrate_copy(nbytes=256 << 20, reps=4):
     """Plain device copies of a known size: the HBM counters of the copy kernel
     give the factor between counter units and bytes."""
@@ -338,6 +365,40 @@ def timed(fn, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t) / reps
+
+
+def decode_leg(ctx, pcbz, torch, dev, frames, outs, prm, blobs):
+    """GPU decompression of the benchmark's containers (device-resident):
+    one call per frame and the three in one call; every decoded frame is
+    compared with the original on the device; per-stage kernel times."""
+    log("decode leg")
+    lens = [len(b) for b in blobs]
+    blob_dev = [outs[i][: lens[i]] for i in range(len(blobs))]
+    dec = [torch.empty_like(d) for d in dev]
+    raw = 2 * H * W * len(frames)
+
+    def single():
+        for i in range(len(blobs)):
+            ctx.decompress_batch_into([blob_dev[i]], [lens[i]], None, [dec[i]])
+
+    def batch():
+        ctx.decompress_batch_into(blob_dev, lens, None, dec)
+
+    t_single = timed(single, 5)
+    t_batch = timed(batch, 5)
+    batch()
+    equal = all(bool(torch.equal(dec[i], dev[i])) for i in range(len(frames)))
+    ctx.trace(True, None)
+    single()
+    tr = ctx.trace_read(reset=True)
+    ctx.trace(False)
+    st = {}
+    for key, (ms, calls, nbytes) in tr.items():
+        stage = key.split("|", 1)[0] if "|" in key else "other"
+        if stage.startswith("dec_"):
+            st[stage] = round(st.get(stage, 0.0) + ms * 1e3 / len(frames), 1)
+    return {"value": round(raw / t_single / 1e6, 2), "unit": "MB/s", "batched_mb_s": round(raw / t_batch / 1e6, 2),
+            "frames": len(frames), "equal_to_original": equal, "us_per_frame": dict(sorted(st.items()))}
 
 
 def series_leg(ctx, pcbz, torch, n_frames, sel_path):
@@ -366,6 +427,11 @@ def series_leg(ctx, pcbz, torch, n_frames, sel_path):
     t_graph = timed(lambda: ctx.compress_batch_into(dev, dprev, prms, outs), 3)
     lens = ctx.compress_batch_into(dev, dprev, prms, outs)
     ref = [outs[i][: lens[i]].cpu().numpy().tobytes() for i in range(len(frames))]
+    # the 64 containers back to frames in one GPU decompression call
+    blob_dev = [outs[i][: lens[i]] for i in range(len(frames))]
+    dec = [torch.empty_like(d) for d in dev]
+    t_dec = timed(lambda: ctx.decompress_batch_into(blob_dev, lens, dprev, dec), 3)
+    dec_equal = all(bool(torch.equal(dec[i], dev[i])) for i in range(len(frames)))
     ctx.set_graphs(0)
     t_eager = timed(lambda: ctx.compress_batch_into(dev, dprev, prms, outs), 3)
     lens_e = ctx.compress_batch_into(dev, dprev, prms, outs)
@@ -374,7 +440,8 @@ def series_leg(ctx, pcbz, torch, n_frames, sel_path):
     out = {"frames": len(frames), "raw_mb": round(raw / 1e6, 2),
            "bands": int(sum(pcbz.plan(p.h, p.w, PITCH, LEVEL, p.cand_mask)[0] for p in prms)),
            "value": round(raw / t_graph / 1e6, 2), "unit": "MB/s", "eager_mb_s": round(raw / t_eager / 1e6, 2),
-           "ratio": round(raw / sum(lens), 4), "graph_equals_eager": same}
+           "ratio": round(raw / sum(lens), 4), "graph_equals_eager": same,
+           "decode_mb_s": round(raw / t_dec / 1e6, 2), "decode_equals_original": dec_equal}
     if os.path.exists(sel_path):
         sel = pcbz.Selector.load_file(ctx, sel_path)
         tau = 0.9
@@ -440,6 +507,7 @@ def run_extras(ctx, pcbz, torch, dev, frames, outs, prm, blobs, args):
                            "plain_single_mb_s": round(raw / t_plain / 1e6, 2),
                            "regret": round(sel_bytes / exh - 1.0, 6),
                            "bands_judged_last_frame": list(judged)}
+    res["decode"] = decode_leg(ctx, pcbz, torch, dev, frames, outs, prm, blobs)
     if args.series_frames > 0:
         res["time_series"] = series_leg(ctx, pcbz, torch, args.series_frames, path)
     if args.serve_seconds > 0:

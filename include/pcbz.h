@@ -10,6 +10,18 @@
  *   PCBZ_VIEW     sub-aperture-view (phase-space) order,
  *   PCBZ_VIEW_DX  view order with the lens-neighbour delta mod 2^16,
  *   PCBZ_VIEW_DT  view order of the delta to the previous frame mod 2^16,
+ *   ids 4..15     the paper's predictor family (Sec. 2.1.1, Fig. 1b, Fig. 3b/3c):
+ *                 id = 4 + 4 * domain + function; each pixel X predicted from
+ *                 three causal neighbours A (left), B (above), C (above-left)
+ *                 over neighbouring pixels (domain 0), the same pixel in
+ *                 neighbouring lenses (domain 1) or phase space (domain 2: A
+ *                 one lens to the left, B the pixel above inside the lens, C
+ *                 the pixel above inside the lens to the left), with the
+ *                 lossless-JPEG functions A+B-C, A+floor((B-C)/2),
+ *                 B+floor((A-C)/2), floor((A+B)/2) (function 0..3); band-local
+ *                 edges (only A: A, only B: B, neither: 0); the residual mod
+ *                 2^16 as a signed value mapped 0,-1,1,-2,... -> 0,1,2,3,...;
+ *                 raster order,
  * scores them with the 2D image entropy criterion (Sec. 2.1.2, Eq. 1:
  * first-byte-only rotation sort, last column, adjacent-byte pair entropy),
  * codes the chosen arrangement with bzip2 (Sec. 2.1.3), and stores an 8-bit
@@ -39,7 +51,7 @@ extern "C" {
 typedef enum {
   PCBZ_OK = 0,
   PCBZ_EINVAL = -1,    /* bad parameters: h or w zero or not a multiple of pitch, pitch outside 1..90,
-                          level outside 1..9, cand_mask empty or with bits above 3, sizes too large */
+                          level outside 1..9, cand_mask empty or with bits above 15, sizes too large */
   PCBZ_ENOSPC = -2,    /* out_cap below the container size; *out_len receives the required size */
   PCBZ_EDATA = -3,     /* corrupt container: bad magic, lengths or a CRC mismatch */
   PCBZ_ENEEDPREV = -4, /* the temporal candidate is requested or stored but d_prev is NULL */
@@ -47,10 +59,11 @@ typedef enum {
   PCBZ_EDEVICE = -6    /* HIP runtime error (see pcbz_last_error) */
 } pcbz_status;
 
-enum { PCBZ_RASTER = 0, PCBZ_VIEW = 1, PCBZ_VIEW_DX = 2, PCBZ_VIEW_DT = 3 };
+enum { PCBZ_RASTER = 0, PCBZ_VIEW = 1, PCBZ_VIEW_DX = 2, PCBZ_VIEW_DT = 3, PCBZ_PRED_FIRST = 4, PCBZ_NCAND = 16 };
 
 /* Frame geometry and coding parameters.  level 1..9 sets the bzip2 block
- * limit 100000*level-19 bytes; cand_mask bit i enables arrangement id i. */
+ * limit 100000*level-19 bytes; cand_mask bit i enables arrangement id i
+ * (i = 0..15). */
 typedef struct {
   uint32_t h, w, pitch, level, cand_mask;
 } pcbz_params;
@@ -75,9 +88,10 @@ int pcbz_plan(const pcbz_params *prm, uint32_t *n_bands, size_t *compress_bound)
 
 /* Entropy judgement only (Sec. 2.1.2, Eq. 1).  Writes d_choice[n_bands] (the
  * lowest-entropy enabled arrangement per band, ties to the lowest id) and,
- * when non-NULL, d_entropy[n_bands*4] (bits per pair; NaN for disabled ids)
- * and d_score[n_bands*4] (the exact fixed-point sum of P*log2(P)*2^20 that
- * decides the choice; INT64_MIN for disabled ids). */
+ * when non-NULL, d_entropy[n_bands*16] (bits per pair; NaN for disabled ids)
+ * and d_score[n_bands*16] (the exact fixed-point sum of P*log2(P)*2^20 that
+ * decides the choice; INT64_MIN for disabled ids), 16 entries per band, one
+ * per arrangement id. */
 int pcbz_judge(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame, const uint16_t *d_prev,
                uint8_t *d_choice, double *d_entropy, int64_t *d_score, void *stream);
 
@@ -141,13 +155,33 @@ int pcbz_peek(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_ba
 
 /* The decompression pipeline of Fig. 1c and Fig. 2b: unpack the header,
  * decode each band's bzip2 streams, invert the arrangement named by the
- * band's id (Sec. 2.1, last paragraph before 2.1.1).  Decompresses a
- * container held in host memory into d_out (device, out_elems >= H*W, else
- * PCBZ_ENOSPC).  d_prev is required when a band uses PCBZ_VIEW_DT
- * (PCBZ_ENEEDPREV).  Every block CRC is checked (PCBZ_EDATA on mismatch or
- * any malformed field).  Synchronises `stream`. */
-int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
+ * band's id (Sec. 2.1, last paragraph before 2.1.1), all on the device.
+ * Decompresses a container held in device memory (d_in, in_len bytes) into
+ * d_out (device, out_elems >= H*W pixels, else PCBZ_ENOSPC).  d_prev is
+ * required when a band uses PCBZ_VIEW_DT (PCBZ_ENEEDPREV).  Every block CRC
+ * is checked; a malformed field, a CRC mismatch or a band that decodes to the
+ * wrong size gives PCBZ_EDATA (d_out may then be partly written).  Reads the
+ * container header back to the host, synchronises `stream`. */
+int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *d_in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
                     size_t out_elems, void *stream);
+
+/* pcbz_decompress for n containers at once (every block of every container
+ * is decoded in one pass).  Arrays are host arrays of n entries; d_prevs may
+ * be NULL or hold NULL entries.  Returns the first error. */
+int pcbz_decompress_batch(pcbz_ctx *ctx, uint32_t n, const uint8_t *const *d_ins, const size_t *in_lens,
+                          const uint16_t *const *d_prevs, uint16_t *const *d_outs, const size_t *out_elems,
+                          void *stream);
+
+/* Copies the first `bytes` of one intermediate array of the last
+ * decompression call on `ctx` to host memory, so that its stages can be
+ * checked one by one (valid until the next call on the context):
+ *   which 0  per-slot block records (header fields, symbol counts, lengths),
+ *         1  Huffman-decoded symbols (uint16, band after band),
+ *         2  the blocks after the zero runs and move-to-front (the BWT output),
+ *         3  the blocks after the inverse BWT (the first run-length stage),
+ *         4  the raw band bytes (arranged), 5 the call's counters.
+ * PCBZ_EINVAL for an unknown `which`, too many bytes or no call yet. */
+int pcbz_decompress_inspect(const pcbz_ctx *ctx, int which, void *host, size_t bytes);
 
 /* Statistics of the last compress call on this context (for profiling):
  * raw bytes, first-stage bytes, blocks, doubling rounds of the suffix sort. */
@@ -173,7 +207,9 @@ int pcbz_trace_read(pcbz_ctx *ctx, char *names, size_t name_stride, double *ms, 
  * features, the arrangement the judgement would choose; bands whose
  * predicted probability reaches min_conf skip the judgement and build only
  * the predicted arrangement, the rest are judged as usual.  Output stays a
- * valid container whose ids may differ from the exhaustive choice.
+ * valid container whose ids may differ from the exhaustive choice.  The
+ * network predicts among ids 0..3: a band whose cand_mask enables any of the
+ * predictor family (ids 4..15) is always judged.
  *
  * Features (pcbz_features): per band, the band's pixels are split into
  * 64 x 64 cells (cell (i, j) covers rows [i*Hb/64, (i+1)*Hb/64) and columns

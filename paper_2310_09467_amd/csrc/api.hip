@@ -102,8 +102,6 @@ void trace_end_impl(const char *name, hipStream_t s) {
   if (g_tracer.done.size() > 4096) g_tracer.collect();
 }
 
-int decode_container_host(const uint8_t *in, size_t in_len, const uint16_t *prev_host, uint16_t *frame_host,
-                          std::string &err);
 
 // A captured compression graph for one batch shape and schedule.
 struct GraphEntry {
@@ -164,6 +162,11 @@ struct pcbz_ctx {
   int use_graphs = 1;  // pcbz_compress_batch: 0 eager, 1 graphs where faster, 2 graphs
   uint32_t last_sel_bands = 0, last_sel_fallback = 0;
   std::string fixed_err;  // why the fixed workspace could not be set up (empty: it is)
+  // decompression: pinned header read-back area and the last call's workspace
+  uint8_t *h_dec = nullptr;
+  size_t h_dec_size = 0;
+  pcbz::DecWork last_dec{};
+  bool last_dec_valid = false;
 };
 
 namespace {
@@ -218,7 +221,7 @@ int check_params(const pcbz_params *p) {
   if (p->pitch == 0 || p->pitch > kMaxPitch || p->h == 0 || p->w == 0) return PCBZ_EINVAL;
   if (p->h % p->pitch || p->w % p->pitch) return PCBZ_EINVAL;
   if (p->level < 1 || p->level > 9) return PCBZ_EINVAL;
-  if (p->cand_mask == 0 || (p->cand_mask & ~0xFu)) return PCBZ_EINVAL;
+  if (p->cand_mask == 0 || (p->cand_mask & ~0xFFFFu)) return PCBZ_EINVAL;
   uint64_t lens_row = 2ull * p->pitch * p->w;
   uint64_t r = (100000ull * p->level - 19) / lens_row;
   if (r < 1) r = 1;
@@ -257,6 +260,7 @@ struct Plan {
   uint32_t slots = 0, segs = 0, pitch_max = 1, nt_max = 1, band_n_max = 0, lens_per_wg = 1, remap_chunks = 1;
   bool any_forced = false;
   bool selector = false;  // the selector decides bands before the judge
+  uint32_t used_ids = 0;  // arrangement ids some band may need (all of them for forced frames)
   bool use_forced() const { return any_forced || selector; }
 };
 
@@ -269,6 +273,7 @@ int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, 
     if (!F.forced && (F.p.cand_mask & 8u) && !F.prev)
       return fail(ctx, PCBZ_ENEEDPREV, "frame %zu: temporal candidate without a previous frame", f);
     if (F.forced) P.any_forced = true;
+    P.used_ids |= F.forced ? 0xFFFFu : F.p.cand_mask;
     uint32_t R, nb;
     plan_rows(&F.p, &R, &nb);
     const uint32_t p = F.p.pitch, W = F.p.w, ns = F.p.h / p;
@@ -397,7 +402,8 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.forced = A.get<uint8_t>(nbands + 4);
   w.ctr = A.get<uint32_t>(64);
   w.choice = A.get<uint8_t>(nbands + 4);
-  for (int id = 0; id < kNumCand; id++) w.cb.p[id] = A.get<uint8_t>(P.ntot + 16);
+  // a candidate buffer per arrangement id that some band of the call can use
+  for (int id = 0; id < kNumCand; id++) w.cb.p[id] = ((P.used_ids >> id) & 1u) ? A.get<uint8_t>(P.ntot + 16) : nullptr;
   w.hist = A.get<uint32_t>((size_t)P.tasks.size() * 65536);
   w.seg_first = A.get<uint16_t>((size_t)P.segs * 256);
   w.seg_last = A.get<uint16_t>((size_t)P.segs * 256);
@@ -650,8 +656,12 @@ int ensure_small(pcbz_ctx *ctx) {
 void enqueue_judge(const int64_t *tq, const Plan &P, Work &w, hipStream_t s) {
   const uint8_t *forced = P.use_forced() ? w.forced : nullptr;
   trace_stage("arrange");
-  launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
-                0xFu, s);
+  if (P.used_ids & 0xFu)
+    launch_remap2(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
+                  0xFu, s);
+  if (P.used_ids & 0xFFF0u)
+    launch_predict(w.bands, w.rows, (uint32_t)P.rows.size(), P.remap_chunks, P.lens_per_wg, P.pitch_max, w.cb, forced,
+                   s);
   trace_stage("judge");
   if (!P.tasks.empty()) {
     // the caller has cleared w.hist and w.score
@@ -1084,6 +1094,309 @@ int setup_fixed(pcbz_ctx *ctx, int dev) {
 }
 }  // namespace
 
+// ---------------------------------------------------------------- decompression host side
+namespace pcbz {
+
+uint32_t rd_le(const uint8_t *p, int k) {
+  uint32_t v = 0;
+  for (int i = 0; i < k; i++) v |= (uint32_t)p[i] << (8 * i);
+  return v;
+}
+
+// Container header (Sec. 2.1.4: the 8-bit arrangement id of each band is
+// stored in the header): geometry, level, band ids and stream lengths; the
+// lengths must add up to the container.  Host only.
+int peek_container(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_bands, std::vector<uint8_t> *ids,
+                   std::vector<uint32_t> *lens) {
+  if (in_len < 20 || memcmp(in, "PCBZ", 4) != 0 || in[4] != 1) return PCBZ_EDATA;
+  pcbz_params p;
+  p.level = in[5];
+  p.pitch = rd_le(in + 6, 2);
+  p.h = rd_le(in + 8, 4);
+  p.w = rd_le(in + 12, 4);
+  const uint32_t nb = rd_le(in + 16, 2);
+  p.cand_mask = 0;
+  if (p.level < 1 || p.level > 9 || p.pitch == 0 || p.h == 0 || p.w == 0 || p.h % p.pitch || p.w % p.pitch)
+    return PCBZ_EDATA;
+  if (in_len < 20 + 5ull * nb) return PCBZ_EDATA;
+  uint64_t total = 20 + 5ull * nb;
+  for (uint32_t b = 0; b < nb; b++) {
+    const uint8_t id = in[20 + 5 * b];
+    const uint32_t l = rd_le(in + 20 + 5 * b + 1, 4);
+    if (id >= kNumCand) return PCBZ_EDATA;
+    p.cand_mask |= 1u << id;
+    if (ids) ids->push_back(id);
+    if (lens) lens->push_back(l);
+    total += l;
+  }
+  if (total != in_len) return PCBZ_EDATA;
+  // the band count must match the plan for this geometry
+  uint64_t r = (100000ull * p.level - 19) / (2ull * p.pitch * p.w);
+  if (r < 1) r = 1;
+  const uint64_t ns = p.h / p.pitch;
+  if ((ns + r - 1) / r != nb) return PCBZ_EDATA;
+  *out = p;
+  if (n_bands) *n_bands = nb;
+  return PCBZ_OK;
+}
+
+}  // namespace pcbz
+
+namespace {
+
+struct DecIn {
+  const uint8_t *in;
+  size_t len;
+  const uint16_t *prev;
+  uint16_t *out;
+  size_t out_elems;
+};
+
+struct DecPlan {
+  std::vector<DecBand> bands;
+  std::vector<RowItem> rows;
+  uint32_t slots = 0, max_nslots = 0, band_n_max = 0;
+  uint64_t sym_total = 0, n_max = 0, raw_total = 0, col0_total = 0;
+  uint32_t pred_pixel = 0, pred_lines = 0, pred_sets = 0, nt_max = 0;
+};
+
+size_t dec_layout(Arena &A, const DecPlan &P, DecWork &w) {
+  w.n_bands = (uint32_t)P.bands.size();
+  w.n_slots = P.slots;
+  w.max_nslots = P.max_nslots;
+  w.sym_total = (uint32_t)P.sym_total;
+  w.n_max = (uint32_t)P.n_max;
+  w.raw_total = (uint32_t)P.raw_total;
+  w.n_rows = (uint32_t)P.rows.size();
+  w.pred_pixel = P.pred_pixel;
+  w.pred_lines = P.pred_lines;
+  w.pred_sets = P.pred_sets;
+  w.nt_max = P.nt_max;
+  w.max_chunks = (uint32_t)(P.sym_total / kDecChunk + P.slots + 1);
+  w.max_segs = w.max_chunks / kDecSeg + P.slots + 1;
+  w.max_spl = (uint32_t)(P.n_max / kDecSplit + 2ull * P.slots + 1);
+  w.max_tiles = (uint32_t)(P.n_max / kDecTile + P.slots + 1);
+  const size_t S = P.slots, N = P.n_max;
+  w.bands = A.get<DecBand>(w.n_bands);
+  w.rows = A.get<RowItem>(w.n_rows);
+  w.slots = A.get<DecSlot>(S);
+  w.ctr = A.get<uint32_t>(kDcWords);
+  w.seq = A.get<uint8_t>(S * 256);
+  w.sym = A.get<uint16_t>(P.sym_total + 64);
+  w.tok = A.get<uint8_t>(P.sym_total + 64);
+  w.chunk_slot = A.get<uint32_t>(w.max_chunks);
+  w.chunk_tot = A.get<uint32_t>(w.max_chunks);
+  w.chunk_off = A.get<uint32_t>(w.max_chunks);
+  w.chunk_fin = A.get<uint8_t>((size_t)w.max_chunks * 256);
+  w.chunk_in = A.get<uint8_t>((size_t)w.max_chunks * 256);
+  w.seg_slot = A.get<uint32_t>(w.max_segs);
+  w.seg_perm = A.get<uint8_t>((size_t)w.max_segs * 256);
+  w.seg_in = A.get<uint8_t>((size_t)w.max_segs * 256);
+  w.seg_tot = A.get<uint32_t>(w.max_segs);
+  w.seg_off = A.get<uint32_t>(w.max_segs);
+  w.L = A.get<uint8_t>(N + 16);
+  w.T = A.get<uint8_t>(N + 16);
+  w.key[0] = A.get<uint64_t>(N + 1);
+  w.key[1] = A.get<uint64_t>(N + 1);
+  w.val[0] = A.get<uint32_t>(N + 1);
+  w.val[1] = A.get<uint32_t>(N + 1);
+  w.E = A.get<uint32_t>(N + 1);
+  w.counts = A.get<uint32_t>(radix_counts_words((uint32_t)N, (uint32_t)S));
+  w.blk_start = A.get<uint32_t>(S + 1);
+  w.blk_slot = A.get<uint32_t>(S + 1);
+  w.blk_spl0 = A.get<uint32_t>(S + 1);
+  w.blk_tile0 = A.get<uint32_t>(S + 1);
+  w.spl_nxt = A.get<uint32_t>(w.max_spl);
+  w.spl_len = A.get<uint32_t>(w.max_spl);
+  w.spl_pos = A.get<uint32_t>(w.max_spl);
+  w.tile_agg = A.get<uint32_t>((size_t)w.max_tiles * 6);
+  w.tile_in = A.get<uint32_t>((size_t)w.max_tiles * 2);
+  w.raw = A.get<uint8_t>(P.raw_total + 16);
+  w.col0_total = (uint32_t)P.col0_total;
+  w.col0 = A.get<uint16_t>(P.col0_total + 8);
+  w.blocks = A.get<BlockDesc>(S + 1);
+  w.blk_raw_start = A.get<uint32_t>(S + 1);
+  w.crc_acc = A.get<uint32_t>(S + 1);
+  return A.off;
+}
+
+const char *dec_err_text(uint32_t bits) {
+  if (bits & kDecErrStream) return "malformed bzip2 stream";
+  if (bits & kDecErrSlots) return "band streams do not end where the band does";
+  if (bits & kDecErrMtf) return "bad move-to-front index, zero run or block length";
+  if (bits & kDecErrBwt) return "inverse BWT does not form one cycle";
+  if (bits & kDecErrLen) return "band decodes to the wrong number of bytes";
+  if (bits & kDecErrCrc) return "block CRC mismatch";
+  return "corrupt data";
+}
+
+// The decompression path (Fig. 1c, Fig. 2b) for containers in device memory:
+// the headers come back to the host (one copy each), every band of every
+// container is decoded on the device at once, and the counters come back
+// twice (after the move-to-front stage, to size the later launches, and at
+// the end for the status).
+int run_decompress(pcbz_ctx *ctx, const std::vector<DecIn> &in, hipStream_t s) {
+  constexpr size_t kHead = 4096;
+  const size_t n = in.size();
+  if (n * kHead > ctx->h_dec_size) {
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (ctx->h_dec) HIPCHK(ctx, hipHostFree(ctx->h_dec));
+    ctx->h_dec = nullptr;
+    ctx->h_dec_size = 0;
+    HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_dec, n * kHead, hipHostMallocDefault));
+    ctx->h_dec_size = n * kHead;
+  }
+  for (size_t i = 0; i < n; i++)
+    HIPCHK(ctx, hipMemcpyAsync(ctx->h_dec + i * kHead, in[i].in, std::min(in[i].len, kHead), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  DecPlan P;
+  std::vector<uint8_t> big;
+  for (size_t i = 0; i < n; i++) {
+    const uint8_t *h = ctx->h_dec + i * kHead;
+    const size_t avail = std::min(in[i].len, kHead);
+    if (avail < 20) return fail(ctx, PCBZ_EDATA, "container %zu: too short", i);
+    const uint32_t nb_hdr = rd_le(h + 16, 2);
+    const size_t hdr = 20 + 5ull * nb_hdr;
+    if (hdr > avail) {  // a long band table: read the whole table
+      if (hdr > in[i].len) return fail(ctx, PCBZ_EDATA, "container %zu: truncated band table", i);
+      big.resize(hdr);
+      HIPCHK(ctx, hipMemcpy(big.data(), in[i].in, hdr, hipMemcpyDeviceToHost));
+      h = big.data();
+    }
+    pcbz_params p;
+    uint32_t nb = 0;
+    std::vector<uint8_t> ids;
+    std::vector<uint32_t> lens;
+    if (peek_container(h, in[i].len, &p, &nb, &ids, &lens))
+      return fail(ctx, PCBZ_EDATA, "container %zu: bad header", i);
+    pcbz_params q = p;
+    q.cand_mask = 1;
+    if (check_params(&q)) return fail(ctx, PCBZ_EDATA, "container %zu: geometry outside the library's limits", i);
+    const size_t npix = (size_t)p.h * p.w;
+    if (in[i].out_elems < npix)
+      return fail(ctx, PCBZ_ENOSPC, "container %zu: output holds %zu pixels, frame has %zu", i, in[i].out_elems, npix);
+    uint32_t R, nbp;
+    plan_rows(&p, &R, &nbp);
+    const uint32_t P0 = p.pitch, W = p.w, ns = p.h / P0;
+    const uint32_t lim = 100000u * p.level - 19u;
+    size_t pos = hdr;
+    for (uint32_t k = 0; k < nb; k++) {
+      if (lens[k] > (64u << 20)) return fail(ctx, PCBZ_EDATA, "container %zu: band %u longer than 64 MiB", i, k);
+      if (ids[k] == PCBZ_VIEW_DT && !in[i].prev)
+        return fail(ctx, PCBZ_ENEEDPREV, "container %zu: band %u uses the temporal arrangement", i, k);
+      DecBand B{};
+      B.src = in[i].in + pos;
+      B.src_len = lens[k];
+      B.out = in[i].out;
+      B.prev = in[i].prev;
+      B.id = ids[k];
+      B.W = W;
+      B.pitch = P0;
+      B.Nt = W / P0;
+      B.Rb = std::min(R, ns - k * R);
+      B.y0 = k * R * P0;
+      B.n = 2u * B.Rb * P0 * W;
+      B.level = p.level;
+      B.raw_off = (uint32_t)P.raw_total;
+      B.col0_off = (uint32_t)P.col0_total;
+      if (B.id >= 4) {
+        const uint32_t domain = (B.id - 4) / 4;
+        if (domain == 0) {
+          P.pred_pixel = 1;
+        } else {
+          if (B.Nt > 32768)
+            return fail(ctx, PCBZ_EINVAL, "container %zu: predictor bands wider than 32768 lenses are not decoded", i);
+          P.pred_lines = 1;
+          P.pred_sets = std::max<uint32_t>(P.pred_sets, domain == 1 ? P0 * P0 : B.Rb * P0);
+          P.nt_max = std::max<uint32_t>(P.nt_max, B.Nt);
+        }
+      }
+      if (B.id == PCBZ_VIEW_DX) P.col0_total += (uint64_t)P0 * P0 * B.Rb;
+      const uint64_t cap = (uint64_t)B.n + B.n / 4 + 8;
+      B.blk_cap = (uint32_t)cap;
+      B.nslots = (uint32_t)((cap + (lim - 4) - 1) / (lim - 4) + 1);
+      B.slot0 = P.slots;
+      B.sym_base = (uint32_t)P.sym_total;
+      B.sym_end = (uint32_t)(P.sym_total + cap + B.nslots + 1);
+      P.slots += B.nslots;
+      P.max_nslots = std::max(P.max_nslots, B.nslots);
+      P.sym_total = B.sym_end;
+      P.n_max += cap;
+      P.raw_total += B.n;
+      P.band_n_max = std::max(P.band_n_max, B.n);
+      const uint32_t bi = (uint32_t)P.bands.size();
+      for (uint32_t r = 0; r < B.Rb; r++) P.rows.push_back(RowItem{bi, r});
+      P.bands.push_back(B);
+      pos += lens[k];
+    }
+    if (P.raw_total >= (1ull << 31) || P.n_max >= (1ull << 31) || P.sym_total >= (1ull << 31))
+      return fail(ctx, PCBZ_EINVAL, "batch too large to decode in one call");
+  }
+  if (P.bands.empty()) return PCBZ_OK;
+  DecWork w{};
+  Arena meas{nullptr};
+  const size_t need = dec_layout(meas, P, w);
+  int st;
+  if ((st = ensure_arena(ctx, need))) return st;
+  if ((st = ensure_tables(ctx, P.band_n_max))) return st;
+  Arena A{ctx->arena};
+  dec_layout(A, P, w);
+  ctx->last_dec = w;
+  ctx->last_dec_valid = true;
+  // plan tables through the pinned staging area (one copy)
+  {
+    std::vector<uint8_t> buf;
+    std::vector<UploadItem> items;
+    auto add = [&](const void *src, size_t bytes, void *dst) {
+      size_t off = align_up(buf.size(), 256);
+      buf.resize(off + bytes + 16);
+      if (!bytes || !dst) return;
+      memcpy(buf.data() + off, src, bytes);
+      items.push_back({off, bytes, dst});
+    };
+    add(P.bands.data(), P.bands.size() * sizeof(DecBand), w.bands);
+    add(P.rows.data(), P.rows.size() * sizeof(RowItem), w.rows);
+    HIPCHK(ctx, hipStreamSynchronize(s));
+    if (buf.size() > ctx->h_stage_size) {
+      if (ctx->h_stage) HIPCHK(ctx, hipHostFree(ctx->h_stage));
+      ctx->h_stage = nullptr;
+      size_t sz = align_up(buf.size() * 2, 1 << 16);
+      HIPCHK(ctx, hipHostMalloc((void **)&ctx->h_stage, sz, hipHostMallocDefault));
+      ctx->h_stage_size = sz;
+      ctx->gen++;
+    }
+    memcpy(ctx->h_stage, buf.data(), buf.size());
+    if ((st = enqueue_upload(ctx, items, s))) return st;
+  }
+  trace_stage("decode");
+  ZeroSpans z;
+  z.add(w.ctr, kDcWords);
+  z.add(w.slots, (size_t)P.slots * sizeof(DecSlot) / 4);
+  z.add(w.crc_acc, (size_t)P.slots + 1);
+  zero_spans(z, s);
+  fill_u32(w.ctr + kDcBand, 0xFFFFFFFFu, 1, s);
+  launch_dec_front(w, s);
+  if ((st = ensure_small(ctx))) return st;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, kDcWords * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  uint32_t hc[kDcWords];
+  memcpy(hc, ctx->h_small, sizeof hc);
+  if (hc[kDcErr]) {
+    trace_stage(nullptr);
+    return fail(ctx, PCBZ_EDATA, "%s (band %u of the call)", dec_err_text(hc[kDcErr]), hc[kDcBand]);
+  }
+  launch_dec_back(w, hc, ctx->eager_items, ctx->d_xchunk, ctx->d_xbyte, ctx->d_xpow2, s);
+  trace_stage(nullptr);
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 2 * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  const uint32_t err = ctx->h_small[kDcErr], band = ctx->h_small[kDcBand];
+  if (err) return fail(ctx, PCBZ_EDATA, "%s (band %u of the call)", dec_err_text(err), band);
+  return PCBZ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int pcbz_create(pcbz_ctx **out, int hip_device, size_t hbm_budget_bytes) {
@@ -1137,6 +1450,7 @@ void pcbz_destroy(pcbz_ctx *c) {
   if (c->d_xchunk) (void)hipFree(c->d_xchunk);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->h_small) (void)hipHostFree(c->h_small);
+  if (c->h_dec) (void)hipHostFree(c->h_dec);
   for (pcbz::GraphEntry &g : c->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   for (hipEvent_t e : c->ev)
@@ -1297,31 +1611,43 @@ int pcbz_peek(const uint8_t *in, size_t in_len, pcbz_params *out, uint32_t *n_ba
   return peek_container(in, in_len, out, n_bands, nullptr, nullptr);
 }
 
-int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
+int pcbz_decompress(pcbz_ctx *ctx, const uint8_t *d_in, size_t in_len, const uint16_t *d_prev, uint16_t *d_out,
                     size_t out_elems, void *stream) {
-  if (!ctx || !in || !d_out) return fail(ctx, PCBZ_EINVAL, "null argument");
+  return pcbz_decompress_batch(ctx, 1, &d_in, &in_len, &d_prev, &d_out, &out_elems, stream);
+}
+
+int pcbz_decompress_batch(pcbz_ctx *ctx, uint32_t n, const uint8_t *const *d_ins, const size_t *in_lens,
+                          const uint16_t *const *d_prevs, uint16_t *const *d_outs, const size_t *out_elems,
+                          void *stream) {
+  if (!ctx || !d_ins || !in_lens || !d_outs || !out_elems) return fail(ctx, PCBZ_EINVAL, "null argument");
+  if (n == 0) return PCBZ_OK;
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  hipStream_t s = (hipStream_t)stream;
-  pcbz_params p;
-  uint32_t nb = 0;
-  std::vector<uint8_t> ids;
-  int st = peek_container(in, in_len, &p, &nb, &ids, nullptr);
-  if (st) return fail(ctx, st, "bad container header");
-  const size_t npix = (size_t)p.h * p.w;
-  if (out_elems < npix) return fail(ctx, PCBZ_ENOSPC, "output holds %zu pixels, frame has %zu", out_elems, npix);
-  bool need_prev = false;
-  for (uint8_t id : ids) need_prev |= id == PCBZ_VIEW_DT;
-  std::vector<uint16_t> prev, frame(npix);
-  if (need_prev) {
-    if (!d_prev) return fail(ctx, PCBZ_ENEEDPREV, "container uses the temporal arrangement");
-    prev.resize(npix);
-    HIPCHK(ctx, hipMemcpyAsync(prev.data(), d_prev, npix * 2, hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
+  std::vector<DecIn> in(n);
+  for (uint32_t i = 0; i < n; i++) {
+    if (!d_ins[i] || !d_outs[i]) return fail(ctx, PCBZ_EINVAL, "container %u: null pointer", i);
+    in[i] = DecIn{d_ins[i], in_lens[i], d_prevs ? d_prevs[i] : nullptr, d_outs[i], out_elems[i]};
   }
-  st = decode_container_host(in, in_len, need_prev ? prev.data() : nullptr, frame.data(), ctx->err);
-  if (st) return st;
-  HIPCHK(ctx, hipMemcpyAsync(d_out, frame.data(), npix * 2, hipMemcpyHostToDevice, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
+  return run_decompress(ctx, in, (hipStream_t)stream);
+}
+
+int pcbz_decompress_inspect(const pcbz_ctx *ctx, int which, void *host, size_t bytes) {
+  if (!ctx || !host) return PCBZ_EINVAL;
+  if (!ctx->last_dec_valid) return PCBZ_EINVAL;
+  const DecWork &w = ctx->last_dec;
+  const void *src = nullptr;
+  size_t size = 0;
+  switch (which) {
+    case 0: src = w.slots; size = (size_t)w.n_slots * sizeof(DecSlot); break;
+    case 1: src = w.sym; size = (size_t)w.sym_total * 2; break;
+    case 2: src = w.L; size = w.n_max; break;
+    case 3: src = w.T; size = w.n_max; break;
+    case 4: src = w.raw; size = w.raw_total; break;
+    case 5: src = w.ctr; size = kDcWords * 4; break;
+    default: return PCBZ_EINVAL;
+  }
+  if (bytes > size) return PCBZ_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return PCBZ_EDEVICE;
+  if (hipMemcpy(host, src, bytes, hipMemcpyDeviceToHost) != hipSuccess) return PCBZ_EDEVICE;
   return PCBZ_OK;
 }
 

@@ -396,6 +396,10 @@ __global__ void k_select(const float *logits, uint32_t n_bands, const BandDesc *
   if (forced[b] != 0xFFu) return;  // the caller forced this band
   const float *z = logits + 4 * b;
   const uint32_t mask = bands[b].cand_mask;
+  if (mask >> kNumBasic) {  // the network predicts ids 0..3 only: bands offering the predictor family are judged
+    atomicAdd(n_fallback, 1u);
+    return;
+  }
   float mx = -INFINITY;
   int best = -1;
   for (int c = 0; c < 4; c++)

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_remap(const BandDesc *bands, const RowI
   const uint32_t t1 = min(Nt, t0 + lens_per_wg);
   const uint32_t nl = t1 - t0;
   const uint32_t fc = forced ? forced[ri.band] : 0xFFu;
-  uint32_t wm = fc != 0xFFu ? (1u << fc) : (B.cand_mask & write_mask);
+  uint32_t wm = (fc != 0xFFu ? (1u << fc) : B.cand_mask) & write_mask;
   if (!wm) return;
   const bool need_dt = (wm >> 3) & 1;
   const bool need_dx = (wm >> 2) & 1;
@@ -105,6 +105,73 @@ __global__ __launch_bounds__(256) void k_remap(const BandDesc *bands, const RowI
       ((uint16_t *)(cb.p[2] + B.off))[idx] = (uint16_t)(a - pred);
     }
     if (wm & 8u) ((uint16_t *)(cb.p[3] + B.off))[idx] = (uint16_t)(a - prv[u * (nl * p) + tt * p + v]);
+  }
+}
+
+// ---------------------------------------------------------------- predictor family
+// Arrangement ids 4..15 (Sec. 2.1.1, Fig. 1b, Fig. 3b/3c): id = 4 + 4 * domain
+// + function.  Each pixel X is predicted from three causal neighbours A
+// (left), B (above), C (above-left) taken over neighbouring pixels (domain
+// 0), neighbouring lenses (domain 1: the same pixel one lens over) or phase
+// space (domain 2: A one lens to the left, B the pixel above inside the
+// lens, C the pixel above inside the lens to the left), with the four
+// multi-neighbour lossless-JPEG functions A+B-C, A+floor((B-C)/2),
+// B+floor((A-C)/2), floor((A+B)/2).  Neighbours must lie in the band: only
+// A -> A, only B -> B, neither -> 0.  The residual mod 2^16, read as a signed
+// 16-bit value, is mapped 0, -1, 1, -2, ... -> 0, 1, 2, 3, ... and written in
+// the band's raster order.  A workgroup stages its lens row and the one
+// above (when the band has it), with the lens to the left of its run.
+__device__ __forceinline__ int32_t pred_fn(uint32_t f, int32_t A, int32_t B, int32_t C) {
+  return f == 0 ? A + B - C : f == 1 ? A + ((B - C) >> 1) : f == 2 ? B + ((A - C) >> 1) : (A + B) >> 1;
+}
+__device__ __forceinline__ uint16_t zigzag16(int32_t r) {
+  const int32_t v = (int16_t)(uint16_t)r;
+  return (uint16_t)((v << 1) ^ (v >> 15));
+}
+
+__global__ __launch_bounds__(256) void k_predict(const BandDesc *bands, const RowItem *rows, CandBufs cb,
+                                                 const uint8_t *forced, uint32_t lens_per_wg) {
+  extern __shared__ uint16_t sm[];
+  const RowItem ri = rows[blockIdx.x];
+  const BandDesc B = bands[ri.band];
+  const uint32_t p = B.pitch, W = B.W, Nt = B.Nt, s = ri.s;
+  const uint32_t t0 = blockIdx.y * lens_per_wg;
+  if (t0 >= Nt) return;
+  const uint32_t t1 = min(Nt, t0 + lens_per_wg), nl = t1 - t0;
+  const uint32_t fc = forced ? forced[ri.band] : 0xFFu;
+  const uint32_t wm = (fc != 0xFFu ? (1u << fc) : B.cand_mask) & 0xFFF0u;
+  if (!wm) return;
+  const uint32_t left = t0 > 0 ? 1u : 0u, up = s > 0 ? 1u : 0u;
+  const uint32_t tw = (nl + left) * p, th = (1 + up) * p;
+  const uint32_t x_lo = (t0 - left) * p;
+  const size_t row_lo = (size_t)B.y0 + (size_t)(s - up) * p;
+  for (uint32_t e = threadIdx.x; e < th * tw; e += blockDim.x) {
+    const uint32_t r = e / tw, c = e % tw;
+    sm[e] = B.frame[(row_lo + r) * W + x_lo + c];
+  }
+  __syncthreads();
+  const uint32_t pw = nl * p;
+  for (uint32_t bits = wm; bits; bits &= bits - 1) {
+    const uint32_t id = __ffs(bits) - 1, k = id - 4, domain = k >> 2, f = k & 3;
+    uint16_t *out = (uint16_t *)(cb.p[id] + B.off);
+    // A one step left along x, B one step up; the step lengths per domain
+    const uint32_t ax = domain == 0 ? 1u : p, by = domain == 1 ? p : 1u;
+    for (uint32_t e = threadIdx.x; e < p * pw; e += blockDim.x) {
+      const uint32_t u = e / pw, xx = e % pw;
+      const uint32_t yy = s * p + u, x = t0 * p + xx;
+      const uint32_t sr = up * p + u, sc = left * p + xx;
+      const int32_t X = sm[sr * tw + sc];
+      const bool hasA = x >= ax;
+      const bool hasB = domain == 0 ? yy >= 1 : domain == 1 ? s >= 1 : u >= 1;
+      int32_t pred = 0;
+      if (hasA && hasB)
+        pred = pred_fn(f, sm[sr * tw + sc - ax], sm[(sr - by) * tw + sc], sm[(sr - by) * tw + sc - ax]);
+      else if (hasA)
+        pred = sm[sr * tw + sc - ax];
+      else if (hasB)
+        pred = sm[(sr - by) * tw + sc];
+      out[(size_t)yy * W + x] = zigzag16(X - pred);
+    }
   }
 }
 
@@ -378,6 +445,17 @@ void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, 
   size_t lds = remap_lds_bytes(pitch_max, lens_per_wg);
   PCBZ_LAUNCH(k_remap, dim3(n_rows, max_chunks), dim3(256), lds, s, bands, rows, cb, forced, write_mask,
                      lens_per_wg);
+}
+
+size_t predict_lds_bytes(uint32_t pitch, uint32_t lens_per_wg) {
+  return (size_t)2 * pitch * (lens_per_wg + 1) * pitch * sizeof(uint16_t);
+}
+
+void launch_predict(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, uint32_t max_chunks,
+                    uint32_t lens_per_wg, uint32_t pitch_max, CandBufs cb, const uint8_t *forced, hipStream_t s) {
+  if (!n_rows) return;
+  PCBZ_LAUNCH(k_predict, dim3(n_rows, max_chunks), dim3(256), predict_lds_bytes(pitch_max, lens_per_wg), s, bands,
+              rows, cb, forced, lens_per_wg);
 }
 
 void launch_judge2(const JudgeTask *tasks, uint32_t n_tasks, const uint32_t *tile_task, const uint32_t *tile_local,

@@ -11,7 +11,8 @@
 namespace pcbz {
 
 constexpr int kWave = 64;
-constexpr int kNumCand = 4;             // RASTER, VIEW, VIEW_DX, VIEW_DT
+constexpr int kNumCand = 16;            // RASTER, VIEW, VIEW_DX, VIEW_DT, then the predictor family (ids 4..15)
+constexpr int kNumBasic = 4;            // ids the rearrangement kernel writes (and the selector predicts)
 constexpr uint32_t kNone16 = 0xFFFFu;   // "no byte" marker in 16-bit tables
 constexpr int kMaxAlpha = 258;          // bzip2 alphabet bound (256 byte ranks + RUNA/RUNB... + EOB)
 constexpr int kMaxGroups = 6;
@@ -315,6 +316,10 @@ void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);  // one word, 
 
 // judge.hip
 size_t remap_lds_bytes(uint32_t pitch, uint32_t lens_per_wg);
+size_t predict_lds_bytes(uint32_t pitch, uint32_t lens_per_wg);
+// Residuals of the predictor family (ids 4..15) of every band that enables or is forced to one.
+void launch_predict(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, uint32_t max_chunks,
+                    uint32_t lens_per_wg, uint32_t pitch_max, CandBufs cb, const uint8_t *forced, hipStream_t s);
 void launch_remap2(const BandDesc *bands, const RowItem *rows, uint32_t n_rows, uint32_t max_chunks,
                    uint32_t lens_per_wg, uint32_t pitch_max, CandBufs cb, const uint8_t *forced,
                    uint32_t write_mask, hipStream_t s);
@@ -415,6 +420,122 @@ void launch_pack2(const uint32_t *d_nb, uint32_t max_blocks, const BlockDesc *bl
                   uint32_t n_frames, const BandDesc *bands, const uint8_t *choice, uint32_t *band_len,
                   uint64_t *frame_len, uint32_t *word_start, uint32_t *d_words, uint32_t max_words,
                   hipEvent_t prefix_ready, hipStream_t s);
+
+// ---------------------------------------------------------------- decompression
+// One band of a decompression call (host-built).
+struct DecBand {
+  const uint8_t *src;      // the band's bzip2 streams inside the container (device)
+  uint16_t *out;           // the frame being written (device)
+  const uint16_t *prev;    // previous frame (VIEW_DT) or nullptr
+  uint32_t src_len;        // bytes of the band's streams
+  uint32_t id;             // arrangement id
+  uint32_t W, pitch, Nt, Rb, y0;
+  uint32_t n;              // raw bytes of the band (2 * Rb * pitch * W)
+  uint32_t raw_off;        // first byte of the band in the call's raw byte space
+  uint32_t slot0, nslots;  // block slots of the band
+  uint32_t level;          // container level (block limit 100000 * level)
+  uint32_t sym_base, sym_end;  // the band's range of the symbol space
+  uint32_t blk_cap;        // bound on the band's block bytes (n + n / 4 + 8)
+  uint32_t col0_off;       // first value of the band's first-lens-column sums (VIEW_DX)
+};
+
+// One block slot of a decompression call (device-built).
+struct DecSlot {
+  uint32_t valid;         // a stream was decoded into this slot
+  uint32_t band;
+  uint32_t start_byte;    // first byte of the stream in its band
+  uint32_t end_byte;      // first byte after the stream
+  uint32_t crc;           // stored block CRC
+  uint32_t orig_ptr;
+  uint32_t n_in_use;
+  uint32_t n_sym;         // symbols including the end-of-block symbol
+  uint32_t sym_off;       // first symbol in the symbol space
+  uint32_t m;             // block length (inverse move-to-front output)
+  uint32_t l_off;         // first byte of the block in the packed block space
+  uint32_t raw_len;       // bytes once the first run-length stage is undone
+  uint32_t raw_off;       // first byte in the call's raw byte space (0xFFFFFFFF: band failed)
+  uint32_t chunk0, n_chunks;  // move-to-front chunks
+  uint32_t seg0, n_segs;      // segments of 32 chunks
+  uint32_t blk;               // index among the valid slots
+  uint32_t cyc;               // length of the inverse-BWT cycle through the origin row (divides m)
+};
+
+constexpr uint32_t kDecChunk = 1024;      // symbols per inverse move-to-front chunk
+constexpr uint32_t kDecSeg = 32;          // chunks per segment of the list chain
+constexpr uint32_t kDecSplit = 64;        // stride of the inverse-BWT splitters
+constexpr uint32_t kDecTile = 4096;       // positions per inverse run-length tile
+constexpr uint32_t kDecHeadBytes = 24576; // bytes staged for a stream header (it is shorter)
+constexpr uint32_t kDecMaxBlock = 900000; // the format's largest block (level 9)
+constexpr uint32_t kDecMaxSpl = kDecMaxBlock / kDecSplit + 2;  // splitters of one block
+
+// Error bits of a decompression call (word 0 of its counters).
+enum : uint32_t {
+  kDecErrStream = 1u,    // malformed stream header or Huffman data
+  kDecErrMtf = 2u,       // bad move-to-front index, run or block length
+  kDecErrBwt = 4u,       // the inverse BWT permutation is not one cycle
+  kDecErrLen = 8u,       // a band decodes to the wrong number of bytes
+  kDecErrCrc = 16u,      // block CRC mismatch
+  kDecErrSlots = 32u,    // streams left over in a band, or none
+};
+
+// Counter words of a decompression call.
+enum : uint32_t {
+  kDcErr = 0, kDcBand = 1, kDcBlocks = 2, kDcChunks = 3, kDcN = 4, kDcSpl = 5, kDcTiles = 6, kDcSegs = 7,
+  kDcCountN = 8, kDcWords = 16
+};
+
+struct DecWork {
+  DecBand *bands;
+  DecSlot *slots;
+  uint32_t *ctr;          // kDcWords counter words
+  uint8_t *seq;           // [slots][256] byte of each symbol-map rank
+  uint16_t *sym;          // [sym_total] symbols, band by band
+  uint8_t *tok;           // [sym_total] placeholder tokens
+  uint32_t *chunk_slot;   // [max_chunks]
+  uint32_t *chunk_tot;    // [max_chunks] bytes a chunk expands to
+  uint32_t *chunk_off;    // [max_chunks] its first byte inside the block
+  uint8_t *chunk_fin;     // [max_chunks][256] list permutation at the chunk's end
+  uint8_t *chunk_in;      // [max_chunks][256] incoming list
+  uint32_t *seg_slot;     // [max_segs]
+  uint8_t *seg_perm;      // [max_segs][256]
+  uint8_t *seg_in;        // [max_segs][256]
+  uint32_t *seg_tot;      // [max_segs]
+  uint32_t *seg_off;      // [max_segs]
+  uint8_t *L;             // [n_max + 16] block space
+  uint8_t *T;             // [n_max + 16]
+  uint64_t *key[2];
+  uint32_t *val[2];
+  uint32_t *E;            // [n_max] successor << 8 | byte
+  uint32_t *counts;       // radix counts
+  uint32_t *blk_start;    // [n_slots + 1] dense blocks in the block space
+  uint32_t *blk_slot;     // [n_slots] slot of each dense block
+  uint32_t *blk_spl0;     // [n_slots + 1] first splitter of each dense block
+  uint32_t *blk_tile0;    // [n_slots + 1] first run-length tile of each dense block
+  uint32_t *spl_nxt, *spl_len, *spl_pos;  // [max_spl]
+  uint32_t *tile_agg;     // [max_tiles][6] map + five lengths
+  uint32_t *tile_in;      // [max_tiles][2] in-state, first raw byte
+  uint8_t *raw;           // [raw_total + 16] raw band bytes
+  uint16_t *col0;         // [col0_total] running sums down the first lens column of every view (VIEW_DX)
+  BlockDesc *blocks;      // [n_slots + 1] dense blocks' raw ranges and computed CRCs
+  uint32_t *blk_raw_start;  // [n_slots + 1]
+  uint32_t *crc_acc;      // [n_slots + 1]
+  uint32_t sym_total, max_chunks, max_segs, n_max, max_spl, max_tiles, raw_total, n_slots, n_bands, max_nslots;
+  uint32_t col0_total;
+  RowItem *rows;          // [n_rows] (band, lens row) of every band
+  uint32_t n_rows;
+  uint32_t pred_pixel;    // some band uses a pixel-neighbour predictor
+  uint32_t pred_lines;    // some band uses a lens or phase-space predictor
+  uint32_t pred_sets;     // most line sets of such a band
+  uint32_t nt_max;        // most lens columns of such a band
+};
+
+// decode.hip: the stages of one decompression call, in stream order.  The
+// host reads the counters back after launch_dec_front (the block-space
+// layout and any error) and sizes the later launches from them.
+void launch_dec_front(const DecWork &w, hipStream_t s);
+// hc: the counters as read back (kDcWords words).
+void launch_dec_back(const DecWork &w, const uint32_t *hc, int radix_items, const uint32_t *xpow_chunk,
+                     const uint32_t *xpow_byte, const uint32_t *xpow2, hipStream_t s);
 
 // ---------------------------------------------------------------- learned selector
 }  // namespace pcbz

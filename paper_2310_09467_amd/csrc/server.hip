@@ -280,7 +280,7 @@ void worker_main(pcbz_server *s, int wi) {
           Job &j = *batch[k0 + i];
           if (j.uploaded) (void)hipStreamWaitEvent(st, j.uploaded, 0);
           prm[i] = j.prm;
-          if (!j.prev) prm[i].cand_mask &= 0x7u;
+          if (!j.prev) prm[i].cand_mask &= ~0x8u;
           fr[i] = (const uint16_t *)j.frame->p;
           pv[i] = j.prev ? (const uint16_t *)j.prev->p : nullptr;
           outs[i] = j.out->p;
@@ -426,7 +426,7 @@ int pcbz_server_submit(pcbz_server *s, const pcbz_params *prm, const uint16_t *h
   if (it != s->last.end()) old = it->second;
   // the first frame of a camera and shape has no previous frame: it is coded
   // without the temporal candidate, so it needs another one
-  if (!old && (prm->cand_mask & 7u) == 0) return PCBZ_ENEEDPREV;
+  if (!old && (prm->cand_mask & ~8u) == 0) return PCBZ_ENEEDPREV;
   if ((prm->cand_mask & 8u) && old) {
     j->prev_job = old;
     old->prev_refs++;

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpcbz.so")
 
 OK, EINVAL, ENOSPC, EDATA, ENEEDPREV, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 RASTER, VIEW, VIEW_DX, VIEW_DT = 0, 1, 2, 3
+NCAND = 16  # arrangement ids; 4 + 4 * domain + function: the predictor family
 _NAMES = {EINVAL: "EINVAL", ENOSPC: "ENOSPC", EDATA: "EDATA", ENEEDPREV: "ENEEDPREV", ENOMEM: "ENOMEM",
           EDEVICE: "EDEVICE"}
 
@@ -26,7 +27,7 @@ EXPORTS = ("pcbz_create", "pcbz_destroy", "pcbz_last_error", "pcbz_plan", "pcbz_
            "pcbz_features", "pcbz_selector_forward", "pcbz_selector_gradients", "pcbz_selector_train_step",
            "pcbz_gemm_bf16", "pcbz_set_selector", "pcbz_selector_stats", "pcbz_set_graphs", "pcbz_server_create",
            "pcbz_server_submit", "pcbz_server_poll", "pcbz_server_stats", "pcbz_server_destroy",
-           "pcbz_selector_inspect", "pcbz_judge_noalloc")
+           "pcbz_selector_inspect", "pcbz_judge_noalloc", "pcbz_decompress_batch", "pcbz_decompress_inspect")
 
 
 class PcbzError(RuntimeError):
@@ -84,6 +85,8 @@ def load():
             "pcbz_compress_batch": (i32, [vp, u32, pp, vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp]),
             "pcbz_peek": (i32, [vp, sz, pp, vp]),
             "pcbz_decompress": (i32, [vp, vp, sz, vp, vp, sz, vp]),
+            "pcbz_decompress_batch": (i32, [vp, u32, vp, vp, vp, vp, vp, vp]),
+            "pcbz_decompress_inspect": (i32, [vp, i32, vp, sz]),
             "pcbz_last_stats": (i32, [vp, vp, vp, vp, vp]),
             "pcbz_trace_enable": (i32, [vp, i32, ctypes.c_char_p]),
             "pcbz_trace_read": (i32, [vp, vp, sz, vp, vp, vp, u32, vp, i32]),
@@ -190,7 +193,7 @@ class Context:
         raise PcbzError(st, f"{what}: {msg.decode() if msg else ''}")
 
     def judge(self, frame, prev=None, pitch=15, level=9, cand_mask=0x7, noalloc=False):
-        """Returns (choice uint8[n_bands], entropy float64[n_bands,4], score int64[n_bands,4]) on the device.
+        """Returns (choice uint8[n_bands], entropy float64[n_bands,16], score int64[n_bands,16]) on the device.
 
         noalloc=True calls pcbz_judge_noalloc (fixed device workspace)."""
         torch = _torch()
@@ -199,10 +202,10 @@ class Context:
         h, w = f.shape
         nb, _ = plan(h, w, pitch, level, cand_mask)
         choice = torch.empty(nb, dtype=torch.uint8, device=f.device)
-        ent = torch.empty(nb * 4, dtype=torch.float64, device=f.device)
-        score = torch.empty(nb * 4, dtype=torch.int64, device=f.device)
+        ent = torch.empty(nb * NCAND, dtype=torch.float64, device=f.device)
+        score = torch.empty(nb * NCAND, dtype=torch.int64, device=f.device)
         self.judge_into(f, pv, Params(h, w, pitch, level, cand_mask), choice, ent, score, noalloc)
-        return choice, ent.view(nb, 4), score.view(nb, 4)
+        return choice, ent.view(nb, NCAND), score.view(nb, NCAND)
 
     def judge_into(self, f, pv, p, choice, ent=None, score=None, noalloc=False):
         """Device-level judge: f/pv device tensors, outputs preallocated device tensors."""
@@ -293,17 +296,52 @@ class Context:
         return list(lens)
 
     def decompress(self, blob, prev=None):
-        """Decodes a container (host bytes) into a device int16 tensor (uint16 bits)."""
+        """Decodes a container (host bytes or a device uint8 tensor) into a
+        device int16 tensor (uint16 bits) on the GPU."""
+        return self.decompress_batch([blob], [prev])[0]
+
+    def decompress_batch(self, blobs, prevs=None):
+        """Decodes several containers in one call; returns device int16 tensors."""
         torch = _torch()
-        info = peek(blob)
-        out = torch.empty((info["h"], info["w"]), dtype=torch.int16, device=f"cuda:{self.device}")
-        b = np.frombuffer(bytes(blob), np.uint8)
-        pv = None if prev is None else to_device(prev)
-        st = load().pcbz_decompress(self._h, b.ctypes.data_as(ctypes.c_void_p), b.size, _ptr(pv), _ptr(out),
-                                    out.numel(), _stream())
+        n = len(blobs)
+        dev = [b if hasattr(b, "data_ptr") else
+               torch.from_numpy(np.frombuffer(bytes(b), np.uint8).copy()).to(f"cuda:{self.device}") for b in blobs]
+        outs = []
+        for b, d in zip(blobs, dev):
+            head = bytes(b[:20].cpu().numpy().tobytes()) if hasattr(b, "data_ptr") else bytes(b[:20])
+            h = int.from_bytes(head[8:12], "little") if len(head) >= 20 else 0
+            w = int.from_bytes(head[12:16], "little") if len(head) >= 20 else 0
+            outs.append(torch.empty((h, w), dtype=torch.int16, device=f"cuda:{self.device}"))
+        pvs = [None if prevs is None or prevs[i] is None else to_device(prevs[i]) for i in range(n)]
+        VP = ctypes.c_void_p * n
+        SZ = ctypes.c_size_t * n
+        st = load().pcbz_decompress_batch(self._h, n, VP(*[d.data_ptr() for d in dev]), SZ(*[d.numel() for d in dev]),
+                                          VP(*[0 if p is None else p.data_ptr() for p in pvs]),
+                                          VP(*[o.data_ptr() for o in outs]), SZ(*[o.numel() for o in outs]),
+                                          _stream())
         if st:
             self._err(st, "decompress")
-        return out
+        return outs
+
+    def decompress_batch_into(self, dev_blobs, lens, dev_prevs, outs):
+        """Device-level batch decode: device uint8 containers with their lengths,
+        device int16 previous frames (or None) and outputs."""
+        n = len(dev_blobs)
+        VP = ctypes.c_void_p * n
+        SZ = ctypes.c_size_t * n
+        pv = VP(*[0 if dev_prevs is None or dev_prevs[i] is None else dev_prevs[i].data_ptr() for i in range(n)])
+        st = load().pcbz_decompress_batch(self._h, n, VP(*[d.data_ptr() for d in dev_blobs]), SZ(*lens), pv,
+                                          VP(*[o.data_ptr() for o in outs]), SZ(*[o.numel() for o in outs]), _stream())
+        if st:
+            self._err(st, "decompress")
+
+    def decompress_inspect(self, which, nbytes, dtype=np.uint8):
+        """One intermediate array of the last decompression call (see the header)."""
+        buf = np.zeros(nbytes, np.uint8)
+        st = load().pcbz_decompress_inspect(self._h, int(which), buf.ctypes.data_as(ctypes.c_void_p), nbytes)
+        if st:
+            raise PcbzError(st, "decompress_inspect")
+        return buf.view(dtype)
 
     def trace(self, on=True, kernel=None):
         """Enables HIP-event timing of launches of `kernel` (all kernels when None)."""

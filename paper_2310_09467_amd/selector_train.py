@@ -199,33 +199,6 @@ def pick_threshold(rows, budget):
     return min(ok, key=lambda r: r["min_conf"]) if ok else rows[-1]
 
 
-def throughput(ctx, sel, frames, tau, reps=3):
-    """Input MB/s of single-frame compress calls without and with the selector."""
-    import torch
-
-    dev = [(pcbz.to_device(f), None if p is None else pcbz.to_device(p), m) for f, p, m in frames]
-    raw = sum(2 * f.shape[0] * f.shape[1] for f, _, _ in dev)
-    outs = [torch.empty(pcbz.plan(f.shape[0], f.shape[1], PITCH, LEVEL, m)[1], dtype=torch.uint8, device="cuda")
-            for f, _, m in dev]
-
-    def run():
-        for (f, p, m), out in zip(dev, outs):
-            ctx.compress_into(f, p, pcbz.Params(f.shape[0], f.shape[1], PITCH, LEVEL, m), out)
-
-    res = {}
-    for name, s in (("judge_all", None), ("selector", sel)):
-        ctx.set_selector(s, tau)
-        run()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            run()
-        torch.cuda.synchronize()
-        res[name] = raw * reps / (time.perf_counter() - t) / 1e6
-    ctx.set_selector(None)
-    return res
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-frames", type=int, default=4000)
@@ -272,8 +245,6 @@ def main():
     worst = [dict(a, regret=max(a["regret"], b["regret"]), judged_frac=max(a["judged_frac"], b["judged_frac"]))
              for a, b in zip(ev["thresholds"], ev_v["thresholds"])]
     pick = pick_threshold(worst, args.budget)
-    large = [fr for fr in test_set.frames if fr[0].shape[0] == H][:8]
-    tp = throughput(ctx, sel, large, pick["min_conf"])
     rep = {
         "train_frames": args.train_frames, "vessel_frames": args.vessel_frames, "test_frames": args.test_frames,
         "test_vessel_frames": args.test_vessel_frames, "test_vessel_bands": int(test_ves.feat.shape[0]),
@@ -285,7 +256,6 @@ def main():
         "loss_first": hist[0], "loss_last": hist[-1],
         "train_agreement": train_agree, "test_agreement": ev["agreement"],
         "thresholds": ev["thresholds"], "budget": args.budget, "picked": pick,
-        "throughput_mb_s_2040": tp,
         "seconds": {"data": round(t1 - t0, 1), "train": round(t2 - t1, 1)},
     }
     if args.out:

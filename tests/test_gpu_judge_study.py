@@ -20,23 +20,27 @@ def test_judge_study_small(orc):
     frame = synth.config1_frame(1)
     big, _ = synth.beads_frame(450, 300, 40, 300.0, seed=13)
     rows = []
-    for f, lv in ((frame, 1), (big, 2)):
-        row = judge_study.study_frame(ctx, f, None, 15, lv, 0x7)
-        choice, ent, sizes, ids = row
-        oc, _, oh = orc.judge(f, None, 15, lv, 0x7)
+    for f, lv, mask in ((frame, 1, 0x7), (big, 2, 0x7), (big, 9, 0xFFF7)):
+        row = judge_study.study_frame(ctx, f, None, 15, lv, mask, with_proxies=True)
+        choice, ent, sizes, ids, prox = row
+        oc, _, oh = orc.judge(f, None, 15, lv, mask)
         np.testing.assert_array_equal(choice, oc)
         for c in ids:
             np.testing.assert_allclose(ent[:, c], oh[:, c], rtol=0, atol=1e-9)
-            blob, _ = orc.compress(f, None, 15, lv, 0x7, forced_choice=np.full(len(oc), c, np.uint8))
+            blob, _ = orc.compress(f, None, 15, lv, mask, forced_choice=np.full(len(oc), c, np.uint8))
             info = orc.peek(blob)
             np.testing.assert_array_equal(sizes[:, c], info["band_len"])
             assert (info["ids"] == c).all()
+            # the cheaper criteria from the oracle's arranged bytes of each band
+            for b in range(len(oc)):
+                x = orc.to_bytes(orc.arrange(f, b, c, None, 15, lv))
+                np.testing.assert_allclose(prox[b, c], judge_study.proxies(x), rtol=0, atol=1e-12)
         rows.append(row)
     s = judge_study.summarize(rows)
     # the summary recomputed from the oracle-checked sizes by hand
     n = agree = 0
     judged = best = 0
-    for choice, ent, sizes, ids in rows:
+    for choice, ent, sizes, ids, prox in rows:
         for b in range(len(choice)):
             c_best = min(ids, key=lambda c: (sizes[b, c], c))
             agree += int(choice[b]) == c_best

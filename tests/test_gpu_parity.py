@@ -150,7 +150,7 @@ def test_errors(ctx, orc):
         ctx.compress(f, None, 15, 1, 0x3, forced=[3, 0])
     assert e.value.code == pcbz.ENEEDPREV
     with pytest.raises(pcbz.PcbzError) as e:
-        ctx.compress(f, None, 15, 1, 0x3, forced=[7, 0])
+        ctx.compress(f, None, 15, 1, 0x3, forced=[16, 0])
     assert e.value.code == pcbz.EINVAL
     blob = ctx.compress(f, None, 15, 1, 0x3)
     dev = pcbz.to_device(f)

@@ -77,7 +77,7 @@ def test_plan_matches_oracle(lib, orc):
 
 
 @pytest.mark.parametrize("h,w,p,lv,mask", [(224, 225, 15, 9, 7), (225, 225, 15, 0, 7), (225, 225, 15, 9, 0),
-                                           (225, 225, 15, 9, 16), (182, 182, 91, 9, 7)])
+                                           (225, 225, 15, 9, 1 << 16), (182, 182, 91, 9, 7)])
 def test_plan_rejects(lib, h, w, p, lv, mask):
     from paper_2310_09467_amd import pcbz
 

@@ -43,7 +43,7 @@ def test_noalloc_judge_equals_judge(orc):
         # and the oracle's choices on the same frame
         oc, osc, _ = orc.judge(f, pv, 15, level, mask)
         assert np.array_equal(got[0].cpu().numpy(), oc)
-        on = [(mask >> i) & 1 == 1 for i in range(4)]
+        on = [(mask >> i) & 1 == 1 for i in range(16)]
         assert np.array_equal(got[2].cpu().numpy()[:, on], osc[:, on])
     ctx.close()
 
