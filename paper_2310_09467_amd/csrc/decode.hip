@@ -31,21 +31,38 @@ constexpr uint32_t kLutSize = 1u << kLutBits;
 constexpr uint32_t kWinWords = 1024;  // 4 KB window of Huffman data bits in LDS
 constexpr uint32_t kInvalid = 0x1FFu;
 constexpr uint32_t kMaxLen = 20;      // the format's longest code
+constexpr uint32_t kOutBuf = 1024;    // symbols gathered in LDS before a store
 
 __device__ __forceinline__ void set_err(uint32_t *ctr, uint32_t bit, uint32_t band) {
   atomicOr(&ctr[0], bit);
   atomicMin(&ctr[1], band);
 }
 
-// Big-endian word k of a byte range (bytes past `len` read as zero).
-__device__ __forceinline__ uint32_t be_word(const uint8_t *p, uint32_t len, uint32_t k) {
-  uint32_t v = 0;
+// Words [w0, w0 + n) of the big-endian word view of src[0, len) into dst
+// (bytes past len read as zero), by the whole wavefront; every load is in
+// bounds and unconditional, so that a lane's sixteen loads are in flight
+// together (len >= 1).
+__device__ __forceinline__ void stage_be_words(uint32_t *dst, const uint8_t *src, uint32_t len, uint32_t w0,
+                                               uint32_t n) {
+  const uint32_t lane = (uint32_t)lane_id();
+  for (uint32_t k0 = 0; k0 < n; k0 += 4 * kWave) {
+    uint32_t b[16];
 #pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const uint32_t i = 4 * k + j;
-    v = (v << 8) | (i < len ? (uint32_t)p[i] : 0u);
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const uint32_t i = 4 * (w0 + k0 + q * kWave + lane) + j;
+        b[q * 4 + j] = src[min(i, len - 1)];
+      }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint32_t k = k0 + q * kWave + lane;
+      uint32_t v = 0;
+#pragma unroll
+      for (int j = 0; j < 4; j++) v = (v << 8) | (4 * (w0 + k) + j < len ? b[q * 4 + j] : 0u);
+      if (k < n) dst[k] = v;
+    }
   }
-  return v;
 }
 
 // 32 bits starting at bit q of a word array (MSB first).
@@ -69,6 +86,38 @@ union BlockLds {
   DecodeLds dec;
 };
 
+// Follows code boundaries across the lanes' first-level entries e (symbol |
+// length << 9, one per lane for the code starting at that lane's bit): from
+// lane p (and k codes so far) it marks each code start in `starts` and moves
+// p by the code's length, while p < 64 and k < room.  Stops early at an entry
+// of length 0 and returns that entry (0: a longer code; otherwise no code).
+// Scalar registers and branches only: the chain is sequential by nature, and
+// a compiler-placed vector loop with masked branches cost ten times more.
+__device__ __forceinline__ uint32_t chain_follow(uint32_t e, uint32_t room, uint64_t &starts, uint32_t &p,
+                                                 uint32_t &k) {
+  uint32_t ep, l;
+  asm volatile(
+      "s_mov_b32 %[ep], 1\n"
+      "1:\n\t"
+      "s_cmp_ge_u32 %[p], 64\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_cmp_ge_u32 %[k], %[room]\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "v_readlane_b32 %[ep], %[e], %[p]\n\t"
+      "s_lshr_b32 %[l], %[ep], 9\n\t"
+      "s_cmp_eq_u32 %[l], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      "s_bitset1_b64 %[st], %[p]\n\t"
+      "s_add_u32 %[p], %[p], %[l]\n\t"
+      "s_add_u32 %[k], %[k], 1\n\t"
+      "s_branch 1b\n"
+      "2:"
+      : [st] "+s"(starts), [p] "+s"(p), [k] "+s"(k), [ep] "=&s"(ep), [l] "=&s"(l)
+      : [e] "v"(e), [room] "s"(room)
+      : "scc");
+  return ep;
+}
+
 // Canonical decode of a 32-bit window with table g (codes assigned in
 // (length, symbol) order): symbol | length << 9, or kInvalid.
 __device__ __forceinline__ uint32_t canon_decode(const DecodeLds &L, int g, uint32_t w) {
@@ -90,6 +139,9 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
   __shared__ uint8_t lens_lds[kMaxGroups][kMaxAlpha];
   __shared__ uint8_t seq_lds[256];
   __shared__ uint32_t over_lds;
+  // decoded symbols gather here and go to global memory a thousand at a time
+  // (a store per step made every step wait for the last one's data register)
+  __shared__ uint16_t obuf[kOutBuf];
   const uint32_t b = blockIdx.x;
   const DecBand B = bands[b];
   const int lane = threadIdx.x;
@@ -119,14 +171,26 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
   };
   // ---- stage the header bytes (big-endian words) into LDS
   const uint32_t head_bytes = min(len, kDecHeadBytes);
-  for (uint32_t k = lane; k < kDecHeadBytes / 4 + 2; k += 64) S.head.words[k] = be_word(src, head_bytes, k);
+  if (head_bytes > 0) stage_be_words(S.head.words, src, head_bytes, 0, kDecHeadBytes / 4 + 2);
   __syncthreads();
   // ---- header fields (every lane parses the same uniform values)
   const uint32_t *hw = S.head.words;
   const uint32_t hbits = head_bytes * 8;
   uint32_t q = 0;
+  // the two header words around q stay in registers while q moves inside them
+  uint32_t hci = 0xFFFFFFFFu;
+  uint64_t hw64 = 0;
+  auto peek = [&](uint32_t at) -> uint32_t {
+    const uint32_t i = at >> 5;
+    if (i != hci) {  // scalar registers: every lane parses the same header
+      hci = i;
+      hw64 = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)hw[i]) << 32) |
+             (uint32_t)__builtin_amdgcn_readfirstlane((int)hw[i + 1]);
+    }
+    return (uint32_t)((hw64 << (at & 31u)) >> 32);
+  };
   auto get = [&](uint32_t k) -> uint32_t {  // k <= 24 bits
-    const uint32_t v = bits32(hw, q) >> (32 - k);
+    const uint32_t v = peek(q) >> (32 - k);
     q += k;
     return v;
   };
@@ -170,7 +234,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
     uint32_t list = 0x543210u;  // 4 bits per entry, front in the low bits
     for (uint32_t k = 0; k < nsel; k++) {
       if (q > hbits) break;  // reported below
-      const uint32_t w = bits32(hw, q);
+      const uint32_t w = peek(q);
       const uint32_t j = __clz(~w);  // leading ones
       if (j >= G) {
         fail();
@@ -180,7 +244,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       const uint32_t v = (list >> (4 * j)) & 15u;
       const uint32_t below = (1u << (4 * j)) - 1u;
       list = (list & ~((below << 4) | 15u)) | ((list & below) << 4) | v;
-      if (lane == 0) sel_lds[k] = (uint8_t)v;
+      sel_lds[k] = (uint8_t)v;  // every lane writes the same value (no divergent branch)
     }
   }
   if (q > hbits) {
@@ -196,7 +260,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
           fail();
           return;
         }
-        const uint32_t w = bits32(hw, q);
+        const uint32_t w = peek(q);
         if (!(w >> 31)) {
           q += 1;
           break;
@@ -204,7 +268,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
         cur += (w >> 30) & 1u ? -1 : 1;
         q += 2;
       }
-      if (lane == 0) lens_lds[g][sy] = (uint8_t)cur;
+      lens_lds[g][sy] = (uint8_t)cur;
     }
   }
   if (q > hbits) {
@@ -246,11 +310,20 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
     return;
   }
   // first-level table: a prefix of kLutBits bits resolves when a code of at
-  // most kLutBits bits matches it; other prefixes (0) take the canonical search
+  // most kLutBits bits matches it; other prefixes (0) take the canonical
+  // search.  Each symbol with a short code fills the entries of its code
+  // (its code is first[l] plus its place among the codes of length l).
   for (uint32_t g = 0; g < G; g++)
-    for (uint32_t e = lane; e < kLutSize; e += 64) {
-      const uint32_t r = canon_decode(D, (int)g, e << (32 - kLutBits));
-      D.lut[g][e] = (uint16_t)(r != kInvalid && (r >> 9) <= (uint32_t)kLutBits ? r : 0u);
+    for (uint32_t e = lane; e < kLutSize; e += 64) D.lut[g][e] = 0;
+  __syncthreads();
+  for (uint32_t g = 0; g < G; g++)
+    for (uint32_t i = lane; i < alpha; i += 64) {
+      const uint32_t sy = D.perm[g][i];
+      const uint32_t l = lens_lds[g][sy];
+      if (l > (uint32_t)kLutBits) continue;
+      const uint32_t c = D.first[g][l] + (i - D.base[g][l]);
+      const uint32_t e0 = c << (kLutBits - l), e1 = (c + 1) << (kLutBits - l);
+      for (uint32_t e = e0; e < e1 && e < kLutSize; e++) D.lut[g][e] = (uint16_t)(sy | (l << 9));
     }
   // the symbol map goes to global memory for the move-to-front stage
   for (uint32_t i = lane; i < 256; i += 64) seq_all[(size_t)slot * 256 + i] = i < n_in_use ? seq_lds[i] : 0;
@@ -261,55 +334,77 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
   const uint32_t eob = alpha - 1;
   uint32_t o = data_bit;         // bit position relative to src
   uint32_t wbase = 0xFFFFFFFFu;  // first bit held by the window
-  uint32_t g = 0, in_grp = 0, nsym = 0;
+  uint32_t g = 0, in_grp = 0, nsym = 0, nbuf = 0;
   uint32_t t = sel_lds[0];
+  auto flush = [&]() {
+    for (uint32_t i = lane; i < nbuf; i += 64) out[nsym - nbuf + i] = obuf[i];
+    nbuf = 0;
+  };
   bool done = false, ok = true;
   const uint32_t total_bits = len * 8;
   while (!done) {
-    if (o > total_bits) {  // ran past the band
+    if (o > total_bits || g >= nsel) {  // ran past the band, or past the last group
       ok = false;
       break;
     }
     if (wbase == 0xFFFFFFFFu || o + 64 + 32 > wbase + kWinWords * 32) {
       __syncthreads();
       wbase = o & ~31u;
-      const uint32_t w0 = wbase >> 5;
-      for (uint32_t k = lane; k < kWinWords + 4; k += 64) D.win[k] = be_word(src, len, w0 + k);
+      stage_be_words(D.win, src, len, wbase >> 5, kWinWords + 4);
       __syncthreads();
     }
     const uint32_t w = bits32(D.win, o - wbase + lane);
+    // first-level table only: most lanes sit at positions that are no code
+    // boundary, and a longer code is decoded below when the chain reaches it
     uint32_t e = D.lut[t][w >> (32 - kLutBits)];
-    if (e == 0u) e = canon_decode(D, (int)t, w);
-    uint32_t p = 0, cnt = 0, outv = 0;
-    while (p < 64) {
-      const uint32_t ep = (uint32_t)__builtin_amdgcn_readlane((int)e, (int)p);
-      const uint32_t sy = ep & 0x1FFu;
-      if (sy == kInvalid || nsym >= sym_cap) {
-        ok = false;
-        done = true;
+    // follow the true code boundaries from the first lane, marking them, for
+    // at most the rest of the group; what the symbols are is settled after
+    const uint32_t room = (uint32_t)__builtin_amdgcn_readfirstlane((int)(kGroupSize - in_grp));
+    uint64_t starts = 0;
+    uint32_t p = 0, k = 0;
+    bool stuck = false;
+    for (;;) {
+      const uint32_t ep = chain_follow(e, room, starts, p, k);
+      if (p >= 64 || k >= room) break;
+      // the chain stopped on an entry of length 0: a code longer than the
+      // first-level table (decoded here and put into that lane), or none
+      const uint32_t r = ep == 0u ? canon_decode(D, (int)t, (uint32_t)__builtin_amdgcn_readlane((int)w, (int)p))
+                                  : kInvalid;
+      if ((r >> 9) == 0u) {
+        stuck = true;
         break;
       }
-      outv = lane == (int)cnt ? sy : outv;
-      cnt++;
-      nsym++;
-      p += ep >> 9;
-      if (sy == eob) {
-        done = true;
-        break;
-      }
-      if (++in_grp == kGroupSize) {
-        in_grp = 0;
-        if (++g >= nsel) {
-          ok = false;
-          done = true;
-          break;
-        }
-        t = sel_lds[g];
-        break;
-      }
+      e = lane == (int)p ? r : e;
     }
-    if ((uint32_t)lane < cnt) out[nsym - cnt + lane] = (uint16_t)outv;
-    o += p;
+    const bool at = (starts >> lane) & 1ull;
+    const uint32_t sy = e & 0x1FFu;
+    const uint64_t ends = ballot64(at && sy == eob);
+    uint32_t adv = p;  // bits consumed
+    if (ends) {  // the block ends: drop whatever was followed past its last symbol
+      const uint32_t f = (uint32_t)__builtin_ctzll(ends);
+      starts &= f == 63 ? ~0ull : (2ull << f) - 1ull;
+      adv = f + ((uint32_t)__builtin_amdgcn_readlane((int)e, (int)f) >> 9);
+      done = true;
+    } else if (stuck) {
+      ok = false;
+      break;
+    }
+    const uint32_t cnt = (uint32_t)__popcll(starts);
+    if (nsym + cnt > sym_cap) {
+      ok = false;
+      break;
+    }
+    if ((starts >> lane) & 1ull) obuf[nbuf + (uint32_t)__popcll(starts & lanemask_lt())] = (uint16_t)sy;
+    nsym += cnt;
+    nbuf += cnt;
+    if (nbuf > kOutBuf - 64 || done) flush();
+    o += adv;
+    in_grp += cnt;
+    if (in_grp == kGroupSize) {
+      in_grp = 0;
+      g++;
+      if (g < nsel) t = sel_lds[g];
+    }
   }
   // end of stream: magic 0x177245385090, the combined CRC (= the block CRC
   // for a one-block stream), padding to a byte
@@ -318,8 +413,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       ok = false;
     } else {
       __syncthreads();
-      const uint32_t w0 = o >> 5;
-      for (uint32_t k = lane; k < 8; k += 64) D.win[k] = be_word(src, len, w0 + k);
+      stage_be_words(D.win, src, len, o >> 5, 8);
       __syncthreads();
       const uint32_t r = o & 31u;
       const uint32_t a = bits32(D.win, r), c = bits32(D.win, r + 32), d = bits32(D.win, r + 64);
