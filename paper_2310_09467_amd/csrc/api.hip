@@ -449,9 +449,7 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.L = A.get<uint8_t>(nr + 16);
   w.codes = A.get<BlockCode>(S + 1);
   w.max_chunks = (uint32_t)(nr / kMtfChunk + S + 2);
-  w.mw.seq = A.get<uint8_t>((size_t)S * 256);
   w.mw.used = A.get<uint32_t>((size_t)S * 8);
-  w.mw.used_chunk = A.get<uint32_t>((size_t)(nr / kMtfChunk + S + 2) * 8);
   w.mw.chunk_block = A.get<uint32_t>(w.max_chunks + 1);
   w.mw.plist = A.get<uint8_t>((size_t)w.max_chunks * 256);
   w.mw.plen = A.get<uint32_t>(w.max_chunks);
@@ -461,7 +459,6 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.mw.idx = A.get<uint8_t>(nr + 16);
   // the MTF stage runs after the suffix sort: reuse the sort's key buffers
   w.mw.zs = w.bw.key[0] ? (uint32_t *)w.bw.key[0] : nullptr;
-  w.mw.off = w.bw.key[1] ? (uint32_t *)w.bw.key[1] : nullptr;
   w.mw.aggs = w.bw.aggs;  // free once the suffix sort is done
   w.mw.d_n_chunks = w.ctr ? w.ctr + 4 : nullptr;
   w.max_sym = (uint32_t)(nr + S + 1);

@@ -6,8 +6,13 @@
 // occurrence (most recent first) move to the front, the rest keep their
 // order.  So (1) every chunk computes that partial list, (2) the partial lists
 // are chained (in three shallow steps) into each chunk's incoming list, and
-// (3) every chunk replays move-to-front from its incoming list (ranks in
-// registers, see k_mtf_run).
+// (3) every chunk replays move-to-front from its incoming list (k_mtf_run).
+// Lists hold byte values.  A block's initial list is its used bytes in
+// ascending order (the order of the format's symbol map, so a list position
+// is the format's index), then the unused bytes, which never move.  Chunks
+// are short (256 positions): the replay's cost per chunk varies with the
+// data (runs are skipped, symbols deep in the list cost more), and short
+// chunks keep the slowest wavefront close to the average.
 //
 // Zero runs: a run of r zero indices becomes the bijective base-2 digits of
 // r, least significant first (RUNA = 0 for digit 1, RUNB = 1 for digit 2); a
@@ -20,6 +25,7 @@ namespace pcbz {
 namespace {
 
 constexpr uint32_t kChunk = kMtfChunk;
+static_assert(kChunk % 64 == 0 && kChunk <= 1024, "a chunk is replayed from registers, 64 positions a batch");
 
 __device__ __forceinline__ void chunk_range(uint32_t c, const uint32_t *chunk_base, const uint32_t *blk_start,
                                             uint32_t nb, uint32_t &b, uint32_t &p0, uint32_t &p1, uint32_t &bs,
@@ -49,59 +55,14 @@ __global__ void k_mtf_chunks(const uint32_t *blk_start, const uint32_t *d_nb, ui
   *d_n_chunks = acc;
 }
 
-// Used-byte bitmap of each chunk (8 words, plain stores; k_seq ORs a block's).
-__global__ __launch_bounds__(256) void k_used(const uint8_t *L, const uint32_t *chunk_base, const uint32_t *d_n_chunks,
-                                              const uint32_t *blk_start, const uint32_t *d_nb, uint32_t *used_chunk) {
-  __shared__ uint32_t f[256];
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
-  uint32_t b, p0, p1, bs, be;
-  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  f[threadIdx.x] = 0;
-  __syncthreads();
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) f[L[p]] = 1;
-  __syncthreads();
-  const uint64_t bal = ballot64(f[threadIdx.x] != 0);
-  if (lane_id() == 0) {
-    const uint32_t wbase = threadIdx.x / 32;  // word index of this lane group
-    used_chunk[(size_t)c * 8 + wbase] = (uint32_t)bal;
-    used_chunk[(size_t)c * 8 + wbase + 1] = (uint32_t)(bal >> 32);
-  }
-  (void)b;
-}
-
-__global__ __launch_bounds__(256) void k_seq(const uint32_t *used_chunk, uint32_t *used, const uint32_t *d_nb,
-                                             uint8_t *seq, BlockCode *codes) {
-  __shared__ uint32_t u[8];
-  const uint32_t b = blockIdx.x;
-  if (b >= *d_nb) return;
-  const uint32_t c = threadIdx.x;
-  if (c < 8) u[c] = 0;
-  __syncthreads();
-  {
-    // OR of the block's chunk bitmaps: thread t ORs word t % 8 of chunks t / 8, t / 8 + 32, ...
-    const uint32_t k0 = codes[b].chunk_start, nc = codes[b].n_chunks, wd = c & 7u;
-    uint32_t acc = 0;
-    for (uint32_t k = c >> 3; k < nc; k += 32) acc |= used_chunk[(size_t)(k0 + k) * 8 + wd];
-    if (acc) atomicOr(&u[wd], acc);
-  }
-  __syncthreads();
-  if (c < 8) used[b * 8 + c] = u[c];
-  uint32_t before = 0;
-  for (uint32_t k = 0; k < c / 32; k++) before += __popc(u[k]);
-  before += __popc(u[c / 32] & ((1u << (c % 32)) - 1u));
-  seq[b * 256 + c] = (uint8_t)before;
-  if (c == 255) {
-    uint32_t nu = before + ((u[7] >> 31) & 1u);
-    codes[b].n_in_use = nu;
-    codes[b].alpha = nu + 2;
-  }
-}
-
+// The partial list of a chunk orders its bytes by last occurrence, latest
+// first: walking the chunk backwards, it is the sequence of positions that
+// hold the last occurrence of their byte.  Lane l takes the kPer positions
+// p1 - 1 - kPer l down to p1 - kPer (l + 1); a wavefront prefix count of the
+// flagged positions gives each its place in the list.
 __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint32_t *chunk_base,
                                                     const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                    const uint32_t *d_nb, const uint8_t *seq, uint8_t *plist,
-                                                    uint32_t *plen) {
+                                                    const uint32_t *d_nb, uint8_t *plist, uint32_t *plen) {
   __shared__ int lastpos[256];
   const uint32_t c = blockIdx.x;
   if (c >= *d_n_chunks) return;
@@ -109,28 +70,25 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   for (int v = threadIdx.x; v < 256; v += 64) lastpos[v] = -1;
   __syncthreads();
-  const uint8_t *sq = seq + b * 256;
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 64) atomicMax(&lastpos[sq[L[p]]], (int)(p - p0));
-  __syncthreads();
-  // the partial list orders the chunk's symbols by last occurrence, latest
-  // first: walking the chunk backwards, it is the sequence of positions that
-  // hold the last occurrence of their symbol.  Lane l takes the 16 positions
-  // p1 - 1 - 16 l down to p1 - 16 (l + 1); a wavefront prefix count of the
-  // flagged positions gives each its place in the list.
   constexpr uint32_t kPer = kChunk / 64;
   const uint32_t n = p1 - p0, lane = threadIdx.x;
-  uint32_t flags = 0;
   uint8_t sy[kPer];
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
     const uint32_t q = lane * kPer + i;
-    sy[i] = 0;
-    if (q < n) {
-      const uint32_t p = p1 - 1 - q;
-      const uint8_t v = sq[L[p]];
-      sy[i] = v;
-      if (lastpos[v] == (int)(p - p0)) flags |= 1u << i;
-    }
+    sy[i] = q < n ? L[p1 - 1 - q] : (uint8_t)0;
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++) {
+    const uint32_t q = lane * kPer + i;
+    if (q < n) atomicMax(&lastpos[sy[i]], (int)(n - 1 - q));
+  }
+  __syncthreads();
+  uint32_t flags = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; i++) {
+    const uint32_t q = lane * kPer + i;
+    if (q < n && lastpos[sy[i]] == (int)(n - 1 - q)) flags |= 1u << i;
   }
   const uint32_t cnt = (uint32_t)__popc(flags);
   uint32_t incl = cnt;
@@ -143,6 +101,7 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
   for (uint32_t i = 0; i < kPer; i++)
     if ((flags >> i) & 1u) plist[(size_t)c * 256 + r++] = sy[i];
   if (lane == 63) plen[c] = incl;
+  (void)b;
 }
 
 // List chaining.  Folding a partial list P onto a list C gives P followed by
@@ -150,48 +109,75 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
 // chunks are chained in three shallow steps instead of one long one:
 //   1. each of kMtfSegs segments of the block folds its chunks' partial lists
 //      (from an empty list) into a segment partial list;
-//   2. one workgroup per block folds the segment lists from the initial list
-//      (ascending order), recording the list entering each segment;
+//   2. one wavefront per block takes the block's used bytes from the segment
+//      lists, builds the initial list and folds the segment lists onto it,
+//      recording the list entering each segment;
 //   3. each segment folds its chunks again from its entering list, recording
 //      the list entering each chunk.
-// A fold step runs on one workgroup of 256 threads, one list entry each.
-struct FoldLds {
-  uint8_t cur[256], nxt[256], mem[256];
-  uint32_t len;
-  uint32_t wcnt[4];
-};
+// Every step is one wavefront with its lists staged in LDS up front; a list
+// of up to 256 bytes sits in four registers (lane l holds positions l,
+// l + 64, l + 128, l + 192) and a fold step needs no workgroup barrier.
 
-// cur/len := P ++ (cur - P) for units [0, n) of (lists, lens); before unit k
-// the current list is written to out_in + k * 256 when out_in is set.
-__device__ void fold_units(FoldLds &F, const uint8_t *lists, const uint32_t *lens, uint32_t n, uint8_t *out_in) {
-  const uint32_t e = threadIdx.x;
-  const int lane = lane_id(), w = threadIdx.x / kWave;
+// cur/len := P ++ (cur - P), P given as pv (lane l: positions l + 64 k) of
+// length pl.  mark[x] == stamp flags the bytes of P (stamps grow by one per
+// step, so mark is never cleared); buf is the new list.  Branch-free: lanes
+// with nothing to write write to their own slot past the 256 entries, so
+// each group of LDS accesses goes out at once (three round trips a step).
+constexpr uint32_t kFoldSlots = 256 + 64;
+
+__device__ __forceinline__ void wave_fold(uint32_t (&cur)[4], uint32_t &len, const uint32_t (&pv)[4], uint32_t pl,
+                                          uint32_t stamp, uint32_t *mark, uint8_t *buf) {
+  const uint32_t lane = (uint32_t)lane_id();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) mark[lane + 64 * k < pl ? pv[k] : 256 + lane] = stamp;
+  __builtin_amdgcn_wave_barrier();
+  uint32_t mk[4];
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) mk[k] = mark[cur[k]];  // cur holds bytes, also past len
   const uint64_t lt = lanemask_lt();
-  for (uint32_t k = 0; k < n; k++) {
-    if (out_in) out_in[(size_t)k * 256 + e] = F.cur[e];
-    F.mem[e] = 0;
-    __syncthreads();
-    const uint32_t pl = lens[k];
-    if (e < pl) {
-      const uint8_t v = lists[(size_t)k * 256 + e];
-      F.mem[v] = 1;
-      F.nxt[e] = v;
-    }
-    __syncthreads();
-    const bool keep = e < F.len && !F.mem[F.cur[e]];
+  uint32_t base = pl;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    const bool keep = lane + 64 * k < len && mk[k] != stamp;
     const uint64_t bal = ballot64(keep);
-    if (lane == 0) F.wcnt[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t off = (uint32_t)__popcll(bal & lt), tot = 0;
-    for (int q = 0; q < 4; q++) {
-      if (q < w) off += F.wcnt[q];
-      tot += F.wcnt[q];
+    buf[keep ? base + (uint32_t)__popcll(bal & lt) : 256 + lane] = (uint8_t)cur[k];
+    base += (uint32_t)__popcll(bal);
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) buf[lane + 64 * k < pl ? lane + 64 * k : 256 + lane] = (uint8_t)pv[k];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) cur[k] = buf[lane + 64 * k];
+  len = base;
+}
+
+// list i of the LDS-staged lists, lane l taking positions l + 64 k
+__device__ __forceinline__ void lds_list(uint32_t (&pv)[4], const uint8_t *lists, uint32_t i) {
+  const uint32_t lane = (uint32_t)lane_id();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) pv[k] = lists[i * 256 + lane + 64 * k];
+}
+
+// folds the staged lists [0, n) onto cur (stamps 1..n); before fold i the
+// list is written to out + i * 256 when out is set.  The next list is read
+// while the current fold runs.
+__device__ __forceinline__ void fold_staged(uint32_t (&cur)[4], uint32_t &len, const uint8_t *lists,
+                                            const uint32_t *lens, uint32_t n, uint32_t *mark, uint8_t *buf,
+                                            uint8_t *out) {
+  const uint32_t lane = (uint32_t)lane_id();
+  if (n == 0) return;
+  uint32_t pv[4];
+  lds_list(pv, lists, 0);
+  for (uint32_t i = 0; i < n; i++) {
+    if (out) {
+#pragma unroll
+      for (uint32_t k = 0; k < 4; k++) out[(size_t)i * 256 + lane + 64 * k] = (uint8_t)cur[k];
     }
-    if (keep) F.nxt[pl + off] = F.cur[e];
-    __syncthreads();
-    F.cur[e] = F.nxt[e];
-    if (e == 0) F.len = pl + tot;
-    __syncthreads();
+    uint32_t nx[4];
+    lds_list(nx, lists, min(i + 1, n - 1));
+    wave_fold(cur, len, pv, lens[i], i + 1, mark, buf);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) pv[k] = nx[k];
   }
 }
 
@@ -201,41 +187,105 @@ __device__ __forceinline__ void seg_range(const BlockCode &C, uint32_t j, uint32
   u1 = min(C.n_chunks, u0 + per);
 }
 
-// step 1: grid (kMtfSegs, blocks)
-__global__ __launch_bounds__(256) void k_mtf_seg_fold(const uint32_t *d_nb, const BlockCode *codes,
-                                                      const uint8_t *plist, const uint32_t *plen, uint8_t *seglist,
-                                                      uint32_t *seglen) {
+// the partial lists of chunks [c0, c0 + n) into LDS
+__device__ __forceinline__ void stage_lists(uint8_t *lists, uint32_t *lens, const uint8_t *plist,
+                                            const uint32_t *plen, uint32_t c0, uint32_t n) {
+  stage_to_lds((uint32_t *)lists, (const uint32_t *)(plist + (size_t)c0 * 256), n * 64);
+  stage_to_lds(lens, plen + c0, n);
+}
+
+struct FoldLds {
+  uint8_t lists[kMtfUnits * 256];
+  uint32_t lens[kMtfUnits];
+  uint32_t mark[kFoldSlots];
+  uint8_t buf[kFoldSlots];
+};
+
+// step 1: grid (kMtfSegs, blocks), one wavefront each
+__global__ __launch_bounds__(64) void k_mtf_seg_fold(const uint32_t *d_nb, const BlockCode *codes,
+                                                     const uint8_t *plist, const uint32_t *plen, uint8_t *seglist,
+                                                     uint32_t *seglen) {
   __shared__ FoldLds F;
   const uint32_t b = blockIdx.y, j = blockIdx.x;
   if (b >= *d_nb) return;
   const BlockCode C = codes[b];
   uint32_t u0, u1;
   seg_range(C, j, u0, u1);
-  if (threadIdx.x == 0) F.len = 0;
+  const uint32_t n = u1 - u0, lane = (uint32_t)lane_id();
+  stage_lists(F.lists, F.lens, plist, plen, C.chunk_start + u0, n);
+  for (uint32_t e = lane; e < kFoldSlots; e += 64) F.mark[e] = 0;
   __syncthreads();
-  fold_units(F, plist + (size_t)(C.chunk_start + u0) * 256, plen + C.chunk_start + u0, u1 - u0, nullptr);
-  seglist[((size_t)b * kMtfSegs + j) * 256 + threadIdx.x] = F.cur[threadIdx.x];
-  if (threadIdx.x == 0) seglen[(size_t)b * kMtfSegs + j] = F.len;
+  uint32_t cur[4] = {0, 0, 0, 0}, len = 0;
+  fold_staged(cur, len, F.lists, F.lens, n, F.mark, F.buf, nullptr);
+  uint8_t *o = seglist + ((size_t)b * kMtfSegs + j) * 256;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) o[lane + 64 * k] = (uint8_t)cur[k];
+  if (lane == 0) seglen[(size_t)b * kMtfSegs + j] = len;
 }
 
-// step 2: one workgroup per block; the segment lists are replaced by the
-// lists entering the segments
-__global__ __launch_bounds__(256) void k_mtf_seg_chain(const uint32_t *d_nb, uint8_t *seglist, const uint32_t *seglen) {
-  __shared__ FoldLds F;
-  __shared__ uint8_t parts[kMtfSegs * 256];
+// step 2: one wavefront per block; also writes the block's used-byte bitmap
+// and symbol-map size.  The segment lists are replaced by the lists entering
+// the segments.
+__global__ __launch_bounds__(64) void k_mtf_seg_chain(const uint32_t *d_nb, uint8_t *seglist, const uint32_t *seglen,
+                                                      uint32_t *used, BlockCode *codes) {
+  __shared__ uint8_t lists[kMtfSegs * 256];
+  __shared__ uint32_t lens[kMtfSegs];
+  __shared__ uint32_t mark[kFoldSlots];
+  __shared__ uint8_t buf[kFoldSlots];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
+  const uint32_t lane = (uint32_t)lane_id();
   uint8_t *sl = seglist + (size_t)b * kMtfSegs * 256;
-  for (uint32_t i = threadIdx.x; i < kMtfSegs * 256; i += 256) parts[i] = sl[i];
-  F.cur[threadIdx.x] = (uint8_t)threadIdx.x;
-  if (threadIdx.x == 0) F.len = 256;
+  stage_lists(lists, lens, sl, seglen + (size_t)b * kMtfSegs, 0, kMtfSegs);
+  for (uint32_t e = lane; e < kFoldSlots; e += 64) mark[e] = 0;
   __syncthreads();
-  fold_units(F, parts, seglen + (size_t)b * kMtfSegs, kMtfSegs, sl);
+  // the block's used bytes: every byte of a segment list
+  for (uint32_t i = 0; i < kMtfSegs; i++) {
+    const uint32_t l = lens[i];
+    for (uint32_t e = lane; e < l; e += 64) mark[lists[i * 256 + e]] = 1;
+  }
+  __syncthreads();
+  uint64_t ub[4];
+  uint32_t nu = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    ub[k] = ballot64(mark[lane + 64 * k] != 0);
+    nu += (uint32_t)__popcll(ub[k]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (uint32_t w = 0; w < 8; w++) used[b * 8 + w] = (uint32_t)(ub[w / 2] >> (32 * (w % 2)));
+    codes[b].n_in_use = nu;
+    codes[b].alpha = nu + 2;
+  }
+  // initial list: used bytes ascending, then the unused ones
+  const uint64_t lt = lanemask_lt();
+  uint32_t nbu = 0, nbn = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    const bool u = (ub[k] >> lane) & 1ull;
+    const uint32_t pos = u ? nbu + (uint32_t)__popcll(ub[k] & lt) : nu + nbn + (uint32_t)__popcll(~ub[k] & lt);
+    buf[pos] = (uint8_t)(lane + 64 * k);
+    nbu += (uint32_t)__popcll(ub[k]);
+    nbn += 64u - (uint32_t)__popcll(ub[k]);
+  }
+  __syncthreads();
+  uint32_t cur[4], len = 256;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) {
+    cur[k] = buf[lane + 64 * k];
+    mark[lane + 64 * k] = 0;
+  }
+  __syncthreads();
+  // the last segment's fold is not needed (its result is the block's end)
+  fold_staged(cur, len, lists, lens, kMtfSegs - 1, mark, buf, sl);
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) sl[(kMtfSegs - 1) * 256 + lane + 64 * k] = (uint8_t)cur[k];
 }
 
-// step 3: grid (kMtfSegs, blocks)
-__global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
-                                                   const uint32_t *plen, const uint8_t *seglist, uint8_t *inlist) {
+// step 3: grid (kMtfSegs, blocks), one wavefront each
+__global__ __launch_bounds__(64) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
+                                                  const uint32_t *plen, const uint8_t *seglist, uint8_t *inlist) {
   __shared__ FoldLds F;
   const uint32_t b = blockIdx.y, j = blockIdx.x;
   if (b >= *d_nb) return;
@@ -243,112 +293,170 @@ __global__ __launch_bounds__(256) void k_mtf_chain(const uint32_t *d_nb, const B
   uint32_t u0, u1;
   seg_range(C, j, u0, u1);
   if (u0 >= u1) return;
-  F.cur[threadIdx.x] = seglist[((size_t)b * kMtfSegs + j) * 256 + threadIdx.x];
-  if (threadIdx.x == 0) F.len = 256;
+  const uint32_t n = u1 - u0, lane = (uint32_t)lane_id();
+  stage_lists(F.lists, F.lens, plist, plen, C.chunk_start + u0, n);
+  const uint8_t *si = seglist + ((size_t)b * kMtfSegs + j) * 256;
+  uint32_t cur[4], len = 256;
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) cur[k] = si[lane + 64 * k];
+  for (uint32_t e = lane; e < kFoldSlots; e += 64) F.mark[e] = 0;
   __syncthreads();
-  fold_units(F, plist + (size_t)(C.chunk_start + u0) * 256, plen + C.chunk_start + u0, u1 - u0,
-             inlist + (size_t)(C.chunk_start + u0) * 256);
+  uint8_t *o = inlist + (size_t)(C.chunk_start + u0) * 256;
+  fold_staged(cur, len, F.lists, F.lens, n - 1, F.mark, F.buf, o);
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) o[(size_t)(n - 1) * 256 + lane + 64 * k] = (uint8_t)cur[k];
 }
 
-// Replay of one chunk by one wavefront.  The list is held as ranks (the
-// position of each symbol), 16 bits per symbol, two symbols per register and
-// two registers per lane: lane l holds the ranks of symbols l and l + 64
-// (R0 low / high half) and l + 128 and l + 192 (R1).  A step reads the rank
-// r of its symbol from the owning lane (uniform), then every lane updates
-// both halves of both registers with packed 16-bit arithmetic: ranks below r
-// grow by one, the rank equal to r (the symbol itself; ranks are distinct)
-// becomes 0.  No lane diverges and no data moves between lanes.
-// ranks x (two halves, each <= 255) after the symbol at rank r moves to front:
-// t = x - r per half (wrapping below r), lt = t >> 15 (1 where x < r),
-// ne = min(t, 1) (1 where x != r), result (x + lt) * ne.  Written as packed
-// 16-bit instructions: the compiler otherwise splits the halves apart.  r is
-// the low half of the scalar operand (both halves subtract it; its high
-// half is ignored).
-__device__ __forceinline__ uint32_t mtf_ranks(uint32_t x, uint32_t r) {
-  uint32_t t, lt, y, ne, out;
-  asm("v_pk_sub_u16 %0, %1, %2 op_sel_hi:[1,0]" : "=v"(t) : "v"(x), "s"(r));
-  asm("v_pk_lshrrev_b16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(lt) : "v"(t));
-  asm("v_pk_add_u16 %0, %1, %2" : "=v"(y) : "v"(x), "v"(lt));
-  asm("v_pk_min_u16 %0, %1, 1 op_sel_hi:[1,0]" : "=v"(ne) : "v"(t));
-  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(out) : "v"(y), "v"(ne));
-  return out;
+// Replay of one chunk by one wavefront.  The list itself is held in four
+// registers: lane l of Q[i] holds list position 64 i + l, as the byte value
+// there.  A step finds its symbol by one compare with Q[0] (with
+// Q[1..3] only when it is not among the first 64 entries), then moves it to
+// the front: the entries in front of it shift back by one lane with a
+// wavefront shift (DPP wave_shr:1), the symbol enters lane 0 of Q[0], and a
+// register shifted whole passes its lane 63 on to lane 0 of the next one.
+// For LFM data most non-zero indices are below 64.
+//
+// mtf_batch replays the positions of `todo` (lanes of the batch vl) in
+// order; lane k of `mine` takes the index of position k.  A symbol among
+// the first 64 entries (lane q of Q0) costs six vector and six scalar
+// instructions: lanes 0..q of Q0 take Q0 shifted by one lane, lane 0 the
+// symbol.  A deeper one (lane q of Q[j], j >= 1) shifts Q[0..j-1] whole
+// (each passing its lane 63 on to lane 0 of the next) and lanes 0..q of
+// Q[j].  The lane number lives in m0 (v_readlane / v_writelane select).
+// All 64 lanes hold list entries, so the loop runs with the full exec mask
+// (set here, five wait states before the first DPP, restored at the end);
+// a DPP source needs two wait states after a vector write: the fast path's
+// was written a dozen instructions earlier, the others get an s_nop.
+__device__ __forceinline__ void mtf_batch(uint32_t &Q0, uint32_t &Q1, uint32_t &Q2, uint32_t &Q3, uint32_t &mine,
+                                          uint64_t todo, uint32_t vl) {
+  uint32_t v, q, c0, c1, c2, t;
+  uint64_t mq, m1, m2, mk, ex;
+  asm volatile(
+      "s_mov_b64 %[ex], exec\n\t"
+      "s_mov_b64 exec, -1\n\t"
+      "s_nop 4\n"
+      "1:\n\t"
+      "s_cmp_eq_u64 %[todo], 0\n\t"
+      "s_cbranch_scc1 9f\n\t"
+      "s_ff1_i32_b64 m0, %[todo]\n\t"
+      "s_bitset0_b64 %[todo], m0\n\t"
+      "v_readlane_b32 %[v], %[vl], m0\n\t"
+      "v_cmp_eq_u32_e64 %[mq], %[v], %[Q0]\n\t"
+      "s_cmp_eq_u64 %[mq], 0\n\t"
+      "s_cbranch_scc1 2f\n\t"
+      // in Q0 at lane q
+      "s_ff1_i32_b64 %[q], %[mq]\n\t"
+      "s_lshl_b64 %[mk], -2, %[q]\n\t"
+      "v_mov_b32 %[t], %[v]\n\t"
+      "v_mov_b32_dpp %[t], %[Q0] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_cndmask_b32_e64 %[Q0], %[t], %[Q0], %[mk]\n\t"
+      "v_writelane_b32 %[mine], %[q], m0\n\t"
+      "s_branch 1b\n"
+      // deeper: Q0 shifts whole
+      "2:\n\t"
+      "v_cmp_eq_u32_e64 %[m1], %[v], %[Q1]\n\t"
+      "v_cmp_eq_u32_e64 %[m2], %[v], %[Q2]\n\t"
+      "v_cmp_eq_u32_e64 %[mq], %[v], %[Q3]\n\t"
+      "v_readlane_b32 %[c0], %[Q0], 63\n\t"
+      "v_readlane_b32 %[c1], %[Q1], 63\n\t"
+      "v_readlane_b32 %[c2], %[Q2], 63\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[Q0], %[Q0] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_writelane_b32 %[Q0], %[v], 0\n\t"
+      "s_cmp_eq_u64 %[m1], 0\n\t"
+      "s_cbranch_scc1 3f\n\t"
+      // in Q1 at lane q
+      "s_ff1_i32_b64 %[q], %[m1]\n\t"
+      "s_lshl_b64 %[mk], -2, %[q]\n\t"
+      "v_mov_b32 %[t], %[c0]\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[t], %[Q1] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_cndmask_b32_e64 %[Q1], %[t], %[Q1], %[mk]\n\t"
+      "s_add_u32 %[q], %[q], 64\n\t"
+      "v_writelane_b32 %[mine], %[q], m0\n\t"
+      "s_branch 1b\n"
+      // deeper: Q1 shifts whole
+      "3:\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[Q1], %[Q1] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_writelane_b32 %[Q1], %[c0], 0\n\t"
+      "s_cmp_eq_u64 %[m2], 0\n\t"
+      "s_cbranch_scc1 4f\n\t"
+      // in Q2 at lane q
+      "s_ff1_i32_b64 %[q], %[m2]\n\t"
+      "s_lshl_b64 %[mk], -2, %[q]\n\t"
+      "v_mov_b32 %[t], %[c1]\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[t], %[Q2] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_cndmask_b32_e64 %[Q2], %[t], %[Q2], %[mk]\n\t"
+      "s_add_u32 %[q], %[q], 128\n\t"
+      "v_writelane_b32 %[mine], %[q], m0\n\t"
+      "s_branch 1b\n"
+      // in Q3 at lane q (every used byte is in the list): Q2 shifts whole
+      "4:\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[Q2], %[Q2] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_writelane_b32 %[Q2], %[c1], 0\n\t"
+      "s_ff1_i32_b64 %[q], %[mq]\n\t"
+      "s_lshl_b64 %[mk], -2, %[q]\n\t"
+      "v_mov_b32 %[t], %[c2]\n\t"
+      "s_nop 1\n\t"
+      "v_mov_b32_dpp %[t], %[Q3] wave_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_cndmask_b32_e64 %[Q3], %[t], %[Q3], %[mk]\n\t"
+      "s_add_u32 %[q], %[q], 192\n\t"
+      "v_writelane_b32 %[mine], %[q], m0\n\t"
+      "s_branch 1b\n"
+      "9:\n\t"
+      "s_mov_b64 exec, %[ex]"
+      : [Q0] "+v"(Q0), [Q1] "+v"(Q1), [Q2] "+v"(Q2), [Q3] "+v"(Q3), [mine] "+v"(mine), [todo] "+s"(todo),
+        [v] "=&s"(v), [q] "=&s"(q), [c0] "=&s"(c0), [c1] "=&s"(c1), [c2] "=&s"(c2), [mq] "=&s"(mq), [m1] "=&s"(m1),
+        [m2] "=&s"(m2), [mk] "=&s"(mk), [t] "=&v"(t), [ex] "=&s"(ex)
+      : [vl] "v"(vl)
+      : "scc", "m0");
+}
+
+// wavefront shift right by one lane; lane 0 takes `in`
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t x, uint32_t in) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)in, (int)x, 0x138, 0xf, 0xf, false);
 }
 
 constexpr int kRunWaves = 4;  // chunks per workgroup, one per wavefront
 
 __global__ __launch_bounds__(64 * kRunWaves) void k_mtf_run(const uint8_t *L, const uint32_t *chunk_base,
                                                             const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                            const uint32_t *d_nb, const uint8_t *seq,
-                                                            const uint8_t *inlist, uint8_t *idx) {
-  __shared__ uint8_t rk_all[kRunWaves][256];
-  __shared__ uint8_t smap_all[kRunWaves][256];
-  __shared__ uint8_t ssym_all[kRunWaves][kChunk];
-  const uint32_t wv = threadIdx.x / kWave;
-  uint8_t *rk = rk_all[wv], *smap = smap_all[wv], *ssym = ssym_all[wv];
-  const uint32_t c = blockIdx.x * kRunWaves + wv;
-  const bool have = c < *d_n_chunks;  // every wavefront reaches the barriers below
-  uint32_t b = 0, p0 = 0, p1 = 0, bs, be;
-  if (have) chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
+                                                            const uint32_t *d_nb, const uint8_t *inlist,
+                                                            uint8_t *idx) {
+  const uint32_t c = blockIdx.x * kRunWaves + threadIdx.x / kWave;
+  if (c >= *d_n_chunks) return;  // the wavefronts of a workgroup are independent
+  uint32_t b, p0, p1, bs, be;
+  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
   const uint32_t lane = (uint32_t)lane_id();
   const uint32_t m = p1 - p0;
-  if (have) {
-    const uint8_t *il = inlist + (size_t)c * 256;
-    for (uint32_t e = lane; e < 256; e += 64) {
-      rk[il[e]] = (uint8_t)e;
-      smap[e] = seq[b * 256 + e];
-    }
-    // the chunk's bytes, staged up front (many loads in flight) so that the
-    // replay never waits on global memory
-    for (uint32_t base = 0; base < m; base += 64 * 16) {
-      uint8_t v[16];
+  // the chunk's bytes, lane l holding positions l, l + 64, ... (all loads in
+  // flight at once, so that the replay never waits on global memory)
+  uint32_t sy[kChunk / 64];
 #pragma unroll
-      for (uint32_t k = 0; k < 16; k++) {
-        const uint32_t i = base + k * 64 + lane;
-        v[k] = i < m ? L[p0 + i] : (uint8_t)0;
-      }
-#pragma unroll
-      for (uint32_t k = 0; k < 16; k++) {
-        const uint32_t i = base + k * 64 + lane;
-        if (i < m) ssym[i] = v[k];
-      }
-    }
+  for (uint32_t k = 0; k < kChunk / 64; k++) {
+    const uint32_t i = k * 64 + lane;
+    sy[k] = i < m ? (uint32_t)L[p0 + i] : 0x200u;
   }
-  __syncthreads();
-  for (uint32_t i = lane; i < m; i += 64) ssym[i] = smap[ssym[i]];
-  __syncthreads();
-  if (!have) return;
-  uint32_t R0 = (uint32_t)rk[lane] | ((uint32_t)rk[lane + 64] << 16);
-  uint32_t R1 = (uint32_t)rk[lane + 128] | ((uint32_t)rk[lane + 192] << 16);
+  const uint8_t *il = inlist + (size_t)c * 256;
+  uint32_t Q0 = il[lane], Q1 = il[lane + 64], Q2 = il[lane + 128], Q3 = il[lane + 192];
   // A symbol equal to the one before it has index 0 and leaves the list as
   // it is (about half the positions of a typical block): only the other
   // positions are replayed.  The chunk's first position is always replayed.
   uint32_t before = 0xFFFFFFFFu;  // symbol at the position before this batch
-  for (uint32_t base = p0; base < p1; base += 64) {
-    const uint32_t p = base + lane;
-    const bool in = p < p1;
-    const uint32_t vl = in ? (uint32_t)ssym[p - p0] : 0u;
-    uint32_t pv = (uint32_t)__shfl_up((int)vl, 1);
-    if (lane == 0) pv = before;
+#pragma unroll
+  for (uint32_t k = 0; k < kChunk / 64; k++) {
+    if (k * 64 >= m) break;
+    const uint32_t vl = sy[k];
+    const bool in = k * 64 + lane < m;
+    const uint32_t pv = wave_shr1(vl, before);
     uint64_t todo = ballot64(in && vl != pv);
     before = (uint32_t)__builtin_amdgcn_readlane((int)vl, 63);
     uint32_t mine = 0;
-    while (todo) {
-      const uint32_t k = (uint32_t)__builtin_ctzll(todo);
-      todo &= todo - 1;
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)vl, (int)k);  // wave-uniform
-      const uint32_t sl = v & 63u;
-      const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)R0, (int)sl);
-      const uint32_t a1 = (uint32_t)__builtin_amdgcn_readlane((int)R1, (int)sl);
-      const uint32_t word = (v & 128u) ? a1 : a0;
-      // the move-to-front index in the low 16 bits (the high bits are never read:
-      // the rank update takes the low half, the index is stored as a byte)
-      const uint32_t r = (v & 64u) ? (word >> 16) : word;
-      R0 = mtf_ranks(R0, r);
-      R1 = mtf_ranks(R1, r);
-      // lane k keeps its index (one SGPR operand per instruction: the lane goes through m0)
-      asm("s_mov_b32 m0, %2\n\tv_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(r), "s"(k) : "m0");
-    }
-    if (in) idx[p] = (uint8_t)mine;
+    mtf_batch(Q0, Q1, Q2, Q3, mine, todo, vl);
+    if (in) idx[p0 + k * 64 + lane] = (uint8_t)mine;
   }
 }
 
@@ -358,9 +466,10 @@ __global__ __launch_bounds__(64 * kRunWaves) void k_mtf_run(const uint8_t *L, co
 // count is 1 for a nonzero index, the number of bijective base-2 digits of
 // the run at the run's last zero, 0 elsewhere inside a run, plus 1 for the
 // end-of-block symbol at the block's last position.  Three launches over
-// tiles of 4096 positions (per-tile maxima of the segment-start marks;
+// tiles of 4096 positions: per-tile maxima of the segment-start marks;
 // max-scan of the marks (zs) with per-tile symbol counts; exclusive scan of
-// the counts), then the symbol output, one workgroup per chunk.
+// the counts, which places the tile's symbols (staged in LDS, then written
+// out in one coalesced run) and counts their frequencies per block.
 
 __device__ __forceinline__ uint32_t ndigits(uint32_t r) { return 31u - __clz(r + 1u); }
 
@@ -490,13 +599,27 @@ __global__ __launch_bounds__(kTThreads) void k_z_runs(const uint8_t *idx, const 
   }
 }
 
-// Exclusive scan of the symbol counts: off[p] = first symbol of position p;
-// the total goes to *d_n_sym.
-__global__ __launch_bounds__(kTThreads) void k_z_offs(const uint8_t *idx, const uint32_t *zs, const uint32_t *d_N,
-                                                      const uint32_t *blk_start, const uint32_t *d_nb,
-                                                      const uint32_t *aggs_l, uint32_t *off, uint32_t *d_n_sym) {
+// Exclusive scan of the symbol counts gives each position its first symbol;
+// the symbols go out here.  A tile holds at most kTTile positions' symbols,
+// plus the digits of a run that began in an earlier tile (< 32) and one
+// end-of-block symbol per block that ends in it (<= kTTile).
+constexpr uint32_t kZStage = 2 * kTTile + 64;
+
+__device__ __forceinline__ void zcount(uint32_t *f, uint32_t *freq, uint32_t b, uint32_t b0, uint32_t s) {
+  if (b == b0)
+    atomicAdd(&f[s], 1u);
+  else
+    atomicAdd(&freq[b * kMaxAlpha + s], 1u);  // a block that starts inside the tile (rare)
+}
+
+__global__ __launch_bounds__(kTThreads) void k_z_write(const uint8_t *idx, const uint32_t *zs, const uint32_t *d_N,
+                                                       const uint32_t *blk_start, const uint32_t *d_nb,
+                                                       const uint32_t *aggs_l, BlockCode *codes, uint16_t *sym,
+                                                       uint32_t *freq, uint32_t *d_n_sym) {
   __shared__ uint32_t buf[kTPad];
   __shared__ uint32_t sh[kTThreads / kWave];
+  __shared__ uint32_t f[kMaxAlpha];
+  __shared__ uint16_t stage[kZStage];
   const uint32_t N = *d_N, nb = *d_nb;
   const uint32_t nt = (N + kTTile - 1) / kTTile;
   if (blockIdx.x == 0 && threadIdx.x == 0 && nt == 0) *d_n_sym = 0;
@@ -504,6 +627,7 @@ __global__ __launch_bounds__(kTThreads) void k_z_offs(const uint8_t *idx, const 
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const uint32_t base = tile * kTTile;
     const uint32_t p0 = base + threadIdx.x * kTItems;
+    for (uint32_t i = threadIdx.x; i < kMaxAlpha; i += kTThreads) f[i] = 0;  // ordered by the reduction's barriers
     const ZBytes z = load_zbytes(idx, p0, N);  // issued before the carry's loads
     const TileBlocks tb(blk_start, nb, base);
     uint32_t zv[kTItems];
@@ -534,64 +658,48 @@ __global__ __launch_bounds__(kTThreads) void k_z_offs(const uint8_t *idx, const 
       buf[tpad(threadIdx.x * kTItems + i)] = l;
     }
     __syncthreads();
-    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
+    const uint32_t total = tile_scan<false, false>(buf, 0, sh);  // offsets inside the tile
 #pragma unroll
-    for (int i = 0; i < kTItems; i++) zv[i] = buf[tpad(threadIdx.x * kTItems + i)];
-    if (p0 + kTItems <= N) {
-      uint4 *o = (uint4 *)(off + p0);
-#pragma unroll
-      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(zv[4 * q], zv[4 * q + 1], zv[4 * q + 2], zv[4 * q + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < kTItems; i++)
-        if (p0 + i < N) off[p0 + i] = zv[i];
+    for (int i = 0; i < kTItems; i++) {
+      const uint32_t p = p0 + i;
+      if (p >= N) break;
+      uint32_t bs, be;
+      const uint32_t b = tb.find(p, bs, be);
+      uint32_t o = buf[tpad(threadIdx.x * kTItems + i)];
+      if (p == bs) codes[b].sym_start = carry + o;
+      const uint32_t v = z.v[i];
+      const uint32_t next = i == kTItems - 1 ? z.after : z.v[i + 1];
+      if (v != 0) {
+        stage[o++] = (uint16_t)(v + 1);
+        zcount(f, freq, b, tb.b0, v + 1);
+      } else if (p + 1 == be || next != 0) {
+        uint32_t r = p - zv[i] + 1;
+        while (r > 0) {
+          const uint32_t d = (r & 1u) ? 0u : 1u;
+          stage[o++] = (uint16_t)d;
+          zcount(f, freq, b, tb.b0, d);
+          r = (r - 1u - d) >> 1;
+        }
+      }
+      if (p + 1 == be) {
+        const uint32_t eob = codes[b].n_in_use + 1;
+        stage[o] = (uint16_t)eob;
+        zcount(f, freq, b, tb.b0, eob);
+      }
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < total; i += kTThreads) sym[carry + i] = stage[i];
+    for (uint32_t i = threadIdx.x; i < kMaxAlpha; i += kTThreads)
+      if (f[i]) atomicAdd(&freq[tb.b0 * kMaxAlpha + i], f[i]);
     if (tile == nt - 1 && threadIdx.x == 0) *d_n_sym = carry + total;
     __syncthreads();
   }
 }
 
-// Symbol output, one workgroup per chunk: a nonzero index v becomes v + 1, a
-// zero run of length r its bijective digits (RUNA = 0, RUNB = 1, least
-// significant first), each block ends with n_in_use + 1; per-block symbol
-// frequencies, first symbol and count.
-__global__ __launch_bounds__(256) void k_rle2_write(const uint8_t *idx, const uint32_t *zs, const uint32_t *off,
-                                                    const uint32_t *chunk_base, const uint32_t *d_n_chunks,
-                                                    const uint32_t *blk_start, const uint32_t *d_nb,
-                                                    BlockCode *codes, uint16_t *sym, uint32_t *freq) {
-  __shared__ uint32_t f[kMaxAlpha];
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
-  uint32_t b, p0, p1, bs, be;
-  chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  for (int i = threadIdx.x; i < kMaxAlpha; i += 256) f[i] = 0;
-  __syncthreads();
-  const uint32_t nu = codes[b].n_in_use;
-  for (uint32_t p = p0 + threadIdx.x; p < p1; p += 256) {
-    uint32_t o = off[p];
-    const uint32_t v = idx[p];
-    if (v != 0) {
-      sym[o++] = (uint16_t)(v + 1);
-      atomicAdd(&f[v + 1], 1u);
-    } else if (p + 1 == be || idx[p + 1] != 0) {
-      uint32_t r = p - zs[p] + 1;
-      while (r > 0) {
-        const uint32_t d = (r & 1u) ? 0u : 1u;
-        sym[o++] = (uint16_t)d;
-        atomicAdd(&f[d], 1u);
-        r = (r - 1u - d) >> 1;
-      }
-    }
-    if (p + 1 == be) {
-      sym[o] = (uint16_t)(nu + 1);
-      atomicAdd(&f[nu + 1], 1u);
-      codes[b].sym_start = off[bs];
-      codes[b].n_mtf = o + 1 - off[bs];
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kMaxAlpha; i += 256)
-    if (f[i]) atomicAdd(&freq[b * kMaxAlpha + i], f[i]);
+// symbols per block, from the block starts and the total
+__global__ void k_mtf_ends(const uint32_t *d_nb, const uint32_t *d_n_sym, BlockCode *codes) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x, nb = *d_nb;
+  if (b < nb) codes[b].n_mtf = (b + 1 < nb ? codes[b + 1].sym_start : *d_n_sym) - codes[b].sym_start;
 }
 
 }  // namespace
@@ -601,25 +709,21 @@ void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32
                  uint32_t *d_n_sym, hipStream_t s) {
   PCBZ_LAUNCH(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
   const uint32_t *cb = w.chunk_block;
-  PCBZ_LAUNCH(k_used, dim3(max_chunks), dim3(256), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.used_chunk);
-  PCBZ_LAUNCH(k_seq, dim3(max_blocks), dim3(256), 0, s, w.used_chunk, w.used, d_nb, w.seq, codes);
-  PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.seq,
-                     w.plist, w.plen);
-  PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
+  PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.plist, w.plen);
+  PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
               w.seglen);
-  PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(256), 0, s, d_nb, w.seglist, w.seglen);
-  PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(256), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
+  PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(64), 0, s, d_nb, w.seglist, w.seglen, w.used, codes);
+  PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
               w.inlist);
   PCBZ_LAUNCH(k_mtf_run, dim3((max_chunks + kRunWaves - 1) / kRunWaves), dim3(64 * kRunWaves), 0, s, L, cb,
-              w.d_n_chunks, blk_start, d_nb, w.seq,
-                     w.inlist, w.idx);
+              w.d_n_chunks, blk_start, d_nb, w.inlist, w.idx);
   const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (N + kTTile - 1) / kTTile));
   uint32_t *aggs_m = w.aggs, *aggs_l = w.aggs + (N / kTTile + 2);
   PCBZ_LAUNCH(k_z_marks, dim3(gt), dim3(kTThreads), 0, s, w.idx, d_N, blk_start, d_nb, aggs_m);
   PCBZ_LAUNCH(k_z_runs, dim3(gt), dim3(kTThreads), 0, s, w.idx, d_N, blk_start, d_nb, aggs_m, w.zs, aggs_l);
-  PCBZ_LAUNCH(k_z_offs, dim3(gt), dim3(kTThreads), 0, s, w.idx, w.zs, d_N, blk_start, d_nb, aggs_l, w.off, d_n_sym);
-  PCBZ_LAUNCH(k_rle2_write, dim3(max_chunks), dim3(256), 0, s, w.idx, w.zs, w.off, cb, w.d_n_chunks, blk_start, d_nb,
-              codes, sym, freq);
+  PCBZ_LAUNCH(k_z_write, dim3(gt), dim3(kTThreads), 0, s, w.idx, w.zs, d_N, blk_start, d_nb, aggs_l, codes, sym, freq,
+              d_n_sym);
+  PCBZ_LAUNCH(k_mtf_ends, dim3((max_blocks + 255) / 256), dim3(256), 0, s, d_nb, d_n_sym, codes);
 }
 
 }  // namespace pcbz

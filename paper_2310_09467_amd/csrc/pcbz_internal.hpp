@@ -377,12 +377,13 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
             int items, uint32_t *pinned_u, uint64_t *seg_mask, uint32_t *d_left, hipStream_t s);
 
 // mtf.hip
-constexpr uint32_t kMtfSegs = 32;    // segments per block in the move-to-front list chain
-constexpr uint32_t kMtfChunk = 1024;  // positions per move-to-front chunk (one wavefront replays one)
+constexpr uint32_t kMtfSegs = 64;    // segments per block in the move-to-front list chain
+constexpr uint32_t kMtfChunk = 256;  // positions per move-to-front chunk (one wavefront replays one)
+constexpr uint32_t kMtfMaxBlock = 899981;  // longest first-stage block (level 9)
+// chunks per segment of the longest block
+constexpr uint32_t kMtfUnits = ((kMtfMaxBlock + kMtfChunk - 1) / kMtfChunk + kMtfSegs - 1) / kMtfSegs;
 struct MtfWork {
-  uint8_t *seq;          // [max_blocks * 256] byte -> rank among used bytes
   uint32_t *used;        // [max_blocks * 8] used-byte bitmaps
-  uint32_t *used_chunk;  // [max_chunks * 8] used-byte bitmaps of the chunks
   uint32_t *chunk_block; // [max_chunks + 1] first chunk of each block
   uint8_t *plist;        // [max_chunks * 256] chunk partial lists
   uint32_t *plen;        // [max_chunks]
@@ -391,7 +392,6 @@ struct MtfWork {
   uint32_t *seglen;      // [max_blocks * kMtfSegs]
   uint8_t *idx;          // [N] MTF indices
   uint32_t *zs;          // [N] zero-run segment start of each position
-  uint32_t *off;         // [N] first output symbol of each position
   uint32_t *aggs;        // [2 * (N / kTTile + 2)] tile aggregates of the zero-run scans
   uint32_t *d_n_chunks;
 };
