@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *keys, co
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_count_n = 256u * nt;
   const int w = threadIdx.x / kWave;
   const RsLanes RL = rs_lanes(sg);
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     const RsTile T = rs_tile(sg, RL, n, nt, TILE, tile);
     const uint32_t te = T.base + T.tn;
     for (int i = threadIdx.x; i < (kRsThreads / kWave) * 256; i += kRsThreads) (&h[0][0])[i] = 0;
@@ -281,7 +282,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *keys_
   }
   const uint32_t dend = dbase + totals[d0];
   const RsLanes RL = rs_lanes(sg);
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     const RsTile T = rs_tile(sg, RL, n, nt, TILE, tile);
     const uint64_t base = T.base;
     const uint32_t tn = T.tn;
@@ -536,7 +538,8 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
   const uint32_t nt = (U + kRTile - 1) / kRTile;
   const int lane = lane_id();
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     const uint32_t k0 = tile * kRTile + threadIdx.x * kRItems;
     uint64_t key[kRItems];
     uint32_t sl[kRItems];
@@ -581,7 +584,8 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
   const int lane = lane_id();
   uint32_t carry = 0, counted = 0, gmax = 0;
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     const uint32_t base = tile * kRTile;
     const uint32_t k0 = base + threadIdx.x * kRItems;
     uint32_t sl[kRItems], g[kRItems], diff = 0;  // diff bit i: key i differs from key i - 1
@@ -660,7 +664,8 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals,
     if (nt == 0) *d_unew = 0;
   }
   uint32_t carry = 0, counted = 0;
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     carry = tile_carry<false>(aggs_s, counted, tile, carry, sh);
     const uint32_t base = tile * kRTile;
     uint32_t w[kRItems];
@@ -758,10 +763,11 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ uint64_t scomp[kSegCap];  // composites, in runs sorted so far
   __shared__ uint16_t sgs[kSegCap];    // group starts, then group ends at each start
   const uint32_t U = *d_u, nb = *d_nb;
-  const uint64_t t0 = (uint64_t)blockIdx.x * kSegTile;
+  const uint32_t tile = xcd_tile();
+  const uint64_t t0 = (uint64_t)tile * kSegTile;
   if (t0 >= U) return;
-  const uint32_t R0 = min(bound[blockIdx.x], U);
-  const uint32_t R1 = t0 + kSegTile >= U ? U : min(bound[blockIdx.x + 1], U);
+  const uint32_t R0 = min(bound[tile], U);
+  const uint32_t R1 = t0 + kSegTile >= U ? U : min(bound[tile + 1], U);
   if (R1 <= R0) return;  // a group from an earlier tile covers this one
   const uint32_t len = R1 - R0;
   if (len > kSegCap) {
@@ -934,7 +940,8 @@ __global__ __launch_bounds__(kTThreads) void k_bwt_emit(const uint32_t *sa, cons
                                                         BlockCode *codes) {
   const uint32_t N = *d_N, nb = *d_nb;
   const uint32_t nt = (N + kTTile - 1) / kTTile;
-  for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    const uint32_t tile = wk.t;
     const TileBlocks tb(blk_start, nb, tile * kTTile);
     const uint32_t j0 = tile * kTTile + threadIdx.x * kTItems;
     uint32_t g[kTItems], src[kTItems];
@@ -1108,7 +1115,7 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     const bool seg = pinned_u ? maxg <= kSegMaxGroup : rounds <= 64 && ((mask_in >> (rounds - 1)) & 1ull);
     if (seg) {
       if (rounds <= 64) mask_out |= 1ull << (rounds - 1);
-      const uint32_t gs = (uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile);
+      const uint32_t gs = xcd_grid((uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile));
       PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.gstart, w.rank, du[u], w.seg_bound,
                   blk_start, d_nb, compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
       cur ^= 1;

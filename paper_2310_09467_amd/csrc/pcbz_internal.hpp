@@ -187,6 +187,39 @@ __device__ __forceinline__ uint32_t tile_carry(const uint32_t *aggs, uint32_t &c
   return top<kMax>(carry, block_reduce<kMax>(part, sh));
 }
 
+// XCD-aware tile walk.  The dispatcher deals the workgroups of a launch to
+// the eight XCDs round robin (workgroup i to XCD i mod 8), and each XCD has
+// its own L2.  Workgroup i takes the tiles of the (i mod 8)-th eighth of
+// [0, nt), so neighbouring tiles (consecutive list elements, mostly one
+// block's, whose scattered accesses stay inside that block's part of an
+// array) share one L2.  A workgroup's tiles come in increasing order, every
+// tile is taken once; with fewer than eight workgroups it is a plain stride.
+constexpr uint32_t kXcds = 8;
+struct XcdWalk {
+  uint32_t t, end, step;
+  __device__ __forceinline__ explicit XcdWalk(uint32_t nt) {
+    const uint32_t per = gridDim.x / kXcds;  // workgroups per XCD (the grid's remainder idles)
+    if (per == 0) {
+      t = blockIdx.x;
+      end = nt;
+      step = gridDim.x;
+      return;
+    }
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    t = (uint32_t)((uint64_t)nt * x / kXcds) + j;
+    end = j < per ? (uint32_t)((uint64_t)nt * (x + 1) / kXcds) : 0u;
+    step = per;
+  }
+};
+// One tile per workgroup, the same placement: the grid is kXcds * per
+// workgroups (per = ceil(tiles / 8)) and workgroup i takes tile
+// (i mod 8) * per + i / 8 (tiles past the real count return at once).
+__device__ __forceinline__ uint32_t xcd_tile() {
+  const uint32_t per = gridDim.x / kXcds;
+  return per ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
+}
+inline uint32_t xcd_grid(uint32_t tiles) { return tiles < kXcds ? tiles : (tiles + kXcds - 1) / kXcds * kXcds; }
+
 // Binary search: largest i in [0, n) with a[i] <= key (a sorted ascending, a[0] <= key).
 template <typename T>
 __device__ __forceinline__ uint32_t upper_index(const T *a, uint32_t n, T key) {
