@@ -27,13 +27,28 @@ namespace {
 constexpr uint32_t kChunk = kMtfChunk;
 static_assert(kChunk % 64 == 0 && kChunk <= 1024, "a chunk is replayed from registers, 64 positions a batch");
 
+// block and positions of chunk c (wave-uniform).  With fewer than 64 blocks
+// lane l loads block l's first chunk and start (one round trip instead of a
+// chain of dependent loads) and a ballot finds the block.
 __device__ __forceinline__ void chunk_range(uint32_t c, const uint32_t *chunk_base, const uint32_t *blk_start,
                                             uint32_t nb, uint32_t &b, uint32_t &p0, uint32_t &p1, uint32_t &bs,
                                             uint32_t &be) {
-  b = upper_index(chunk_base, nb, c);
-  bs = blk_start[b];
-  be = blk_start[b + 1];
-  p0 = bs + (c - chunk_base[b]) * kChunk;
+  uint32_t cb;
+  if (nb < (uint32_t)kWave) {
+    const uint32_t lane = (uint32_t)lane_id();
+    const uint32_t mc = lane <= nb ? chunk_base[lane] : 0xFFFFFFFFu;
+    const uint32_t ms = lane <= nb ? blk_start[lane] : 0u;
+    b = (uint32_t)__popcll(ballot64(lane < nb && mc <= c)) - 1u;
+    cb = (uint32_t)__shfl((int)mc, (int)b);
+    bs = (uint32_t)__shfl((int)ms, (int)b);
+    be = (uint32_t)__shfl((int)ms, (int)b + 1);
+  } else {
+    b = upper_index(chunk_base, nb, c);
+    cb = chunk_base[b];
+    bs = blk_start[b];
+    be = blk_start[b + 1];
+  }
+  p0 = bs + (c - cb) * kChunk;
   p1 = min(be, p0 + kChunk);
 }
 
@@ -60,30 +75,33 @@ __global__ void k_mtf_chunks(const uint32_t *blk_start, const uint32_t *d_nb, ui
 // hold the last occurrence of their byte.  Lane l takes the kPer positions
 // p1 - 1 - kPer l down to p1 - kPer (l + 1); a wavefront prefix count of the
 // flagged positions gives each its place in the list.
-__global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint32_t *chunk_base,
-                                                    const uint32_t *d_n_chunks, const uint32_t *blk_start,
-                                                    const uint32_t *d_nb, uint8_t *plist, uint32_t *plen) {
-  __shared__ int lastpos[256];
-  const uint32_t c = blockIdx.x;
-  if (c >= *d_n_chunks) return;
+constexpr uint32_t kPartWaves = 4;  // chunks per workgroup, one per wavefront
+
+__global__ __launch_bounds__(64 * kPartWaves) void k_mtf_partial(const uint8_t *L, const uint32_t *chunk_base,
+                                                                const uint32_t *d_n_chunks, const uint32_t *blk_start,
+                                                                const uint32_t *d_nb, uint8_t *plist, uint32_t *plen) {
+  __shared__ int lastpos_all[kPartWaves][256];
+  const uint32_t c = blockIdx.x * kPartWaves + threadIdx.x / kWave;
+  if (c >= *d_n_chunks) return;  // the wavefronts of a workgroup are independent
+  int *lastpos = lastpos_all[threadIdx.x / kWave];
   uint32_t b, p0, p1, bs, be;
   chunk_range(c, chunk_base, blk_start, *d_nb, b, p0, p1, bs, be);
-  for (int v = threadIdx.x; v < 256; v += 64) lastpos[v] = -1;
-  __syncthreads();
   constexpr uint32_t kPer = kChunk / 64;
-  const uint32_t n = p1 - p0, lane = threadIdx.x;
+  const uint32_t n = p1 - p0, lane = (uint32_t)lane_id();
   uint8_t sy[kPer];
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
     const uint32_t q = lane * kPer + i;
     sy[i] = q < n ? L[p1 - 1 - q] : (uint8_t)0;
   }
+  for (uint32_t v = lane; v < 256; v += 64) lastpos[v] = -1;
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
     const uint32_t q = lane * kPer + i;
     if (q < n) atomicMax(&lastpos[sy[i]], (int)(n - 1 - q));
   }
-  __syncthreads();
+  __builtin_amdgcn_wave_barrier();
   uint32_t flags = 0;
 #pragma unroll
   for (uint32_t i = 0; i < kPer; i++) {
@@ -106,17 +124,20 @@ __global__ __launch_bounds__(64) void k_mtf_partial(const uint8_t *L, const uint
 
 // List chaining.  Folding a partial list P onto a list C gives P followed by
 // C without P's symbols (order kept); folding is associative, so a block's
-// chunks are chained in three shallow steps instead of one long one:
-//   1. each of kMtfSegs segments of the block folds its chunks' partial lists
-//      (from an empty list) into a segment partial list;
-//   2. one wavefront per block takes the block's used bytes from the segment
-//      lists, builds the initial list and folds the segment lists onto it,
-//      recording the list entering each segment;
-//   3. each segment folds its chunks again from its entering list, recording
-//      the list entering each chunk.
-// Every step is one wavefront with its lists staged in LDS up front; a list
-// of up to 256 bytes sits in four registers (lane l holds positions l,
-// l + 64, l + 128, l + 192) and a fold step needs no workgroup barrier.
+// chunks are chained in three steps:
+//   1. each of kMtfSegs segments of the block combines its chunks' partial
+//      lists into a segment partial list;
+//   2. one workgroup per block takes the block's used bytes from the segment
+//      lists, builds the initial list and computes the list entering each
+//      segment;
+//   3. each segment computes the list entering each of its chunks from the
+//      list entering the segment.
+// Each step is a workgroup of W wavefronts with its lists staged in LDS.  A list of up to 256 bytes sits in four registers of a wavefront (lane
+// l holds positions l, l + 64, l + 128, l + 192); one fold step needs no
+// workgroup barrier.  Inside a step the n lists are split into W groups:
+// each wavefront combines its group (n / W folds), a Hillis-Steele scan
+// combines the group lists (log2 W folds), and
+// each wavefront replays its group from the list entering it.
 
 // cur/len := P ++ (cur - P), P given as pv (lane l: positions l + 64 k) of
 // length pl.  mark[x] == stamp flags the bytes of P (stamps grow by one per
@@ -151,160 +172,211 @@ __device__ __forceinline__ void wave_fold(uint32_t (&cur)[4], uint32_t &len, con
   len = base;
 }
 
-// list i of the LDS-staged lists, lane l taking positions l + 64 k
-__device__ __forceinline__ void lds_list(uint32_t (&pv)[4], const uint8_t *lists, uint32_t i) {
-  const uint32_t lane = (uint32_t)lane_id();
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) pv[k] = lists[i * 256 + lane + 64 * k];
-}
-
-// folds the staged lists [0, n) onto cur (stamps 1..n); before fold i the
-// list is written to out + i * 256 when out is set.  The next list is read
-// while the current fold runs.
-__device__ __forceinline__ void fold_staged(uint32_t (&cur)[4], uint32_t &len, const uint8_t *lists,
-                                            const uint32_t *lens, uint32_t n, uint32_t *mark, uint8_t *buf,
-                                            uint8_t *out) {
-  const uint32_t lane = (uint32_t)lane_id();
-  if (n == 0) return;
-  uint32_t pv[4];
-  lds_list(pv, lists, 0);
-  for (uint32_t i = 0; i < n; i++) {
-    if (out) {
-#pragma unroll
-      for (uint32_t k = 0; k < 4; k++) out[(size_t)i * 256 + lane + 64 * k] = (uint8_t)cur[k];
-    }
-    uint32_t nx[4];
-    lds_list(nx, lists, min(i + 1, n - 1));
-    wave_fold(cur, len, pv, lens[i], i + 1, mark, buf);
-#pragma unroll
-    for (uint32_t k = 0; k < 4; k++) pv[k] = nx[k];
-  }
-}
-
 __device__ __forceinline__ void seg_range(const BlockCode &C, uint32_t j, uint32_t &u0, uint32_t &u1) {
   const uint32_t per = (C.n_chunks + kMtfSegs - 1) / kMtfSegs;
   u0 = min(C.n_chunks, j * per);
   u1 = min(C.n_chunks, u0 + per);
 }
 
-// the partial lists of chunks [c0, c0 + n) into LDS
-__device__ __forceinline__ void stage_lists(uint8_t *lists, uint32_t *lens, const uint8_t *plist,
-                                            const uint32_t *plen, uint32_t c0, uint32_t n) {
-  stage_to_lds((uint32_t *)lists, (const uint32_t *)(plist + (size_t)c0 * 256), n * 64);
-  stage_to_lds(lens, plen + c0, n);
-}
+// wavefronts per workgroup: the per-block step has one workgroup per block
+// and takes 16; the per-segment steps have one per segment (640 for ten
+// blocks) and take 8, so that all of them fit on the chip at once
+constexpr uint32_t kFoldMax = kMtfUnits > kMtfSegs ? kMtfUnits : kMtfSegs;  // lists a step holds
 
+template <uint32_t W>
 struct FoldLds {
-  uint8_t lists[kMtfUnits * 256];
-  uint32_t lens[kMtfUnits];
-  uint32_t mark[kFoldSlots];
-  uint8_t buf[kFoldSlots];
+  uint8_t lists[kFoldMax * 256];
+  uint32_t lens[kFoldMax];
+  uint8_t sl[2][W][256];  // scan buffers: group lists, then their prefixes
+  uint32_t slen[2][W];
+  uint8_t init[256];
+  uint32_t mark[W][kFoldSlots];
+  uint8_t buf[W][kFoldSlots];
 };
 
-// step 1: grid (kMtfSegs, blocks), one wavefront each
-__global__ __launch_bounds__(64) void k_mtf_seg_fold(const uint32_t *d_nb, const BlockCode *codes,
-                                                     const uint8_t *plist, const uint32_t *plen, uint8_t *seglist,
-                                                     uint32_t *seglen) {
-  __shared__ FoldLds F;
+// the n lists [c0, c0 + n) of (plist, plen) into LDS
+template <uint32_t W>
+__device__ __forceinline__ void stage_lists(FoldLds<W> &F, const uint8_t *plist, const uint32_t *plen, uint32_t c0,
+                                            uint32_t n) {
+  stage_to_lds((uint32_t *)F.lists, (const uint32_t *)(plist + (size_t)c0 * 256), n * 64);
+  stage_to_lds(F.lens, plen + c0, n);
+  for (uint32_t e = threadIdx.x; e < W * kFoldSlots; e += blockDim.x) (&F.mark[0][0])[e] = 0;
+}
+
+__device__ __forceinline__ void lds_get(uint32_t (&v)[4], const uint8_t *src) {
+  const uint32_t lane = (uint32_t)lane_id();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) v[k] = src[lane + 64 * k];
+}
+__device__ __forceinline__ void lds_put(uint8_t *dst, const uint32_t (&v)[4]) {
+  const uint32_t lane = (uint32_t)lane_id();
+#pragma unroll
+  for (uint32_t k = 0; k < 4; k++) dst[lane + 64 * k] = (uint8_t)v[k];
+}
+
+// Each wavefront's group of the staged lists: [g0, g1).
+template <uint32_t W>
+__device__ __forceinline__ void fold_group(uint32_t n, uint32_t w, uint32_t &g0, uint32_t &g1) {
+  const uint32_t g = (n + W - 1) / W;
+  g0 = min(n, w * g);
+  g1 = min(n, g0 + g);
+}
+
+// Phases 1 and 2: F.sl[r][w] / F.slen[r][w] (r returned) = lists [0, g1(w))
+// combined (the newest first).  Wavefront w folds with F.mark[w], F.buf[w]
+// and stamps from *stamp on.
+template <uint32_t W>
+__device__ uint32_t fold_scan(FoldLds<W> &F, uint32_t n, uint32_t &stamp) {
+  const uint32_t w = threadIdx.x / kWave;
+  uint32_t g0, g1;
+  fold_group<W>(n, w, g0, g1);
+  uint32_t cur[4] = {0, 0, 0, 0}, len = 0;
+  for (uint32_t i = g0; i < g1; i++) {
+    uint32_t pv[4];
+    lds_get(pv, F.lists + i * 256);
+    wave_fold(cur, len, pv, F.lens[i], ++stamp, F.mark[w], F.buf[w]);
+  }
+  lds_put(F.sl[0][w], cur);
+  if (lane_id() == 0) F.slen[0][w] = len;
+  uint32_t r = 0;
+  for (uint32_t d = 1; d < W; d <<= 1) {
+    __syncthreads();
+    if (w >= d) {
+      // the older lists combined, then this wavefront's (newer) on top
+      uint32_t pv[4];
+      lds_get(cur, F.sl[r][w - d]);
+      lds_get(pv, F.sl[r][w]);
+      len = F.slen[r][w - d];
+      wave_fold(cur, len, pv, F.slen[r][w], ++stamp, F.mark[w], F.buf[w]);
+    } else {
+      lds_get(cur, F.sl[r][w]);
+      len = F.slen[r][w];
+    }
+    lds_put(F.sl[r ^ 1][w], cur);
+    if (lane_id() == 0) F.slen[r ^ 1][w] = len;
+    r ^= 1;
+  }
+  __syncthreads();
+  return r;
+}
+
+// Phase 3: the list entering each staged list i < n, written to
+// out + i * 256, starting from the 256-entry list F.init.
+template <uint32_t W>
+__device__ void fold_replay(FoldLds<W> &F, uint32_t n, uint32_t r, uint32_t &stamp, uint8_t *out) {
+  const uint32_t w = threadIdx.x / kWave;
+  uint32_t g0, g1;
+  fold_group<W>(n, w, g0, g1);
+  if (g0 >= g1) return;
+  uint32_t cur[4], len = 256;
+  lds_get(cur, F.init);
+  if (w > 0) {  // the groups before this one, combined, on top of the initial list
+    uint32_t pv[4];
+    lds_get(pv, F.sl[r][w - 1]);
+    wave_fold(cur, len, pv, F.slen[r][w - 1], ++stamp, F.mark[w], F.buf[w]);
+  }
+  for (uint32_t i = g0; i < g1; i++) {
+    lds_put(out + (size_t)i * 256, cur);  // global
+    if (i + 1 < g1) {
+      uint32_t pv[4];
+      lds_get(pv, F.lists + i * 256);
+      wave_fold(cur, len, pv, F.lens[i], ++stamp, F.mark[w], F.buf[w]);
+    }
+  }
+}
+
+constexpr uint32_t kSegWaves = 8, kBlkWaves = 16;
+
+// step 1: grid (kMtfSegs, blocks)
+__global__ __launch_bounds__(64 * kSegWaves) void k_mtf_seg_fold(const uint32_t *d_nb, const BlockCode *codes,
+                                                                const uint8_t *plist, const uint32_t *plen,
+                                                                uint8_t *seglist, uint32_t *seglen) {
+  __shared__ FoldLds<kSegWaves> F;
   const uint32_t b = blockIdx.y, j = blockIdx.x;
   if (b >= *d_nb) return;
   const BlockCode C = codes[b];
   uint32_t u0, u1;
   seg_range(C, j, u0, u1);
-  const uint32_t n = u1 - u0, lane = (uint32_t)lane_id();
-  stage_lists(F.lists, F.lens, plist, plen, C.chunk_start + u0, n);
-  for (uint32_t e = lane; e < kFoldSlots; e += 64) F.mark[e] = 0;
+  const uint32_t n = u1 - u0;
+  stage_lists(F, plist, plen, C.chunk_start + u0, n);
   __syncthreads();
-  uint32_t cur[4] = {0, 0, 0, 0}, len = 0;
-  fold_staged(cur, len, F.lists, F.lens, n, F.mark, F.buf, nullptr);
-  uint8_t *o = seglist + ((size_t)b * kMtfSegs + j) * 256;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) o[lane + 64 * k] = (uint8_t)cur[k];
-  if (lane == 0) seglen[(size_t)b * kMtfSegs + j] = len;
+  uint32_t stamp = 0;
+  const uint32_t r = fold_scan(F, n, stamp);
+  // the last wavefront's prefix is the whole segment
+  const uint32_t t = threadIdx.x;
+  if (t < 256) seglist[((size_t)b * kMtfSegs + j) * 256 + t] = F.sl[r][kSegWaves - 1][t];
+  if (t == 0) seglen[(size_t)b * kMtfSegs + j] = F.slen[r][kSegWaves - 1];
 }
 
-// step 2: one wavefront per block; also writes the block's used-byte bitmap
+// step 2: one workgroup per block; also writes the block's used-byte bitmap
 // and symbol-map size.  The segment lists are replaced by the lists entering
 // the segments.
-__global__ __launch_bounds__(64) void k_mtf_seg_chain(const uint32_t *d_nb, uint8_t *seglist, const uint32_t *seglen,
-                                                      uint32_t *used, BlockCode *codes) {
-  __shared__ uint8_t lists[kMtfSegs * 256];
-  __shared__ uint32_t lens[kMtfSegs];
-  __shared__ uint32_t mark[kFoldSlots];
-  __shared__ uint8_t buf[kFoldSlots];
+__global__ __launch_bounds__(64 * kBlkWaves) void k_mtf_seg_chain(const uint32_t *d_nb, uint8_t *seglist,
+                                                                 const uint32_t *seglen, uint32_t *used,
+                                                                 BlockCode *codes) {
+  __shared__ FoldLds<kBlkWaves> F;
+  __shared__ uint32_t seen[256];
   const uint32_t b = blockIdx.x;
   if (b >= *d_nb) return;
-  const uint32_t lane = (uint32_t)lane_id();
+  const uint32_t t = threadIdx.x, lane = (uint32_t)lane_id();
   uint8_t *sl = seglist + (size_t)b * kMtfSegs * 256;
-  stage_lists(lists, lens, sl, seglen + (size_t)b * kMtfSegs, 0, kMtfSegs);
-  for (uint32_t e = lane; e < kFoldSlots; e += 64) mark[e] = 0;
+  stage_lists(F, sl, seglen + (size_t)b * kMtfSegs, 0, kMtfSegs);
+  if (t < 256) seen[t] = 0;
   __syncthreads();
   // the block's used bytes: every byte of a segment list
-  for (uint32_t i = 0; i < kMtfSegs; i++) {
-    const uint32_t l = lens[i];
-    for (uint32_t e = lane; e < l; e += 64) mark[lists[i * 256 + e]] = 1;
+  for (uint32_t e = t; e < kMtfSegs * 256; e += blockDim.x)
+    if ((e & 255u) < F.lens[e >> 8]) seen[F.lists[e]] = 1;
+  __syncthreads();
+  if (t < kWave) {
+    uint64_t ub[4];
+    uint32_t nu = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) {
+      ub[k] = ballot64(seen[lane + 64 * k] != 0);
+      nu += (uint32_t)__popcll(ub[k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (uint32_t q = 0; q < 8; q++) used[b * 8 + q] = (uint32_t)(ub[q / 2] >> (32 * (q % 2)));
+      codes[b].n_in_use = nu;
+      codes[b].alpha = nu + 2;
+    }
+    // initial list: used bytes ascending, then the unused ones
+    const uint64_t lt = lanemask_lt();
+    uint32_t nbu = 0, nbn = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; k++) {
+      const bool u = (ub[k] >> lane) & 1ull;
+      const uint32_t pos = u ? nbu + (uint32_t)__popcll(ub[k] & lt) : nu + nbn + (uint32_t)__popcll(~ub[k] & lt);
+      F.init[pos] = (uint8_t)(lane + 64 * k);
+      nbu += (uint32_t)__popcll(ub[k]);
+      nbn += 64u - (uint32_t)__popcll(ub[k]);
+    }
   }
   __syncthreads();
-  uint64_t ub[4];
-  uint32_t nu = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) {
-    ub[k] = ballot64(mark[lane + 64 * k] != 0);
-    nu += (uint32_t)__popcll(ub[k]);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (uint32_t w = 0; w < 8; w++) used[b * 8 + w] = (uint32_t)(ub[w / 2] >> (32 * (w % 2)));
-    codes[b].n_in_use = nu;
-    codes[b].alpha = nu + 2;
-  }
-  // initial list: used bytes ascending, then the unused ones
-  const uint64_t lt = lanemask_lt();
-  uint32_t nbu = 0, nbn = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) {
-    const bool u = (ub[k] >> lane) & 1ull;
-    const uint32_t pos = u ? nbu + (uint32_t)__popcll(ub[k] & lt) : nu + nbn + (uint32_t)__popcll(~ub[k] & lt);
-    buf[pos] = (uint8_t)(lane + 64 * k);
-    nbu += (uint32_t)__popcll(ub[k]);
-    nbn += 64u - (uint32_t)__popcll(ub[k]);
-  }
-  __syncthreads();
-  uint32_t cur[4], len = 256;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) {
-    cur[k] = buf[lane + 64 * k];
-    mark[lane + 64 * k] = 0;
-  }
-  __syncthreads();
-  // the last segment's fold is not needed (its result is the block's end)
-  fold_staged(cur, len, lists, lens, kMtfSegs - 1, mark, buf, sl);
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) sl[(kMtfSegs - 1) * 256 + lane + 64 * k] = (uint8_t)cur[k];
+  uint32_t stamp = 0;
+  const uint32_t r = fold_scan(F, kMtfSegs, stamp);
+  fold_replay(F, kMtfSegs, r, stamp, sl);
 }
 
-// step 3: grid (kMtfSegs, blocks), one wavefront each
-__global__ __launch_bounds__(64) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes, const uint8_t *plist,
-                                                  const uint32_t *plen, const uint8_t *seglist, uint8_t *inlist) {
-  __shared__ FoldLds F;
+// step 3: grid (kMtfSegs, blocks)
+__global__ __launch_bounds__(64 * kSegWaves) void k_mtf_chain(const uint32_t *d_nb, const BlockCode *codes,
+                                                             const uint8_t *plist, const uint32_t *plen,
+                                                             const uint8_t *seglist, uint8_t *inlist) {
+  __shared__ FoldLds<kSegWaves> F;
   const uint32_t b = blockIdx.y, j = blockIdx.x;
   if (b >= *d_nb) return;
   const BlockCode C = codes[b];
   uint32_t u0, u1;
   seg_range(C, j, u0, u1);
   if (u0 >= u1) return;
-  const uint32_t n = u1 - u0, lane = (uint32_t)lane_id();
-  stage_lists(F.lists, F.lens, plist, plen, C.chunk_start + u0, n);
-  const uint8_t *si = seglist + ((size_t)b * kMtfSegs + j) * 256;
-  uint32_t cur[4], len = 256;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) cur[k] = si[lane + 64 * k];
-  for (uint32_t e = lane; e < kFoldSlots; e += 64) F.mark[e] = 0;
+  const uint32_t n = u1 - u0;
+  stage_lists(F, plist, plen, C.chunk_start + u0, n);
+  if (threadIdx.x < 256) F.init[threadIdx.x] = seglist[((size_t)b * kMtfSegs + j) * 256 + threadIdx.x];
   __syncthreads();
-  uint8_t *o = inlist + (size_t)(C.chunk_start + u0) * 256;
-  fold_staged(cur, len, F.lists, F.lens, n - 1, F.mark, F.buf, o);
-#pragma unroll
-  for (uint32_t k = 0; k < 4; k++) o[(size_t)(n - 1) * 256 + lane + 64 * k] = (uint8_t)cur[k];
+  uint32_t stamp = 0;
+  const uint32_t r = fold_scan(F, n, stamp);
+  fold_replay(F, n, r, stamp, inlist + (size_t)(C.chunk_start + u0) * 256);
 }
 
 // Replay of one chunk by one wavefront.  The list itself is held in four
@@ -709,12 +781,13 @@ void launch_mtf2(const uint8_t *L, const uint32_t *d_N, uint32_t N, const uint32
                  uint32_t *d_n_sym, hipStream_t s) {
   PCBZ_LAUNCH(k_mtf_chunks, dim3(1), dim3(64), 0, s, blk_start, d_nb, w.chunk_block, w.d_n_chunks, codes);
   const uint32_t *cb = w.chunk_block;
-  PCBZ_LAUNCH(k_mtf_partial, dim3(max_chunks), dim3(64), 0, s, L, cb, w.d_n_chunks, blk_start, d_nb, w.plist, w.plen);
-  PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
-              w.seglen);
-  PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(64), 0, s, d_nb, w.seglist, w.seglen, w.used, codes);
-  PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(64), 0, s, d_nb, codes, w.plist, w.plen, w.seglist,
-              w.inlist);
+  PCBZ_LAUNCH(k_mtf_partial, dim3((max_chunks + kPartWaves - 1) / kPartWaves), dim3(64 * kPartWaves), 0, s, L, cb,
+              w.d_n_chunks, blk_start, d_nb, w.plist, w.plen);
+  PCBZ_LAUNCH(k_mtf_seg_fold, dim3(kMtfSegs, max_blocks), dim3(64 * kSegWaves), 0, s, d_nb, codes, w.plist, w.plen,
+              w.seglist, w.seglen);
+  PCBZ_LAUNCH(k_mtf_seg_chain, dim3(max_blocks), dim3(64 * kBlkWaves), 0, s, d_nb, w.seglist, w.seglen, w.used, codes);
+  PCBZ_LAUNCH(k_mtf_chain, dim3(kMtfSegs, max_blocks), dim3(64 * kSegWaves), 0, s, d_nb, codes, w.plist, w.plen,
+              w.seglist, w.inlist);
   PCBZ_LAUNCH(k_mtf_run, dim3((max_chunks + kRunWaves - 1) / kRunWaves), dim3(64 * kRunWaves), 0, s, L, cb,
               w.d_n_chunks, blk_start, d_nb, w.inlist, w.idx);
   const uint32_t gt = std::max<uint32_t>(1, std::min<uint32_t>(2048, (N + kTTile - 1) / kTTile));
