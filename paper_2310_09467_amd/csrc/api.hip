@@ -39,6 +39,15 @@ struct Tracer {
   std::vector<double> ms;
   std::vector<uint64_t> calls;
   std::vector<uint64_t> bytes;
+  struct Pending {
+    size_t slot;
+    uint64_t per_elem;
+  };
+  // byte counts waiting for their element counts, which a one-thread kernel
+  // copied at launch time into snap[i] (device)
+  std::vector<Pending> pending;
+  uint32_t *snap = nullptr;
+  static constexpr size_t kSnap = 4096;
   size_t slot(const std::string &name) {
     size_t i = 0;
     while (i < names.size() && names[i] != name) i++;
@@ -88,6 +97,28 @@ void trace_begin_impl(const char *name, hipStream_t s) {
 void trace_bytes_impl(const char *name, uint64_t bytes) {
   if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
   g_tracer.bytes[g_tracer.slot(trace_key(g_trace_stage, name))] += bytes;
+}
+
+__global__ void k_trace_snap(const uint32_t *d_count, uint32_t *snap) { *snap = *d_count; }
+
+void trace_bytes_count_impl(const char *name, uint64_t per_elem, const uint32_t *d_count, hipStream_t s) {
+  if (!g_tracer.filter.empty() && g_tracer.filter != name) return;
+  if (!g_tracer.snap && hipMalloc((void **)&g_tracer.snap, Tracer::kSnap * sizeof(uint32_t)) != hipSuccess) {
+    g_tracer.snap = nullptr;
+    return;
+  }
+  if (g_tracer.pending.size() >= Tracer::kSnap) return;
+  hipLaunchKernelGGL(k_trace_snap, dim3(1), dim3(1), 0, s, d_count, g_tracer.snap + g_tracer.pending.size());
+  g_tracer.pending.push_back({g_tracer.slot(trace_key(g_trace_stage, name)), per_elem});
+}
+
+void trace_settle_impl(hipStream_t s) {
+  if (g_tracer.pending.empty()) return;
+  std::vector<uint32_t> n(g_tracer.pending.size());
+  if (hipMemcpyAsync(n.data(), g_tracer.snap, n.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+      hipStreamSynchronize(s) == hipSuccess)
+    for (size_t i = 0; i < n.size(); i++) g_tracer.bytes[g_tracer.pending[i].slot] += g_tracer.pending[i].per_elem * n[i];
+  g_tracer.pending.clear();
 }
 
 void trace_end_impl(const char *name, hipStream_t s) {
@@ -152,6 +183,9 @@ struct pcbz_ctx {
   hipEvent_t fev[3] = {nullptr, nullptr, nullptr};
   std::vector<pcbz::GraphEntry> graphs;
   std::vector<pcbz::TuneRec> tune;
+  // pcbz_compress: per-shape round count and in-group-sort rounds of the last
+  // call that read its counts back (the later calls enqueue that schedule)
+  std::vector<pcbz::TuneRec> fixed;
   std::string tune_path;
   int eager_items = 8;
   int tune_rounds = 0;          // round budget the tuner gives graphs (0: the eager call's rounds + 1)
@@ -160,6 +194,7 @@ struct pcbz_ctx {
   pcbz_selector *sel = nullptr;
   float min_conf = 1.f;
   int use_graphs = 1;  // pcbz_compress_batch: 0 eager, 1 graphs where faster, 2 graphs
+  int use_fixed = 1;   // pcbz_compress: enqueue a known shape's schedule without read-backs
   uint32_t last_sel_bands = 0, last_sel_fallback = 0;
   std::string fixed_err;  // why the fixed workspace could not be set up (empty: it is)
   // decompression: pinned header read-back area and the last call's workspace
@@ -822,9 +857,16 @@ void copy_choices(pcbz_ctx *ctx, const Plan &P, const Work &w, const std::vector
   (void)ctx;
 }
 
-// Eager compression: host read-backs size every launch tightly.
+// Compression with host read-backs (fixed null: the block count, the
+// first-stage size and each round's unresolved count are read back and size
+// every launch tightly) or with a fixed schedule (no read-back until the
+// results).  A fixed schedule that leaves rotations unresolved, or meets a
+// group too large for the in-group sort, returns kRedo: the outputs then
+// hold no valid result and the caller runs the call again with read-backs.
+constexpr int kRedo = -1000;
+
 int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, std::vector<size_t> &lens,
-                 std::vector<uint8_t *> choice_out) {
+                 std::vector<uint8_t *> choice_out, const Tuning *fixed = nullptr) {
   Plan P;
   Work w{};
   int st = prepare(ctx, fin, P, w);
@@ -834,11 +876,14 @@ int run_compress(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, hipStream_t s, 
   if ((st = enqueue_upload(ctx, items, s))) return st;
   Tuning tu;
   tu.radix_items = ctx->eager_items;
+  if (fixed) tu = *fixed;
   int rounds = 0;
   if ((st = enqueue_compress(ctx, P, w, tu, s, &rounds))) return st;
   copy_choices(ctx, P, w, choice_out, s);
   uint32_t ctr[16];
   if ((st = read_results(ctx, P, w, s, lens, ctr))) return st;
+  trace_settle(s);
+  if (fixed && ctr[9] != 0) return kRedo;
   ctx->last_raw = P.ntot;
   ctx->last_rle = ctr[3];
   ctx->last_blocks = ctr[1];
@@ -1387,6 +1432,7 @@ int run_decompress(pcbz_ctx *ctx, const std::vector<DecIn> &in, hipStream_t s) {
   HIPCHK(ctx, hipGetLastError());
   HIPCHK(ctx, hipMemcpyAsync(ctx->h_small, w.ctr, 2 * 4, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  trace_settle(s);
   const uint32_t err = ctx->h_small[kDcErr], band = ctx->h_small[kDcBand];
   if (err) return fail(ctx, PCBZ_EDATA, "%s (band %u of the call)", dec_err_text(err), band);
   return PCBZ_OK;
@@ -1572,9 +1618,42 @@ int pcbz_compress(pcbz_ctx *ctx, const pcbz_params *prm, const uint16_t *d_frame
   HIPCHK(ctx, hipSetDevice(ctx->device));
   std::vector<FrameIn> fin(1);
   fin[0] = FrameIn{*prm, d_frame, d_prev, d_forced_choice, d_out, out_cap};
+  const hipStream_t s = (hipStream_t)stream;
   std::vector<size_t> lens;
-  int st = run_compress(ctx, fin, (hipStream_t)stream, lens, {d_choice_out});
+  // a shape seen before runs the schedule its last read-back call needed
+  // (one round spare) and syncs once, for the results
+  const bool sched = ctx->use_fixed && !getenv("PCBZ_NO_FIXED");
+  const std::string key = sched ? shape_key(ctx, fin) : std::string();
+  TuneRec *rec = nullptr;
+  for (TuneRec &r : ctx->fixed)
+    if (sched && r.key == key) rec = &r;
+  int st;
+  if (rec) {
+    Tuning tu;
+    tu.radix_items = ctx->eager_items;
+    tu.rounds = rec->rounds;
+    tu.seg_mask = rec->seg_mask;
+    st = run_compress(ctx, fin, s, lens, {d_choice_out}, &tu);
+    if (st != kRedo) {
+      if (!lens.empty()) *out_len = lens[0];
+      return st;
+    }
+  }
+  st = run_compress(ctx, fin, s, lens, {d_choice_out});
   if (!lens.empty()) *out_len = lens[0];
+  if (st || !sched) return st;
+  if (rec) {  // the data needed more: widen the shape's schedule
+    rec->rounds = std::max(rec->rounds, (int)ctx->last_rounds + 1);
+    rec->seg_mask &= seg_schedule(ctx);
+  } else {
+    if (ctx->fixed.size() >= 64) ctx->fixed.erase(ctx->fixed.begin());
+    TuneRec r;
+    r.key = key;
+    r.items = ctx->eager_items;
+    r.rounds = (int)ctx->last_rounds + 1;
+    r.seg_mask = seg_schedule(ctx);
+    ctx->fixed.push_back(r);
+  }
   return st;
 }
 

@@ -753,17 +753,14 @@ __device__ __forceinline__ uint32_t rot_ahead(uint32_t g, uint32_t s, uint32_t m
 // outputs start with one binary search on its diagonal and merges them
 // sequentially.  A level is skipped when no group crosses the middle of a
 // window of that level (its merge would move nothing).
-__global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_seg_sort(
-    const uint32_t *vals, const uint32_t *slot, const uint32_t *gstart, const uint32_t *rank, const uint32_t *d_u,
-    const uint32_t *bound,
-    const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h, int rbits, uint32_t *vals_out, uint64_t *keys_out,
-    uint32_t *d_fail) {
+// one tile of the in-group sort (every exit is uniform over the workgroup)
+__device__ __forceinline__ void seg_sort_tile(uint32_t tile, uint32_t U, uint32_t nb, const uint32_t *vals,
+                                              const uint32_t *slot, const uint32_t *gstart, const uint32_t *rank,
+                                              const uint32_t *bound, const uint32_t *blk_start, uint32_t h, int rbits,
+                                              uint32_t *vals_out, uint64_t *keys_out, uint32_t *d_fail,
+                                              uint64_t *scomp, uint16_t *sgs) {
   constexpr int kPer = (int)(kSegCap / kSegThreads);  // 8 consecutive elements per thread
   constexpr int kLevels = 10;                         // runs of 8 << i, i < 10
-  __shared__ uint64_t scomp[kSegCap];  // composites, in runs sorted so far
-  __shared__ uint16_t sgs[kSegCap];    // group starts, then group ends at each start
-  const uint32_t U = *d_u, nb = *d_nb;
-  const uint32_t tile = xcd_tile();
   const uint64_t t0 = (uint64_t)tile * kSegTile;
   if (t0 >= U) return;
   const uint32_t R0 = min(bound[tile], U);
@@ -913,6 +910,27 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))
   }
 }
 
+// The tiles come from an XCD-aware walk over a capped grid, so a round with
+// few unresolved rotations (or none: a round of a fixed schedule past the
+// data's need) costs a few workgroups, not one per tile of the bound.
+constexpr uint32_t kSegGridCap = 512;  // two workgroups of 80 KB LDS per CU
+
+__global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_seg_sort(
+    const uint32_t *vals, const uint32_t *slot, const uint32_t *gstart, const uint32_t *rank, const uint32_t *d_u,
+    const uint32_t *bound,
+    const uint32_t *blk_start, const uint32_t *d_nb, uint32_t h, int rbits, uint32_t *vals_out, uint64_t *keys_out,
+    uint32_t *d_fail) {
+  __shared__ uint64_t scomp[kSegCap];  // composites, in runs sorted so far
+  __shared__ uint16_t sgs[kSegCap];    // group starts, then group ends at each start
+  const uint32_t U = *d_u, nb = *d_nb;
+  const uint32_t nt = (U + kSegTile - 1) / kSegTile;
+  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
+    seg_sort_tile(wk.t, U, nb, vals, slot, gstart, rank, bound, blk_start, h, rbits, vals_out, keys_out, d_fail,
+                  scomp, sgs);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
 __global__ void k_bwt_left(const uint32_t *d_u, const uint32_t *d_fail, uint32_t *d_left) {
   *d_left = *d_u + *d_fail;
 }
@@ -1009,6 +1027,10 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
   if (blk_start)
     PCBZ_LAUNCH(k_rs_tile_base, dim3(1), dim3(256), 0, s, blk_start, d_nb, TILE, (uint32_t *)sg.tile_base);
   const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
+  // algorithmic bytes of the scatter passes: each reads and writes every
+  // 8-byte key and 4-byte value once (24 B per element a pass, counted at
+  // this point of the stream: later rounds reuse the count's slot)
+  trace_bytes_count("k_rs_scatter<ITEMS>", 24ull * (uint64_t)((bits + 7) / 8), d_n, s);
   for (int shift = 0; shift < bits; shift += 8) {
     PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, sg, shift, counts,
                 d_count_n);
@@ -1016,8 +1038,6 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
     PCBZ_LAUNCH(k_rs_scatter<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur],
                 iota_vals && shift == 0 ? nullptr : vals[cur], keys[cur ^ 1],
                 vals[cur ^ 1], d_n, n_max, sg, shift, counts, totals);
-    // a scatter pass reads and writes every 8-byte key and 4-byte value once
-    trace_bytes("k_rs_scatter<ITEMS>", 24ull * n_max);
     cur ^= 1;
   }
   return cur;
@@ -1115,7 +1135,8 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     const bool seg = pinned_u ? maxg <= kSegMaxGroup : rounds <= 64 && ((mask_in >> (rounds - 1)) & 1ull);
     if (seg) {
       if (rounds <= 64) mask_out |= 1ull << (rounds - 1);
-      const uint32_t gs = xcd_grid((uint32_t)std::max<uint64_t>(1, (n_cur + kSegTile - 1) / kSegTile));
+      const uint32_t gs = xcd_grid((uint32_t)std::max<uint64_t>(
+          1, std::min<uint64_t>(kSegGridCap, (n_cur + kSegTile - 1) / kSegTile)));
       PCBZ_LAUNCH(k_seg_sort, dim3(gs), dim3(kSegThreads), 0, s, vals[cur], slot, w.gstart, w.rank, du[u], w.seg_bound,
                   blk_start, d_nb, compared, rbits, vals[cur ^ 1], keys[cur ^ 1], w.d_fail);
       cur ^= 1;

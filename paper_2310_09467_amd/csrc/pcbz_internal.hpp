@@ -211,13 +211,8 @@ struct XcdWalk {
     step = per;
   }
 };
-// One tile per workgroup, the same placement: the grid is kXcds * per
-// workgroups (per = ceil(tiles / 8)) and workgroup i takes tile
-// (i mod 8) * per + i / 8 (tiles past the real count return at once).
-__device__ __forceinline__ uint32_t xcd_tile() {
-  const uint32_t per = gridDim.x / kXcds;
-  return per ? (blockIdx.x % kXcds) * per + blockIdx.x / kXcds : blockIdx.x;
-}
+// A grid of whole XCD groups (grids of eight or more workgroups are rounded
+// up to a multiple of eight, so no XCD idles in XcdWalk).
 inline uint32_t xcd_grid(uint32_t tiles) { return tiles < kXcds ? tiles : (tiles + kXcds - 1) / kXcds * kXcds; }
 
 // Binary search: largest i in [0, n) with a[i] <= key (a sorted ascending, a[0] <= key).
@@ -306,6 +301,18 @@ inline void trace_end(const char *name, hipStream_t s) {
 void trace_bytes_impl(const char *name, uint64_t bytes);
 inline void trace_bytes(const char *name, uint64_t bytes) {
   if (g_trace_on) trace_bytes_impl(name, bytes);
+}
+// The same with the element count in device memory (launches sized by a
+// bound): a one-thread kernel on s copies *d_count as it is at this point of
+// the stream, and per_elem times that count is added when trace_settle reads
+// the copies back after the call's results (the call ends with a sync anyway).
+void trace_bytes_count_impl(const char *name, uint64_t per_elem, const uint32_t *d_count, hipStream_t s);
+inline void trace_bytes_count(const char *name, uint64_t per_elem, const uint32_t *d_count, hipStream_t s) {
+  if (g_trace_on) trace_bytes_count_impl(name, per_elem, d_count, s);
+}
+void trace_settle_impl(hipStream_t s);
+inline void trace_settle(hipStream_t s) {
+  if (g_trace_on) trace_settle_impl(s);
 }
 #define PCBZ_LAUNCH(kernel, grid, block, lds, stream, ...)                  \
   do {                                                                      \

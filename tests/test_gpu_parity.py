@@ -172,6 +172,21 @@ def test_repeat_calls_are_deterministic(ctx, orc):
     assert a == b
 
 
+def test_known_shape_schedule(ctx, orc):
+    """A shape seen before runs the round schedule its last read-back call
+    needed, without read-backs; a frame that needs more rounds than that (or
+    has a group too large for the in-group sort) is redone with read-backs.
+    The adversarial frames share one shape and need very different rounds."""
+    from paper_2310_09467_amd import synth
+
+    frames = synth.adversarial_frames(150, 150)
+    for rep in range(2):
+        for name in sorted(frames):
+            f = frames[name]
+            _say("known shape", rep, name)
+            assert ctx.compress(f, None, 15, 9, 0x7) == orc.compress(f, None, 15, 9, 0x7)[0]
+
+
 def test_batch_equals_single_frames(ctx, orc):
     from paper_2310_09467_amd import synth
 
