@@ -1028,9 +1028,10 @@ int radix_sort_t(uint64_t *keys[2], uint32_t *vals[2], const uint32_t *d_n, uint
     PCBZ_LAUNCH(k_rs_tile_base, dim3(1), dim3(256), 0, s, blk_start, d_nb, TILE, (uint32_t *)sg.tile_base);
   const uint32_t grid = std::min<uint32_t>(ntiles, kGridCap);
   // algorithmic bytes of the scatter passes: each reads and writes every
-  // 8-byte key and 4-byte value once (24 B per element a pass, counted at
-  // this point of the stream: later rounds reuse the count's slot)
-  trace_bytes_count("k_rs_scatter<ITEMS>", 24ull * (uint64_t)((bits + 7) / 8), d_n, s);
+  // 8-byte key and 4-byte value once (24 B per element a pass; the first
+  // pass of a sort whose values are the positions reads none: 20 B), counted
+  // at this point of the stream (later rounds reuse the count's slot)
+  trace_bytes_count("k_rs_scatter<ITEMS>", 24ull * (uint64_t)((bits + 7) / 8) - (iota_vals ? 4u : 0u), d_n, s);
   for (int shift = 0; shift < bits; shift += 8) {
     PCBZ_LAUNCH(k_rs_hist<ITEMS>, dim3(grid), dim3(kRsThreads), 0, s, keys[cur], d_n, n_max, sg, shift, counts,
                 d_count_n);
