@@ -212,19 +212,35 @@ __global__ __launch_bounds__(kSelThreads) void k_tab_select(const uint16_t *sym,
     if (tf[i]) atomicAdd(&t0[i], tf[i]);
 }
 
-__device__ __forceinline__ uint32_t count_less(const uint32_t *a, uint32_t n, uint32_t x) {
-  uint32_t lo = 0, hi = n;  // first index with a[i] >= x
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] < x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-__device__ __forceinline__ uint32_t count_le(const uint32_t *a, uint32_t n, uint32_t x) {
-  uint32_t lo = 0, hi = n;  // first index with a[i] > x
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+// Number of elements of the sorted LDS array a[0, n) below x (kLE: at most
+// x) by an 8-way search: a step reads seven pivots at once (one LDS round
+// trip instead of three for a binary search) and keeps the part of the range
+// they bracket; the predicate is true on a prefix of the pivots, so the last
+// true pivot and the first false one bound the count.  Three steps for
+// n <= 258 (the levels of package-merge are a chain of these searches).
+template <bool kLE>
+__device__ __forceinline__ uint32_t count_sorted(const uint32_t *a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;  // the count lies in [lo, hi]
+  while (hi > lo) {
+    const uint32_t w = hi - lo;
+    uint32_t pv[7];
+    bool pr[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) pv[i] = lo + (w * (uint32_t)(i + 1) >> 3);  // in [lo, hi), non-decreasing
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+      const uint32_t v = a[pv[i]];
+      pr[i] = kLE ? v <= x : v < x;
+    }
+    uint32_t nlo = lo, nhi = hi;
+#pragma unroll
+    for (int i = 0; i < 7; i++)
+      if (pr[i]) nlo = pv[i] + 1;
+#pragma unroll
+    for (int i = 6; i >= 0; i--)
+      if (!pr[i]) nhi = pv[i];
+    lo = nlo;
+    hi = nhi;
   }
   return lo;
 }
@@ -283,12 +299,12 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
     if (t < np) pw[t] = wt[cur][2 * t] + wt[cur][2 * t + 1];
     __syncthreads();
     if (t < n) {
-      const uint32_t pos = t + count_less(pw, np, lw[t]);
+      const uint32_t pos = t + count_sorted<false>(pw, np, lw[t]);
       wt[cur ^ 1][pos] = lw[t];
       pk[j][pos] = 0;
     }
     if (t < np) {
-      const uint32_t pos = t + count_le(lw, n, pw[t]);
+      const uint32_t pos = t + count_sorted<true>(lw, n, pw[t]);
       wt[cur ^ 1][pos] = pw[t];
       pk[j][pos] = 1;
     }
@@ -318,7 +334,13 @@ __global__ __launch_bounds__(kPmThreads) void k_tab_lengths(const uint32_t *d_nb
         if (t < full) p = (uint32_t)__popcll(word);
         else if (t == full && rest) p = (uint32_t)__popcll(word & ((1ull << rest) - 1ull));
       }
-      for (int d = kWave / 2; d > 0; d >>= 1) p += (uint32_t)__shfl_xor((int)p, d);
+      // only lanes 0..15 hold words: a prefix sum along the first row of 16
+      // lanes with DPP row shifts, the total in lane 15
+      p += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, 0x111, 0xf, 0xf, false);  // row_shr:1
+      p += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, 0x112, 0xf, 0xf, false);  // row_shr:2
+      p += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, 0x114, 0xf, 0xf, false);  // row_shr:4
+      p += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, 0x118, 0xf, 0xf, false);  // row_shr:8
+      p = (uint32_t)__builtin_amdgcn_readlane((int)p, 15);
       if (t == 0) leaves_sel[j] = selc - p;
       selc = 2 * p;
     }
