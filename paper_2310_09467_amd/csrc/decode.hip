@@ -86,36 +86,101 @@ union BlockLds {
   DecodeLds dec;
 };
 
-// Follows code boundaries across the lanes' first-level entries e (symbol |
-// length << 9, one per lane for the code starting at that lane's bit): from
-// lane p (and k codes so far) it marks each code start in `starts` and moves
-// p by the code's length, while p < 64 and k < room.  Stops early at an entry
-// of length 0 and returns that entry (0: a longer code; otherwise no code).
-// Scalar registers and branches only: the chain is sequential by nature, and
-// a compiler-placed vector loop with masked branches cost ten times more.
-__device__ __forceinline__ uint32_t chain_follow(uint32_t e, uint32_t room, uint64_t &starts, uint32_t &p,
-                                                 uint32_t &k) {
-  uint32_t ep, l;
+// Follows code boundaries across the lanes: nx holds, per lane, the bit
+// where the next code starts if a code starts at that lane's bit (lane plus
+// the code's length; 128 plus the lane when the first-level entry has no
+// length).  From lane p it marks each start in `starts` and steps to its
+// successor until the successor is 64 or more (past the window, or 128 + a
+// lane to decode by the canonical search), and returns that successor.
+// Scalar registers and branches only, unrolled four codes deep: a lane read
+// whose select was written by another lane read needs four instructions
+// between them, and a taken branch costs more than the exits it replaces.
+__device__ __forceinline__ uint32_t chain_run(uint32_t nx, uint64_t &starts, uint32_t p) {
+  uint32_t q;
   asm volatile(
-      "s_mov_b32 %[ep], 1\n"
-      "1:\n\t"
       "s_cmp_ge_u32 %[p], 64\n\t"
-      "s_cbranch_scc1 2f\n\t"
-      "s_cmp_ge_u32 %[k], %[room]\n\t"
-      "s_cbranch_scc1 2f\n\t"
-      "v_readlane_b32 %[ep], %[e], %[p]\n\t"
-      "s_lshr_b32 %[l], %[ep], 9\n\t"
-      "s_cmp_eq_u32 %[l], 0\n\t"
-      "s_cbranch_scc1 2f\n\t"
+      "s_cbranch_scc1 9f\n"
+      "1:\n\t"
+      "v_readlane_b32 %[q], %[nx], %[p]\n\t"
       "s_bitset1_b64 %[st], %[p]\n\t"
-      "s_add_u32 %[p], %[p], %[l]\n\t"
-      "s_add_u32 %[k], %[k], 1\n\t"
+      "s_cmp_ge_u32 %[q], 64\n\t"
+      "s_cbranch_scc1 8f\n\t"
+      "s_nop 0\n\t"
+      "v_readlane_b32 %[p], %[nx], %[q]\n\t"
+      "s_bitset1_b64 %[st], %[q]\n\t"
+      "s_cmp_ge_u32 %[p], 64\n\t"
+      "s_cbranch_scc1 9f\n\t"
+      "s_nop 0\n\t"
+      "v_readlane_b32 %[q], %[nx], %[p]\n\t"
+      "s_bitset1_b64 %[st], %[p]\n\t"
+      "s_cmp_ge_u32 %[q], 64\n\t"
+      "s_cbranch_scc1 8f\n\t"
+      "s_nop 0\n\t"
+      "v_readlane_b32 %[p], %[nx], %[q]\n\t"
+      "s_bitset1_b64 %[st], %[q]\n\t"
+      "s_cmp_ge_u32 %[p], 64\n\t"
+      "s_cbranch_scc1 9f\n\t"
+      "s_nop 0\n\t"
       "s_branch 1b\n"
-      "2:"
-      : [st] "+s"(starts), [p] "+s"(p), [k] "+s"(k), [ep] "=&s"(ep), [l] "=&s"(l)
-      : [e] "v"(e), [room] "s"(room)
+      "8:\n\t"
+      "s_mov_b32 %[p], %[q]\n"
+      "9:"
+      : [st] "+s"(starts), [p] "+s"(p), [q] "=&s"(q)
+      : [nx] "v"(nx)
       : "scc");
-  return ep;
+  return p;
+}
+
+// The same walk four codes per lane read: j holds, per lane, where the walk
+// from that lane stands after four codes (or where it left the window or met
+// an entry without length), and (mlo, mhi) the code starts it passes on the
+// way (the lane's own bit included, the landing excluded).
+__device__ __forceinline__ uint32_t chain_jump(uint32_t j, uint32_t mlo, uint32_t mhi, uint64_t &starts) {
+  uint32_t p = 0, q, a, b, lo = 0, hi = 0;
+  asm volatile(
+      "1:\n\t"
+      "v_readlane_b32 %[q], %[j], %[p]\n\t"
+      "v_readlane_b32 %[a], %[ml], %[p]\n\t"
+      "v_readlane_b32 %[b], %[mh], %[p]\n\t"
+      "s_or_b32 %[lo], %[lo], %[a]\n\t"
+      "s_or_b32 %[hi], %[hi], %[b]\n\t"
+      "s_cmp_ge_u32 %[q], 64\n\t"
+      "s_cbranch_scc1 8f\n\t"
+      "v_readlane_b32 %[p], %[j], %[q]\n\t"
+      "v_readlane_b32 %[a], %[ml], %[q]\n\t"
+      "v_readlane_b32 %[b], %[mh], %[q]\n\t"
+      "s_or_b32 %[lo], %[lo], %[a]\n\t"
+      "s_or_b32 %[hi], %[hi], %[b]\n\t"
+      "s_cmp_ge_u32 %[p], 64\n\t"
+      "s_cbranch_scc0 1b\n\t"
+      "s_branch 9f\n"
+      "8:\n\t"
+      "s_mov_b32 %[p], %[q]\n"
+      "9:"
+      : [p] "+s"(p), [q] "=&s"(q), [a] "=&s"(a), [b] "=&s"(b), [lo] "+s"(lo), [hi] "+s"(hi)
+      : [j] "v"(j), [ml] "v"(mlo), [mh] "v"(mhi)
+      : "scc");
+  starts = (uint64_t)hi << 32 | lo;
+  return p;
+}
+
+// Four steps of the walk for every lane at once (two rounds of lane
+// permutes: the successor's successor, then the successor of that and its
+// own successor's successor); positions of 64 and more stay where they are.
+__device__ __forceinline__ void walk4(uint32_t nx, int lane, uint32_t &j, uint32_t &mlo, uint32_t &mhi) {
+  const uint32_t n1 = nx;
+  const uint32_t t2 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(n1 << 2), (int)nx);
+  const uint32_t n2 = n1 < 64 ? t2 : n1;
+  const uint32_t t3 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(n2 << 2), (int)nx);
+  const uint32_t t4 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(n2 << 2), (int)n2);
+  const uint32_t n3 = n2 < 64 ? t3 : n2;
+  j = n2 < 64 ? t4 : n2;
+  uint64_t m = 1ull << lane;
+  if (n1 < 64) m |= 1ull << n1;
+  if (n2 < 64) m |= 1ull << n2;
+  if (n3 < 64) m |= 1ull << n3;
+  mlo = (uint32_t)m;
+  mhi = (uint32_t)(m >> 32);
 }
 
 // Canonical decode of a 32-bit window with table g (codes assigned in
@@ -357,29 +422,47 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
     // first-level table only: most lanes sit at positions that are no code
     // boundary, and a longer code is decoded below when the chain reaches it
     uint32_t e = D.lut[t][w >> (32 - kLutBits)];
-    // follow the true code boundaries from the first lane, marking them, for
-    // at most the rest of the group; what the symbols are is settled after
+    // follow the true code boundaries from the first lane to the end of the
+    // window, marking them; codes past the group's end (read with this
+    // group's table) and past the block's end are cut off after
     const uint32_t room = (uint32_t)__builtin_amdgcn_readfirstlane((int)(kGroupSize - in_grp));
-    uint64_t starts = 0;
-    uint32_t p = 0, k = 0;
+    const uint32_t len0 = e >> 9;
+    uint32_t nx = len0 ? (uint32_t)lane + len0 : 128u + (uint32_t)lane;
+    uint32_t j, mlo, mhi;
+    walk4(nx, lane, j, mlo, mhi);
+    uint64_t starts;
+    uint32_t p = chain_jump(j, mlo, mhi, starts);
     bool stuck = false;
-    for (;;) {
-      const uint32_t ep = chain_follow(e, room, starts, p, k);
-      if (p >= 64 || k >= room) break;
-      // the chain stopped on an entry of length 0: a code longer than the
-      // first-level table (decoded here and put into that lane), or none
-      const uint32_t r = ep == 0u ? canon_decode(D, (int)t, (uint32_t)__builtin_amdgcn_readlane((int)w, (int)p))
-                                  : kInvalid;
+    // after a stop the lanes' four-code jumps no longer hold: one code a read
+    while (p >= 128) {
+      // a start whose first-level entry has no length: a code longer than
+      // the first-level table (decoded here and put into that lane), or none.
+      // Not needed when the group or the block ends before it.
+      const uint32_t s = p - 128;
+      if ((uint32_t)__popcll(starts) - 1u >= room) break;
+      if (ballot64(((starts >> lane) & 1ull) && lane != (int)s && (e & 0x1FFu) == eob)) break;
+      const uint32_t r = canon_decode(D, (int)t, (uint32_t)__builtin_amdgcn_readlane((int)w, (int)s));
       if ((r >> 9) == 0u) {
         stuck = true;
         break;
       }
-      e = lane == (int)p ? r : e;
+      e = lane == (int)s ? r : e;
+      p = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s + (r >> 9)));
+      nx = lane == (int)s ? p : nx;
+      p = chain_run(nx, starts, p);
+    }
+    // the group's last code: the starts past the room-th are the next group's
+    const uint32_t rank = (uint32_t)__popcll(starts & lanemask_lt());
+    const uint64_t over = ballot64(((starts >> lane) & 1ull) && rank == room);
+    uint32_t adv = p;  // bits consumed
+    if (over) {
+      adv = (uint32_t)__builtin_ctzll(over);
+      starts &= (1ull << adv) - 1ull;
+      stuck = false;
     }
     const bool at = (starts >> lane) & 1ull;
     const uint32_t sy = e & 0x1FFu;
     const uint64_t ends = ballot64(at && sy == eob);
-    uint32_t adv = p;  // bits consumed
     if (ends) {  // the block ends: drop whatever was followed past its last symbol
       const uint32_t f = (uint32_t)__builtin_ctzll(ends);
       starts &= f == 63 ? ~0ull : (2ull << f) - 1ull;
@@ -394,7 +477,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       ok = false;
       break;
     }
-    if ((starts >> lane) & 1ull) obuf[nbuf + (uint32_t)__popcll(starts & lanemask_lt())] = (uint16_t)sy;
+    if ((starts >> lane) & 1ull) obuf[nbuf + rank] = (uint16_t)sy;  // the cuts keep lower starts
     nsym += cnt;
     nbuf += cnt;
     if (nbuf > kOutBuf - 64 || done) flush();
