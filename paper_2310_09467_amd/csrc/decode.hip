@@ -206,7 +206,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
   __shared__ uint32_t over_lds;
   // decoded symbols gather here and go to global memory a thousand at a time
   // (a store per step made every step wait for the last one's data register)
-  __shared__ uint16_t obuf[kOutBuf];
+  __shared__ uint16_t obuf[kOutBuf + 64];  // 64 spare entries for lanes with nothing to store
   const uint32_t b = blockIdx.x;
   const DecBand B = bands[b];
   const int lane = threadIdx.x;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
     start = pv.end_byte;
     sym0 = pv.sym_off + pv.n_sym;
   }
-  const uint32_t sym_cap = B.sym_end > sym0 ? B.sym_end - sym0 : 0u;
+  const uint32_t sym_cap = (uint32_t)__builtin_amdgcn_readfirstlane((int)(B.sym_end > sym0 ? B.sym_end - sym0 : 0u));
   const uint8_t *src = B.src + start;
   const uint32_t len = B.src_len - start;  // bytes left in the band
   auto fail = [&](void) {
@@ -418,6 +418,8 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       stage_be_words(D.win, src, len, wbase >> 5, kWinWords + 4);
       __syncthreads();
     }
+    // the next group's table, read ahead (the last group's own when none follows)
+    const uint32_t t_next = sel_lds[g + 1 < nsel ? g + 1 : g];
     const uint32_t w = bits32(D.win, o - wbase + lane);
     // first-level table only: most lanes sit at positions that are no code
     // boundary, and a longer code is decoded below when the chain reaches it
@@ -451,23 +453,23 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       nx = lane == (int)s ? p : nx;
       p = chain_run(nx, starts, p);
     }
-    // the group's last code: the starts past the room-th are the next group's
-    const uint32_t rank = (uint32_t)__popcll(starts & lanemask_lt());
-    const uint64_t over = ballot64(((starts >> lane) & 1ull) && rank == room);
-    uint32_t adv = p;  // bits consumed
-    if (over) {
-      adv = (uint32_t)__builtin_ctzll(over);
-      starts &= (1ull << adv) - 1ull;
-      stuck = false;
-    }
-    const bool at = (starts >> lane) & 1ull;
+    // the cuts: the group ends after its room-th code, the block after its
+    // end-of-block code, whichever comes first (both masks from one pair of
+    // compares; a lane that is no start takes a rank no cut matches)
     const uint32_t sy = e & 0x1FFu;
-    const uint64_t ends = ballot64(at && sy == eob);
+    const uint32_t rank = (uint32_t)__popcll(starts & lanemask_lt());
+    const uint32_t key = (starts >> lane) & 1ull ? rank : 0xFFFFu;
+    const uint64_t over = ballot64(key == room);
+    const uint64_t ends = ballot64((sy == eob ? key : 0xFFFFu) < room);
+    uint32_t adv = p;  // bits consumed
     if (ends) {  // the block ends: drop whatever was followed past its last symbol
       const uint32_t f = (uint32_t)__builtin_ctzll(ends);
       starts &= f == 63 ? ~0ull : (2ull << f) - 1ull;
       adv = f + ((uint32_t)__builtin_amdgcn_readlane((int)e, (int)f) >> 9);
       done = true;
+    } else if (over) {  // the rest is the next group's
+      adv = (uint32_t)__builtin_ctzll(over);
+      starts &= (1ull << adv) - 1ull;
     } else if (stuck) {
       ok = false;
       break;
@@ -477,17 +479,18 @@ __global__ __launch_bounds__(64) void k_dec_block(const DecBand *bands, DecSlot 
       ok = false;
       break;
     }
-    if ((starts >> lane) & 1ull) obuf[nbuf + rank] = (uint16_t)sy;  // the cuts keep lower starts
+    // every lane stores: the cut starts in order (the cuts keep the lower
+    // ranks), the others into the spare entries past the buffer
+    obuf[(starts >> lane) & 1ull ? nbuf + rank : kOutBuf + (uint32_t)lane] = (uint16_t)sy;
     nsym += cnt;
     nbuf += cnt;
     if (nbuf > kOutBuf - 64 || done) flush();
     o += adv;
     in_grp += cnt;
-    if (in_grp == kGroupSize) {
-      in_grp = 0;
-      g++;
-      if (g < nsel) t = sel_lds[g];
-    }
+    const bool next_group = in_grp == kGroupSize;
+    in_grp = next_group ? 0u : in_grp;
+    g += next_group ? 1u : 0u;
+    t = next_group ? t_next : t;
   }
   // end of stream: magic 0x177245385090, the combined CRC (= the block CRC
   // for a one-block stream), padding to a byte

@@ -219,3 +219,12 @@ def adversarial_frames(h=450, w=450, seed=9):
     p7 = np.frombuffer(bytes([3, 1, 4, 1, 5, 9, 2] * ((2 * h * w) // 7 + 1)), np.uint8)[: 2 * h * w]
     out["period7"] = p7.view(np.uint16).reshape(h, w).copy()
     return out
+
+
+def long_tail_frame(h=450, w=450, seed=5, scale=16.0):
+    """Bytes drawn independently with a geometric tail (byte v about
+    2**(-v / scale) as likely as byte 0, 255 taking the rest): the rare bytes
+    get Huffman codes longer than twelve bits."""
+    rng = np.random.default_rng(seed)
+    v = rng.geometric(1.0 - 2.0 ** (-1.0 / scale), size=2 * h * w) - 1
+    return np.minimum(v, 255).astype(np.uint8).view(np.uint16).reshape(h, w).copy()

@@ -129,6 +129,28 @@ def test_adversarial_roundtrip(ctx, orc, level):
         _decode_checked(ctx, orc, f, None, level, ob)
 
 
+@pytest.mark.parametrize("level", [1, 9])
+def test_long_codes_roundtrip(ctx, orc, level):
+    """Codes longer than the decoder's first-level table (12 bits) in every
+    group table: the oracle's own tables for the first block must use them,
+    then the oracle's and the GPU's containers decode to the frame."""
+    from paper_2310_09467_amd import synth
+
+    f = synth.long_tail_frame()
+    x = orc.to_bytes(orc.arrange(f, 0, 0, None, 15, level))
+    T, _, os_ = orc.rle1_blocks(x, level)
+    _, L, _ = orc.bwt(T[: os_[1]] if len(os_) > 1 else T)
+    sym, _, _ = orc.mtf_rle2(L)
+    _, sel, lens = orc.huff_tables(sym, int(sym.max()) + 1)
+    used_long = sum(int((lens[sel[k]][sym[50 * k: 50 * k + 50]] > 12).sum()) for k in range(len(sel)))
+    assert used_long > 100, used_long
+    print("long codes", level, used_long, flush=True)
+    ob, _ = orc.compress(f, None, 15, level, 0x7)
+    _decode_checked(ctx, orc, f, None, level, ob)
+    blob = ctx.compress(f, None, 15, level, 0x7)
+    _decode_checked(ctx, orc, f, None, level, blob)
+
+
 def test_forced_and_temporal_roundtrip(ctx, orc):
     from paper_2310_09467_amd import synth
 
