@@ -472,7 +472,6 @@ size_t layout(Arena &A, const Plan &P, bool compress, Work &w) {
   w.bw.rank = A.get<uint32_t>(nr + 1);
   w.bw.counts = A.get<uint32_t>(radix_counts_words((uint32_t)nr, S));
   w.bw.seg_bound = A.get<uint32_t>(seg_bound_words((uint32_t)nr));
-  w.bw.goff = A.get<uint32_t>(nr + 1);
   w.bw.gstart = A.get<uint32_t>(nr + 1);
   w.bw.aggs = A.get<uint32_t>(rnd_aggs_words((uint32_t)nr));
   w.bw.d_u = w.ctr ? w.ctr + 10 : nullptr;        // [10], [11]

@@ -459,20 +459,21 @@ constexpr uint32_t kSegTile = 4096;                    // positions whose group 
 constexpr uint32_t kSegMaxGroup = kSegCap - kSegTile;  // largest group the in-tile sort takes
 
 // ---------------------------------------------------------------- one doubling round
-// A round turns the sorted list into ranks in three launches over tiles of
+// A round turns the sorted list into ranks in two launches over tiles of
 // 4096 elements (256 threads x 16):
 //   k_rnd_marks    per-tile maximum of the group-start marks (a group start
-//                  is marked with its slot, other elements with 0);
+//                  is marked with its slot, other elements with 0) and
+//                  per-tile count of the elements that stay unresolved (both
+//                  follow from the keys and slots alone);
 //   k_rnd_update   max-scan of the marks (each element's rank = its group's
-//                  first slot), rank and suffix-array writes, and per-tile
-//                  counts of the elements that stay unresolved;
-//   k_rnd_compact  exclusive scan of those flags and the compaction.
+//                  first slot), rank and suffix-array writes, and the
+//                  compaction of the unresolved elements (exclusive scan of
+//                  the counts).
 // Each scan takes its carry by reducing the tile aggregates in front of its
 // tile itself (no look-back: see the tile-scan helpers).
 constexpr int kRThreads = kTThreads;
 constexpr int kRItems = kTItems;
 constexpr uint32_t kRTile = kTTile;
-constexpr uint32_t kUnresNone = 0xFFFFFFFFu;  // goffw entry of a resolved element
 
 // 16 consecutive 32- or 64-bit values from k0 (vector loads when all are in
 // range)
@@ -531,11 +532,58 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Group boundaries around a thread's 16 consecutive list elements: bit i of
+// the result is set where element i starts a group (its key differs from the
+// one before); *ends: the last element's key differs from the next one.
+__device__ __forceinline__ uint32_t group_starts(const uint64_t *keys, uint32_t k0, uint32_t U, int lane,
+                                                 const uint64_t *key, bool &ends) {
+  uint64_t before = shfl64(key[kRItems - 1], lane - 1), after = shfl64(key[0], lane + 1);
+  if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
+  if (lane == kWave - 1) after = k0 + kRItems < U ? keys[k0 + kRItems] : 0ull;
+  uint32_t diff = 0;
+#pragma unroll
+  for (int i = 0; i < kRItems; i++) {
+    const uint64_t pk = i == 0 ? before : key[i - 1];
+    if (k0 + i == 0 || key[i] != pk) diff |= 1u << i;
+  }
+  ends = k0 + kRItems >= U || after != key[kRItems - 1];
+  return diff;
+}
+
+// The elements that leave the list this round (bit i for element k0 + i):
+// groups of one, and every element of a block whose rotations are compared
+// in full.  A slot lies in its rotation's block (the suffix-array slots of a
+// block are the block's own range of positions).  Bit i + 16: element i ends
+// its group.
+__device__ __forceinline__ uint32_t resolved(uint32_t diff, bool ends, const uint32_t *sl, uint32_t k0, uint32_t U,
+                                             bool any_short, const uint32_t *blk_start, uint32_t nb,
+                                             uint32_t compared) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < kRItems; i++) {
+    const uint32_t k = k0 + i;
+    if (k >= U) continue;
+    const bool last = k + 1 == U || (i + 1 < kRItems ? ((diff >> (i + 1)) & 1u) != 0 : ends);
+    bool done = ((diff >> i) & 1u) && last;
+    if (!done && any_short) {
+      const uint32_t b = block_of(blk_start, nb, sl[i]);
+      done = blk_start[b + 1] - blk_start[b] <= compared;
+    }
+    m |= (done ? 1u : 0u) << i;
+    m |= (last ? 1u : 0u) << (i + 16);
+  }
+  return m;
+}
+
 __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, const uint32_t *slot,
-                                                         const uint32_t *d_u, uint32_t *aggs, uint32_t *d_maxg) {
+                                                         const uint32_t *d_u, const uint32_t *blk_start,
+                                                         const uint32_t *d_nb, const uint32_t *d_min_m,
+                                                         uint32_t compared, uint32_t *aggs_m, uint32_t *aggs_s,
+                                                         uint32_t *d_maxg) {
   __shared__ uint32_t sh[kRThreads / kWave];
-  const uint32_t U = *d_u;
+  const uint32_t U = *d_u, nb = *d_nb;
   const uint32_t nt = (U + kRTile - 1) / kRTile;
+  const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
   const int lane = lane_id();
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_maxg = 0;
   for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
@@ -545,63 +593,67 @@ __global__ __launch_bounds__(kRThreads) void k_rnd_marks(const uint64_t *keys, c
     uint32_t sl[kRItems];
     load16(keys, k0, U, key);
     load_slots(slot, k0, U, sl);
-    uint64_t before = shfl64(key[kRItems - 1], lane - 1);
-    if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
+    bool ends;
+    const uint32_t diff = group_starts(keys, k0, U, lane, key, ends);
     // slots grow along the list: the last group start of the thread has the largest mark
     uint32_t m = 0;
 #pragma unroll
-    for (int i = 0; i < kRItems; i++) {
-      const uint64_t pk = i == 0 ? before : key[i - 1];
-      if (k0 + i < U && (k0 + i == 0 || key[i] != pk)) m = sl[i];
-    }
+    for (int i = 0; i < kRItems; i++)
+      if (k0 + i < U && ((diff >> i) & 1u)) m = sl[i];
+    const uint32_t res = resolved(diff, ends, sl, k0, U, any_short, blk_start, nb, compared);
+    const uint32_t valid = k0 >= U ? 0u : k0 + kRItems <= U ? 0xFFFFu : (1u << (U - k0)) - 1u;
+    const uint32_t cnt = (uint32_t)__popc(valid & ~res & 0xFFFFu);
     m = block_reduce<true>(m, sh);
-    if (threadIdx.x == 0) aggs[tile] = m;
+    const uint32_t c = block_reduce<false>(cnt, sh);
+    if (threadIdx.x == 0) {
+      aggs_m[tile] = m;
+      aggs_s[tile] = c;
+    }
   }
 }
 
-// Ranks, suffix-array entries of the elements now in a group of one (or
-// whose block is fully compared), and for every other element its position
-// inside its group (goffw; kUnresNone for resolved ones).  Also the largest
-// group that stays unresolved (its last element knows the size: slots of a
-// group are consecutive and its rank is the first slot).  A thread owns 16
-// consecutive elements (vector loads); keys next to them come from the
-// neighbouring lanes.  From the second round on, bits old_bits and up of a
-// key hold the rank the key was built from, which rank[] still holds: the
-// random rank write is skipped where the new rank equals it (the first part
-// of every group that splits).
-__global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_rnd_update(const uint64_t *keys, const uint32_t *vals,
-                                                          const uint32_t *slot, const uint32_t *d_u,
-                                                          const uint32_t *aggs_m, const uint32_t *blk_start,
-                                                          const uint32_t *d_nb, const uint32_t *d_min_m,
-                                                          uint32_t compared, int old_bits, uint32_t *rank,
-                                                          uint32_t *sa, uint32_t *goffw, uint32_t *aggs_s,
-                                                          uint32_t *d_maxg) {
+// Ranks, suffix-array entries of the elements now resolved, and the list of
+// the unresolved ones moved to the front (their order kept) with the compact
+// position of each one's group start; writes the new count.  Also the
+// largest group that stays unresolved (its last element knows the size:
+// slots of a group are consecutive and its rank is the first slot), and the
+// in-group sort's tile boundaries: the last element of each unresolved group
+// sets bound[t] = the first group start at or after t * kSegTile, which for
+// every t * kSegTile inside (group start, group end] is this group's end.
+// A thread owns 16 consecutive elements (vector loads); keys next to them
+// come from the neighbouring lanes.  The compact list is staged per
+// wavefront in LDS and stored in runs of consecutive positions.  From the
+// second round on, bits old_bits and up of a key hold the rank the key was
+// built from, which rank[] still holds: the random rank write is skipped
+// where the new rank equals it (the first part of every group that splits).
+__global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_rnd_update(
+    const uint64_t *keys, const uint32_t *vals, const uint32_t *slot, const uint32_t *d_u, const uint32_t *aggs_m,
+    const uint32_t *aggs_s, const uint32_t *blk_start, const uint32_t *d_nb, const uint32_t *d_min_m,
+    uint32_t compared, int old_bits, uint32_t *rank, uint32_t *sa, uint32_t *vals2, uint32_t *slot2,
+    uint32_t *gstart2, uint32_t *bound, uint32_t *d_unew, uint32_t *d_maxg) {
   __shared__ uint32_t buf[kRTile + kRTile / 32];
   __shared__ uint32_t oldr[kRTile + kRTile / 32];
   __shared__ uint32_t sh[kRThreads / kWave];
+  __shared__ uint32_t shw[kRThreads / kWave];
   const uint32_t U = *d_u, nb = *d_nb;
   const uint32_t nt = (U + kRTile - 1) / kRTile;
-  const bool any_short = compared >= *d_min_m;  // else no block is fully compared yet
-  const int lane = lane_id();
-  uint32_t carry = 0, counted = 0, gmax = 0;
+  const bool any_short = compared >= *d_min_m;
+  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bound[0] = 0;
+    if (nt == 0) *d_unew = 0;
+  }
+  uint32_t carry = 0, counted = 0, ccarry = 0, ccounted = 0, gmax = 0;
   for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
     const uint32_t tile = wk.t;
     const uint32_t base = tile * kRTile;
     const uint32_t k0 = base + threadIdx.x * kRItems;
-    uint32_t sl[kRItems], g[kRItems], diff = 0;  // diff bit i: key i differs from key i - 1
-    bool ends;                                   // the last element's key differs from the next one
+    uint32_t sl[kRItems], g[kRItems], diff;
+    bool ends;
     {
       uint64_t key[kRItems];
       load16(keys, k0, U, key);
-      uint64_t before = shfl64(key[kRItems - 1], lane - 1), after = shfl64(key[0], lane + 1);
-      if (lane == 0) before = k0 > 0 && k0 - 1 < U ? keys[k0 - 1] : 0ull;
-      if (lane == kWave - 1) after = k0 + kRItems < U ? keys[k0 + kRItems] : 0ull;
-#pragma unroll
-      for (int i = 0; i < kRItems; i++) {
-        const uint64_t pk = i == 0 ? before : key[i - 1];
-        if (k0 + i == 0 || key[i] != pk) diff |= 1u << i;
-      }
-      ends = k0 + kRItems >= U || after != key[kRItems - 1];
+      diff = group_starts(keys, k0, U, lane, key, ends);
       // the rank each key was built from, kept in LDS (registers are the
       // limit on this kernel's occupancy)
 #pragma unroll
@@ -611,91 +663,73 @@ __global__ __launch_bounds__(kRThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     load_slots(slot, k0, U, sl);
     load16(vals, k0, U, g);
     carry = tile_carry<true>(aggs_m, counted, tile, carry, sh);
+    ccarry = tile_carry<false>(aggs_s, ccounted, tile, ccarry, sh);
 #pragma unroll
     for (int i = 0; i < kRItems; i++)
       buf[tpad(threadIdx.x * kRItems + i)] = k0 + i < U && ((diff >> i) & 1u) ? sl[i] : 0u;
     __syncthreads();
     tile_scan<true, true>(buf, carry, sh);
-    uint32_t cnt = 0, gw[kRItems];
+    const uint32_t res = resolved(diff, ends, sl, k0, U, any_short, blk_start, nb, compared);
+    const uint32_t valid = k0 >= U ? 0u : k0 + kRItems <= U ? 0xFFFFu : (1u << (U - k0)) - 1u;
+    const uint32_t unres = valid & ~res & 0xFFFFu;
+    uint32_t off[kRItems];
 #pragma unroll
     for (int i = 0; i < kRItems; i++) {
       const uint32_t k = k0 + i;
-      gw[i] = kUnresNone;
+      off[i] = 0;
       if (k >= U) continue;
       const uint32_t nr = buf[tpad(threadIdx.x * kRItems + i)];
       if (nr != oldr[tpad(threadIdx.x * kRItems + i)]) rank[g[i]] = nr;  // rank[g] already holds the rank the key was built from
-      const bool first = sl[i] == nr;  // ranks are first slots
-      const bool last = k + 1 == U || (i + 1 < kRItems ? ((diff >> (i + 1)) & 1u) != 0 : ends);
-      bool done = first && last;
-      if (!done && any_short) {
-        const uint32_t b = block_of(blk_start, nb, g[i]);
-        done = blk_start[b + 1] - blk_start[b] <= compared;
-      }
-      if (done) sa[sl[i]] = g[i];  // final position; unresolved ones are written in a later round
-      const uint32_t off = sl[i] - nr;
-      gw[i] = done ? kUnresNone : off;
-      cnt += done ? 0u : 1u;
-      if (!done && last) gmax = max(gmax, off + 1u);
+      if ((res >> i) & 1u) sa[sl[i]] = g[i];  // final position; unresolved ones are written in a later round
+      off[i] = sl[i] - nr;
+      if (((unres >> i) & 1u) && ((res >> (i + 16)) & 1u)) gmax = max(gmax, off[i] + 1u);
     }
-    store16(goffw, k0, U, gw);
-    cnt = block_reduce<false>(cnt, sh);
-    if (threadIdx.x == 0) aggs_s[tile] = cnt;
+    // compact positions: the tile's carry, the waves before, the lanes before
+    const uint32_t cnt = (uint32_t)__popc(unres);
+    uint32_t x = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_up((int)x, d);
+      if (lane >= d) x += o;
+    }
+    const uint32_t lane_before = x - cnt, wave_total = (uint32_t)__shfl((int)x, kWave - 1);
+    if (lane == 0) shw[wave] = wave_total;
+    __syncthreads();
+    uint32_t wave_before = 0, tile_total = 0;
+    for (int w = 0; w < kRThreads / kWave; w++) {
+      wave_before += w < wave ? shw[w] : 0u;
+      tile_total += shw[w];
+    }
+    const uint32_t q_wave = ccarry + wave_before;
+    if (tile == nt - 1 && threadIdx.x == 0) *d_unew = ccarry + tile_total;
+    // each wavefront stages its elements in its own quarter of buf (it read
+    // its ranks from there already), then stores runs of 64
+    uint32_t *stage = buf + tpad((uint32_t)wave * (kRTile / (kRThreads / kWave)));
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      uint32_t j = lane_before;
+#pragma unroll
+      for (int i = 0; i < kRItems; i++) {
+        if (!((unres >> i) & 1u)) continue;
+        const uint32_t q = q_wave + j;
+        stage[tpad(j)] = a == 0 ? g[i] : a == 1 ? sl[i] : q - off[i];
+        if (a == 2 && ((res >> (i + 16)) & 1u)) {  // last of its group
+          const uint32_t head = q - off[i], end = q + 1u;
+          for (uint32_t t = head / kSegTile + 1; (uint64_t)t * kSegTile <= end; t++) bound[t] = end;
+        }
+        j++;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t *dst = a == 0 ? vals2 : a == 1 ? slot2 : gstart2;
+      for (uint32_t r = (uint32_t)lane; r < wave_total; r += kWave) dst[q_wave + r] = stage[tpad(r)];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
   gmax = block_reduce<true>(gmax, sh);
   if (threadIdx.x == 0 && gmax) atomicMax(d_maxg, gmax);
-}
-
-// Moves the unresolved elements to the front (their order kept), with the
-// compact position of each one's group start; writes the new count.  The
-// last element of each unresolved group also records the in-group sort's
-// tile boundaries: bound[t] = the first group start at or after
-// t * kSegTile, which for every t * kSegTile inside (group start, group end]
-// is this group's end.
-__global__ __launch_bounds__(kRThreads) void k_rnd_compact(const uint32_t *vals, const uint32_t *slot,
-                                                           const uint32_t *goffw, const uint32_t *d_u,
-                                                           const uint32_t *aggs_s, uint32_t *vals2, uint32_t *slot2,
-                                                           uint32_t *gstart2, uint32_t *bound, uint32_t *d_unew) {
-  __shared__ uint32_t buf[kRTile + kRTile / 32];
-  __shared__ uint32_t sh[kRThreads / kWave];
-  const uint32_t U = *d_u;
-  const uint32_t nt = (U + kRTile - 1) / kRTile;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    bound[0] = 0;
-    if (nt == 0) *d_unew = 0;
-  }
-  uint32_t carry = 0, counted = 0;
-  for (XcdWalk wk(nt); wk.t < wk.end; wk.t += wk.step) {
-    const uint32_t tile = wk.t;
-    carry = tile_carry<false>(aggs_s, counted, tile, carry, sh);
-    const uint32_t base = tile * kRTile;
-    uint32_t w[kRItems];
-#pragma unroll
-    for (int i = 0; i < kRItems; i++) {
-      const int j = i * kRThreads + threadIdx.x;
-      const uint32_t k = base + (uint32_t)j;
-      w[i] = k < U ? goffw[k] : kUnresNone;
-      buf[tpad(j)] = w[i] != kUnresNone ? 1u : 0u;
-    }
-    __syncthreads();
-    const uint32_t total = tile_scan<false, false>(buf, carry, sh);
-#pragma unroll
-    for (int i = 0; i < kRItems; i++) {
-      const int j = i * kRThreads + threadIdx.x;
-      const uint32_t k = base + (uint32_t)j;
-      if (w[i] == kUnresNone) continue;
-      const uint32_t q = buf[tpad(j)], off = w[i];
-      vals2[q] = vals[k];
-      slot2[q] = slot ? slot[k] : k;
-      gstart2[q] = q - off;
-      const uint32_t wn = k + 1 < U ? goffw[k + 1] : kUnresNone;
-      if (wn == 0 || wn == kUnresNone) {  // last of its group: the next element starts another or is resolved
-        const uint32_t head = q - off, end = q + 1u;
-        for (uint32_t t = head / kSegTile + 1; (uint64_t)t * kSegTile <= end; t++) bound[t] = end;
-      }
-    }
-    if (tile == nt - 1 && threadIdx.x == 0) *d_unew = carry + total;
-    __syncthreads();
-  }
 }
 
 __global__ void k_bwt_keys(const uint32_t *vals, const uint32_t *d_u, const uint32_t *rank, const uint32_t *blk_start,
@@ -1105,16 +1139,16 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
   uint32_t n_cur = n_max;  // bound on the unresolved count (exact when read back)
   uint32_t maxg = 0xFFFFFFFFu;
   for (;;) {
-    // new ranks (max-scan of group-start slots), then the compaction
+    // new ranks (max-scan of group-start slots) and the compaction
     const uint32_t gt = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kGridCap, (n_cur + kRTile - 1) / kRTile));
     uint32_t *aggs_m = w.aggs, *aggs_s = w.aggs + rnd_aggs_words(n_max) / 2;
     // after the first sort, list position k is suffix-array slot k
     const uint32_t *slot_in = rounds == 0 ? nullptr : slot;
-    PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot_in, du[u], aggs_m, w.d_maxg);
-    PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot_in, du[u], aggs_m, blk_start,
-                d_nb, w.d_min_m, compared, rounds == 0 ? 0 : rbits, w.rank, sa, w.goff, aggs_s, w.d_maxg);
-    PCBZ_LAUNCH(k_rnd_compact, dim3(gt), dim3(kRThreads), 0, s, vals[cur], slot_in, w.goff, du[u], aggs_s, vals[cur ^ 1],
-                slot2, w.gstart, w.seg_bound, du[u ^ 1]);
+    PCBZ_LAUNCH(k_rnd_marks, dim3(gt), dim3(kRThreads), 0, s, keys[cur], slot_in, du[u], blk_start, d_nb, w.d_min_m,
+                compared, aggs_m, aggs_s, w.d_maxg);
+    PCBZ_LAUNCH(k_rnd_update, dim3(gt), dim3(kRThreads), 0, s, keys[cur], vals[cur], slot_in, du[u], aggs_m, aggs_s,
+                blk_start, d_nb, w.d_min_m, compared, rounds == 0 ? 0 : rbits, w.rank, sa, vals[cur ^ 1], slot2,
+                w.gstart, w.seg_bound, du[u ^ 1], w.d_maxg);
     u ^= 1;
     rounds++;
     if (pinned_u) {

@@ -402,7 +402,6 @@ struct BwtWork {
   uint32_t *d_maxg;     // largest unresolved group of the last round (device, d_u + 6)
   uint32_t *d_fail;     // set when a group did not fit the in-group sort (device)
   uint32_t *seg_bound;  // [seg_bound_words] tile boundaries of the in-group sort
-  uint32_t *goff;       // [N+1] position of each element inside its group (all ones: resolved)
   uint32_t *gstart;     // [N+1] compact position of each unresolved element's group start
   uint32_t *aggs;       // [rnd_aggs_words] tile aggregates of a doubling round's two scans
 };
