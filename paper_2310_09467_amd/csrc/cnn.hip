@@ -14,7 +14,7 @@
 // (64 -> 32 -> 16 -> 8); flatten 2048 -> FC 64, ReLU -> FC 4.  Weights are kept
 // in FP32 (master copy for AdamW) and BF16 (GEMM operand); every layer input
 // (activations, upstream gradients) is rounded to BF16; products accumulate in
-// FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16).  Convolutions are
+// FP32 on the matrix cores (v_mfma_f32_16x16x32_bf16).  Convolutions are
 // explicit im2col GEMMs: rows (image, y, x), columns (ky, kx, channel).
 #include <cmath>
 #include <cstdio>
@@ -28,7 +28,20 @@ namespace pcbz {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));  // BF16 bits
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 32 product on the matrix cores: lane l holds row (A) or
+// column (B) l % 16 and k = 8 * (l / 16) .. + 7 of the step; the result's
+// element t of lane l is row 4 * (l / 16) + t, column l % 16.
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mfma_bf16x8, a),
+                                                  __builtin_bit_cast(mfma_bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 join(bf16x4 lo, bf16x4 hi) {
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
 
 // Round to nearest even; NaN stays NaN.
 __device__ __forceinline__ uint16_t f2bf(float x) {
@@ -54,24 +67,24 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const ui
   f32x4 acc[2][2];
   for (int i = 0; i < 2; i++)
     for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    bf16x4 a[2], b[2];
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    bf16x8 a[2], b[2];
     for (int i = 0; i < 2; i++) {
       const int m = m0 + 16 * i + r;
-      for (int j = 0; j < 4; j++) {
-        const int k = k0 + 4 * q + j;
+      for (int j = 0; j < 8; j++) {
+        const int k = k0 + 8 * q + j;
         a[i][j] = (m < M && k < kend) ? (short)A[(long)m * sam + (long)k * sak] : (short)0;
       }
     }
     for (int i = 0; i < 2; i++) {
       const int n = n0 + 16 * i + r;
-      for (int j = 0; j < 4; j++) {
-        const int k = k0 + 4 * q + j;
+      for (int j = 0; j < 8; j++) {
+        const int k = k0 + 8 * q + j;
         b[i][j] = (n < N && k < kend) ? (short)B[(long)k * sbk + (long)n * sbn] : (short)0;
       }
     }
     for (int i = 0; i < 2; i++)
-      for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; j++) acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
   }
   float *Cz = C + blockIdx.z * split_stride;
   for (int i = 0; i < 2; i++)
@@ -294,33 +307,39 @@ __global__ __launch_bounds__(256) void k_features(const BandDesc *bands, uint32_
 // ---------------------------------------------------------------- fused inference
 // The whole network for one band per workgroup (four wavefronts), with every
 // activation in LDS.  Convolutions are tiles of 16 output pixels x 16
-// channels on the matrix cores; a lane's A operand is four consecutive
-// channels of one input pixel (one 8-byte LDS read) and its B operand four
-// consecutive weights of one output channel.  The fully connected layers
-// use the same instruction with the sample in row 0.  K is walked in steps
-// of 16 in the same order as the layer-by-layer path, so both give the same
-// logits.
+// channels on the matrix cores; a lane's A operand is eight consecutive
+// entries of the im2col row (two runs of four channels of one input pixel,
+// one 8-byte LDS read each) and its B operand eight consecutive weights of
+// one output channel.  The fully connected layers use the same instruction
+// with the sample in row 0.  K is walked in steps of 32 in the same order as
+// the layer-by-layer path, so both give the same logits.
 template <int H, int C>
 __device__ __forceinline__ void conv_tile_layer(const uint16_t *X, const uint16_t *Wt, const float *bias,
                                                 uint16_t *Y) {
-  constexpr int Ho = H / 2, M = Ho * Ho, K = 9 * C, KS = (K + 15) / 16;
+  constexpr int Ho = H / 2, M = Ho * Ho, K = 9 * C, KS = (K + 31) / 32;
+  static_assert(C % 4 == 0, "a run of four channels stays in one pixel");
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const int r = lane & 15, q = lane >> 4;
   for (int mt = w; mt < M / 16; mt += 4) {
     f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
     const int m = mt * 16 + r, oy = m / Ho, ox = m % Ho;
     for (int ks = 0; ks < KS; ks++) {
-      const int k0 = ks * 16 + 4 * q;  // this lane's first k
-      bf16x4 a = {0, 0, 0, 0}, b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
-      if (k0 < K) {
-        const int pos = k0 / C, c0 = k0 % C, ky = pos / 3, kx = pos % 3;
-        const int iy = 2 * oy - 1 + ky, ix = 2 * ox - 1 + kx;
-        if (iy >= 0 && iy < H && ix >= 0 && ix < H) a = *(const bf16x4 *)(X + (iy * H + ix) * C + c0);
-        b0 = *(const bf16x4 *)(Wt + (size_t)r * K + k0);
-        b1 = *(const bf16x4 *)(Wt + (size_t)(16 + r) * K + k0);
+      bf16x4 a[2], b0[2], b1[2];
+#pragma unroll
+      for (int hf = 0; hf < 2; hf++) {
+        const int k0 = ks * 32 + 8 * q + 4 * hf;  // this lane's run of four k
+        a[hf] = b0[hf] = b1[hf] = bf16x4{0, 0, 0, 0};
+        if (k0 < K) {
+          const int pos = k0 / C, c0 = k0 % C, ky = pos / 3, kx = pos % 3;
+          const int iy = 2 * oy - 1 + ky, ix = 2 * ox - 1 + kx;
+          if (iy >= 0 && iy < H && ix >= 0 && ix < H) a[hf] = *(const bf16x4 *)(X + (iy * H + ix) * C + c0);
+          b0[hf] = *(const bf16x4 *)(Wt + (size_t)r * K + k0);
+          b1[hf] = *(const bf16x4 *)(Wt + (size_t)(16 + r) * K + k0);
+        }
       }
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b1, acc1, 0, 0, 0);
+      const bf16x8 av = join(a[0], a[1]);
+      acc0 = mfma32(av, join(b0[0], b0[1]), acc0);
+      acc1 = mfma32(av, join(b1[0], b1[1]), acc1);
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
@@ -339,14 +358,15 @@ __device__ __forceinline__ void fc_layer(const uint16_t *x, const uint16_t *Wt, 
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const int r = lane & 15, q = lane >> 4;
   if (w * 16 >= N) return;
+  static_assert(K % 32 == 0, "whole steps of 32");
   const int n = w * 16 + r;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 8
-  for (int k0 = 4 * q; k0 < K; k0 += 16) {
-    bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
-    if (r == 0) a = *(const bf16x4 *)(x + k0);
-    if (n < N) b = *(const bf16x4 *)(Wt + (size_t)n * K + k0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  for (int k0 = 8 * q; k0 < K; k0 += 32) {
+    bf16x8 a = {0, 0, 0, 0, 0, 0, 0, 0}, b = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r == 0) a = join(*(const bf16x4 *)(x + k0), *(const bf16x4 *)(x + k0 + 4));
+    if (n < N) b = join(*(const bf16x4 *)(Wt + (size_t)n * K + k0), *(const bf16x4 *)(Wt + (size_t)n * K + k0 + 4));
+    acc = mfma32(a, b, acc);
   }
   // row 0 of the result sits in lanes 0..15, element 0
   if (q == 0 && n < N) {
@@ -437,7 +457,7 @@ void gemm_bf16(int M, int N, int K, const uint16_t *A, long sam, long sak, const
     nz = (int)std::min<long>(64, std::max<long>(1, K / 2048));
     while (nz > 1 && (long)nz * M * N > (long)16 << 20) nz--;
   }
-  const int klen = ((K + nz - 1) / nz + 15) / 16 * 16;
+  const int klen = ((K + nz - 1) / nz + 31) / 32 * 32;  // whole steps of the matrix-core product
   nz = (K + klen - 1) / klen;
   dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
   if (nz == 1) {
