@@ -66,8 +66,8 @@ def main():
         decode_only(args.decode_only)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the path shards by camera / frame across GPUs, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the library runs on one GPU; it would shard by camera / frame across GPUs)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
 
