@@ -93,11 +93,13 @@ union BlockLds {
 // successor until the successor is 64 or more (past the window, or 128 + a
 // lane to decode by the canonical search), and returns that successor.
 // Scalar registers and branches only, unrolled four codes deep: a lane read
-// whose select was written by another lane read needs four instructions
-// between them, and a taken branch costs more than the exits it replaces.
+// whose select was written by a vector instruction (another lane read, or
+// the caller's first-lane read of p) needs four instructions between them,
+// and a taken branch costs more than the exits it replaces.
 __device__ __forceinline__ uint32_t chain_run(uint32_t nx, uint64_t &starts, uint32_t p) {
   uint32_t q;
   asm volatile(
+      "s_nop 3\n\t"
       "s_cmp_ge_u32 %[p], 64\n\t"
       "s_cbranch_scc1 9f\n"
       "1:\n\t"
