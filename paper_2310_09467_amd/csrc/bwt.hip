@@ -398,9 +398,11 @@ __global__ void k_iota(uint32_t *v, const uint32_t *d_n, uint32_t n_max) {
 // key = (block, the first `nbytes` bytes of the rotation, cyclic), the block
 // in the bits above 8 * nbytes.  A thread builds 8 consecutive keys: when
 // their windows stay inside one block they come from one 16-byte load
-// (byte-reversed, then shifted per key), else position by position.
-__device__ __forceinline__ void bwt_init_one(const uint8_t *rle, const uint32_t *blk_start, uint32_t nb, int nbytes,
-                                             uint32_t g, uint64_t *keys) {
+// (byte-reversed, then shifted per key), else position by position.  A
+// wavefront's 512 keys are staged in LDS and stored in 1 KB runs (a thread's
+// own 64 bytes would be four 16-byte stores 64 bytes apart across the lanes).
+__device__ __forceinline__ uint64_t bwt_init_one(const uint8_t *rle, const uint32_t *blk_start, uint32_t nb,
+                                                 int nbytes, uint32_t g) {
   const uint32_t k = block_of(blk_start, nb, g);
   const uint32_t s = blk_start[k], m = blk_start[k + 1] - s, i = g - s;
   uint64_t v = 0;
@@ -409,47 +411,75 @@ __device__ __forceinline__ void bwt_init_one(const uint8_t *rle, const uint32_t 
     v = (v << 8) | rle[s + j];
     j = j + 1 == m ? 0u : j + 1;
   }
-  keys[g] = ((uint64_t)k << (8 * nbytes)) | v;
+  return ((uint64_t)k << (8 * nbytes)) | v;
 }
 
-__global__ void k_bwt_init(const uint8_t *rle, const uint32_t *d_N, const uint32_t *blk_start, const uint32_t *d_nb,
-                           int nbytes, uint64_t *keys, uint32_t *d_u) {
+constexpr int kInitThreads = 256;
+constexpr uint32_t kInitStride = 9;  // LDS words of 8 bytes per lane (8 keys and a pad against bank conflicts)
+
+__global__ __launch_bounds__(kInitThreads) void k_bwt_init(const uint8_t *rle, const uint32_t *d_N,
+                                                           const uint32_t *blk_start, const uint32_t *d_nb,
+                                                           int nbytes, uint64_t *keys, uint32_t *d_u) {
+  __shared__ uint64_t stage[kInitThreads / kWave][kWave * kInitStride];
   const uint32_t N = *d_N, nb = *d_nb;
   if (blockIdx.x == 0 && threadIdx.x == 0) *d_u = N;
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  uint64_t *st = stage[wv];
   // the block table in one register per lane when it fits a wavefront
   const bool lane_tab = nb < (uint32_t)kWave;
-  const uint32_t bs = lane_tab && (uint32_t)lane_id() <= nb ? blk_start[lane_id()] : 0u;
+  const uint32_t bs = lane_tab && (uint32_t)lane <= nb ? blk_start[lane] : 0u;
   const int kbits = 8 * nbytes;  // nbytes <= 7
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; (uint64_t)t * 8 < N; t += gridDim.x * blockDim.x) {
-    const uint32_t g0 = t * 8;
-    uint32_t k = 0;
-    if (lane_tab) {
-      for (uint32_t j = 1; j < nb; j++) k += g0 >= (uint32_t)__builtin_amdgcn_readlane((int)bs, (int)j) ? 1u : 0u;
-    } else {
-      k = block_of(blk_start, nb, g0);
-    }
-    const uint32_t e = blk_start[k + 1];
-    // bytes g0 .. g0 + 7 + nbytes - 1 all inside block k (no wrap); the 16
-    // loaded bytes end below N + 8, inside the buffer's padding
-    if ((uint64_t)g0 + 8 <= N && (uint64_t)g0 + 7 + (uint32_t)nbytes <= e) {
-      const uint64_t hi = __builtin_bswap64(*(const uint64_t *)(rle + g0));
-      const uint64_t lo = __builtin_bswap64(*(const uint64_t *)(rle + g0 + 8));
-      const uint64_t top = (uint64_t)k << kbits;
-      uint64_t kk[8];
-#pragma unroll
-      for (int o = 0; o < 8; o++) {
-        const uint64_t w64 = o == 0 ? hi : (hi << (8 * o)) | (lo >> (64 - 8 * o));  // bytes g0 + o .. g0 + o + 7
-        kk[o] = top | (w64 >> (64 - kbits));
+  const uint32_t waves = gridDim.x * (kInitThreads / kWave);
+  // every lane of a wavefront takes every step (the stores are shared)
+  for (uint64_t wbase = (uint64_t)(blockIdx.x * (kInitThreads / kWave) + wv) * 512; wbase < N;
+       wbase += (uint64_t)waves * 512) {
+    const uint32_t g0 = (uint32_t)wbase + 8u * (uint32_t)lane;
+    uint64_t kk[8];
+    if (g0 < N) {
+      uint32_t k = 0;
+      if (lane_tab) {
+        for (uint32_t j = 1; j < nb; j++) k += g0 >= (uint32_t)__builtin_amdgcn_readlane((int)bs, (int)j) ? 1u : 0u;
+      } else {
+        k = block_of(blk_start, nb, g0);
       }
-      uint4 *kq = (uint4 *)(keys + g0);
+      const uint32_t e = blk_start[k + 1];
+      // bytes g0 .. g0 + 7 + nbytes - 1 all inside block k (no wrap); the 16
+      // loaded bytes end below N + 8, inside the buffer's padding
+      if ((uint64_t)g0 + 8 <= N && (uint64_t)g0 + 7 + (uint32_t)nbytes <= e) {
+        const uint64_t hi = __builtin_bswap64(*(const uint64_t *)(rle + g0));
+        const uint64_t lo = __builtin_bswap64(*(const uint64_t *)(rle + g0 + 8));
+        const uint64_t top = (uint64_t)k << kbits;
 #pragma unroll
-      for (int q = 0; q < 4; q++)
-        kq[q] = make_uint4((uint32_t)kk[2 * q], (uint32_t)(kk[2 * q] >> 32), (uint32_t)kk[2 * q + 1],
-                           (uint32_t)(kk[2 * q + 1] >> 32));
-    } else {
-      const uint32_t g1 = min(N, g0 + 8u);
-      for (uint32_t g = g0; g < g1; g++) bwt_init_one(rle, blk_start, nb, nbytes, g, keys);
+        for (int o = 0; o < 8; o++) {
+          const uint64_t w64 = o == 0 ? hi : (hi << (8 * o)) | (lo >> (64 - 8 * o));  // bytes g0 + o .. g0 + o + 7
+          kk[o] = top | (w64 >> (64 - kbits));
+        }
+      } else {
+#pragma unroll
+        for (int o = 0; o < 8; o++) kk[o] = g0 + o < N ? bwt_init_one(rle, blk_start, nb, nbytes, g0 + o) : 0ull;
+      }
     }
+#pragma unroll
+    for (int o = 0; o < 8; o++) st[lane * kInitStride + o] = kk[o];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // store q: keys 2 (64 q + lane) and the one after, of lane (64 q + lane) / 4
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint32_t kx = 2u * (64u * (uint32_t)q + (uint32_t)lane);
+      const uint32_t at = (kx >> 3) * kInitStride + (kx & 7u);
+      const uint64_t a = st[at], b2 = st[at + 1];
+      const uint64_t gk = wbase + kx;
+      if (gk + 2 <= N) {
+        *(uint4 *)(keys + gk) = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b2, (uint32_t)(b2 >> 32));
+      } else if (gk < N) {
+        keys[gk] = a;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
