@@ -657,15 +657,7 @@ __global__ __launch_bounds__(kTThreads) void k_z_runs(const uint8_t *idx, const 
         cnt += zlen(z, i, p, zv[i], be);
       }
     }
-    if (p0 + kTItems <= N) {
-      uint4 *o = (uint4 *)(zs + p0);
-#pragma unroll
-      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(zv[4 * q], zv[4 * q + 1], zv[4 * q + 2], zv[4 * q + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < kTItems; i++)
-        if (p0 + i < N) zs[p0 + i] = zv[i];
-    }
+    tile_store(buf, zs, base, N);
     cnt = block_reduce<false>(cnt, sh);
     if (threadIdx.x == 0) aggs_l[tile] = cnt;
   }

@@ -304,18 +304,7 @@ __global__ __launch_bounds__(kTThreads) void k_sym_offs(const uint16_t *sym, con
     for (int i = 0; i < kTItems; i++) buf[tpad(threadIdx.x * kTItems + i)] = bits[i];
     __syncthreads();
     const uint32_t total = tile_scan<false, false>(buf, carry, sh);
-    uint32_t q[kTItems];
-#pragma unroll
-    for (int i = 0; i < kTItems; i++) q[i] = buf[tpad(threadIdx.x * kTItems + i)];
-    if (k0 + kTItems <= nsym) {
-      uint4 *d = (uint4 *)(sym_off + k0);
-#pragma unroll
-      for (int j = 0; j < kTItems / 4; j++) d[j] = make_uint4(q[4 * j], q[4 * j + 1], q[4 * j + 2], q[4 * j + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < kTItems; i++)
-        if (k0 + i < nsym) sym_off[k0 + i] = q[i];
-    }
+    tile_store(buf, sym_off, tile * kTTile, nsym);
     if (tile == nt - 1 && threadIdx.x == 0) sym_off[nsym] = carry + total;
     __syncthreads();
   }

@@ -177,6 +177,19 @@ __device__ __forceinline__ uint32_t tile_scan(uint32_t *buf, uint32_t carry, uin
   return total;
 }
 
+// Stores a tile's values from buf (tile order, as tile_scan leaves them) at
+// out[tile_base + j] for tile_base + j < n, consecutive threads taking
+// consecutive positions (a thread's own 16 values would be four 16-byte
+// stores 64 bytes apart across the lanes).  buf must stay unchanged until
+// the next barrier.
+__device__ __forceinline__ void tile_store(const uint32_t *buf, uint32_t *out, uint32_t tile_base, uint32_t n) {
+#pragma unroll
+  for (int i = 0; i < kTItems; i++) {
+    const uint32_t j = (uint32_t)(i * kTThreads) + threadIdx.x;
+    if (tile_base + j < n) out[tile_base + j] = buf[tpad((int)j)];
+  }
+}
+
 // carry over aggs[counted, tile), extending a running carry
 template <bool kMax>
 __device__ __forceinline__ uint32_t tile_carry(const uint32_t *aggs, uint32_t &counted, uint32_t tile,

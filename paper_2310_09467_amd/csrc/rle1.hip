@@ -104,15 +104,7 @@ __global__ __launch_bounds__(kTThreads) void k_r1_counts(const uint32_t *band_st
       rs[i] = buf[tpad(threadIdx.x * kTItems + i)];
       if (p0 + i < N) cnt += piece_len_out((p0 + i - rs[i]) % 255u);
     }
-    if (p0 + kTItems <= N) {
-      uint4 *o = (uint4 *)(runstart + p0);
-#pragma unroll
-      for (int q = 0; q < kTItems / 4; q++) o[q] = make_uint4(rs[4 * q], rs[4 * q + 1], rs[4 * q + 2], rs[4 * q + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < kTItems; i++)
-        if (p0 + i < N) runstart[p0 + i] = rs[i];
-    }
+    tile_store(buf, runstart, tile * kTTile, N);
     cnt = block_reduce<false>(cnt, sh);
     if (threadIdx.x == 0) aggs_s[tile] = cnt;
   }
@@ -153,15 +145,7 @@ __global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_sta
     uint32_t q[kTItems];
 #pragma unroll
     for (int i = 0; i < kTItems; i++) q[i] = buf[tpad(threadIdx.x * kTItems + i)];
-    if (p0 + kTItems <= N) {
-      uint4 *d = (uint4 *)(off + p0);
-#pragma unroll
-      for (int k = 0; k < kTItems / 4; k++) d[k] = make_uint4(q[4 * k], q[4 * k + 1], q[4 * k + 2], q[4 * k + 3]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < kTItems; i++)
-        if (p0 + i < N) off[p0 + i] = q[i];
-    }
+    tile_store(buf, off, tile * kTTile, N);
 #pragma unroll
     for (int i = 0; i < kTItems; i++) {
       const uint32_t p = p0 + i;
