@@ -116,6 +116,7 @@ __global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_sta
                                                         uint32_t *d_total) {
   __shared__ uint32_t buf[kTPad];
   __shared__ uint32_t sh[kTThreads / kWave];
+  __shared__ uint8_t stage[2 * kTTile];  // the tile's output bytes (at most two a position)
   const uint32_t nt = (N + kTTile - 1) / kTTile;
   uint32_t carry = 0, counted = 0;
   for (uint32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
@@ -146,21 +147,25 @@ __global__ __launch_bounds__(kTThreads) void k_r1_write(const uint32_t *band_sta
 #pragma unroll
     for (int i = 0; i < kTItems; i++) q[i] = buf[tpad(threadIdx.x * kTItems + i)];
     tile_store(buf, off, tile * kTTile, N);
+    // the tile's output is one run from `carry`: staged, then stored with
+    // consecutive threads on consecutive bytes
 #pragma unroll
     for (int i = 0; i < kTItems; i++) {
       const uint32_t p = p0 + i;
       if (p >= N || o[i] > 3) continue;
       const uint32_t c = z.at(i);
-      rle[q[i]] = (uint8_t)c;
+      stage[q[i] - carry] = (uint8_t)c;
       if (o[i] == 3) {  // the piece's count byte: equal bytes after the fourth, at most 251, inside the band
         const uint32_t b = upper_index(band_start, n_bands, p);
         const uint32_t bend = b + 1 < n_bands ? band_start[b + 1] : N;
         const uint32_t lim = min(bend, p + 252u);
         uint32_t j = p + 1;
         while (j < lim && x[j] == c) j++;
-        rle[q[i] + 1] = (uint8_t)(j - p - 1);
+        stage[q[i] - carry + 1] = (uint8_t)(j - p - 1);
       }
     }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < total; j += kTThreads) rle[carry + j] = stage[j];
     if (tile == nt - 1 && threadIdx.x == 0) {
       off[N] = carry + total;
       if (d_total) *d_total = carry + total;
