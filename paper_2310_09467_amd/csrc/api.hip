@@ -376,9 +376,11 @@ int build_plan(pcbz_ctx *ctx, const std::vector<FrameIn> &fin, bool judge_only, 
   if (P.ntot >= (1ull << 31)) return fail(ctx, PCBZ_EINVAL, "batch too large (%llu bytes)", (unsigned long long)P.ntot);
   P.band_start.push_back((uint32_t)P.ntot);
   const uint32_t pm = P.pitch_max;
+  // lenses per rearrangement workgroup: 16 gives a 2040x2040 frame about
+  // 1200 workgroups (32 lenses per workgroup: 33 us, 16: 24 us, 8: 23 us)
   uint32_t tl = 16384u / (pm * pm);
   tl = tl > 1 ? tl - 1 : 0;
-  if (tl > 32) tl = 32;
+  if (tl > 16) tl = 16;
   if (tl < 1) return fail(ctx, PCBZ_EINVAL, "pitch %u too large", pm);
   P.lens_per_wg = tl;
   P.remap_chunks = (P.nt_max + tl - 1) / tl;
