@@ -537,17 +537,6 @@ __device__ __forceinline__ void load16(const uint64_t *a, uint32_t k0, uint32_t 
     for (int i = 0; i < kTItems; i++) v[i] = k0 + i < n ? a[k0 + i] : 0ull;
   }
 }
-__device__ __forceinline__ void store16(uint32_t *a, uint32_t k0, uint32_t n, const uint32_t *v) {
-  if (k0 + kTItems <= n) {
-    uint4 *q = (uint4 *)(a + k0);
-#pragma unroll
-    for (int j = 0; j < kTItems / 4; j++) q[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < kTItems; i++)
-      if (k0 + i < n) a[k0 + i] = v[i];
-  }
-}
 // slots of 16 consecutive list elements; a null list means slot = position
 __device__ __forceinline__ void load_slots(const uint32_t *slot, uint32_t k0, uint32_t n, uint32_t *v) {
   if (slot) {
@@ -1182,8 +1171,11 @@ int run_bwt(const uint8_t *rle, const uint32_t *d_N, uint32_t n_max, const uint3
     u ^= 1;
     rounds++;
     if (pinned_u) {
-      hipMemcpyAsync(pinned_u, w.d_u, (size_t)(maxg_at + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-      hipStreamSynchronize(s);
+      // a failed read-back ends the rounds; the caller's error check reports it
+      if (hipMemcpyAsync(pinned_u, w.d_u, (size_t)(maxg_at + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        break;
       n_cur = pinned_u[u];
       maxg = pinned_u[maxg_at];
       if (getenv("PCBZ_DEBUG_BWT"))

@@ -361,7 +361,6 @@ __device__ __forceinline__ void fc_layer(const uint16_t *x, const uint16_t *Wt, 
   static_assert(K % 32 == 0, "whole steps of 32");
   const int n = w * 16 + r;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
   for (int k0 = 8 * q; k0 < K; k0 += 32) {
     bf16x8 a = {0, 0, 0, 0, 0, 0, 0, 0}, b = {0, 0, 0, 0, 0, 0, 0, 0};
     if (r == 0) a = join(*(const bf16x4 *)(x + k0), *(const bf16x4 *)(x + k0 + 4));

@@ -1295,10 +1295,6 @@ __global__ void k_dec_crc_check(const BlockDesc *blocks, const DecSlot *slots, c
 }
 
 // ---------------------------------------------------------------- arrangement, inverted
-__device__ __forceinline__ uint16_t rd16(const uint8_t *p, size_t i) {
-  return (uint16_t)(p[2 * i] | ((uint32_t)p[2 * i + 1] << 8));
-}
-
 // Lens-neighbour delta: the first lens column of every view is a running sum
 // down the lens rows (mod 2^16), kept apart from the band bytes.
 __global__ __launch_bounds__(256) void k_udx_col0(const DecBand *bands, const uint8_t *raw, uint16_t *col0,

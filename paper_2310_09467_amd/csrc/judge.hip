@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_judge_score(uint32_t *hist_g, const int
   }
 }
 
-__global__ void k_choose(const BandDesc *bands, uint32_t n_bands, const int32_t *task_of,
+__global__ void k_choose(const BandDesc * /*bands*/, uint32_t n_bands, const int32_t *task_of,
                          const unsigned long long *score, const JudgeTask *tasks, const uint8_t *forced,
                          uint8_t *choice, double *entropy, int64_t *score_out) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;

@@ -396,14 +396,16 @@ __global__ __launch_bounds__(64 * kSegWaves) void k_mtf_chain(const uint32_t *d_
 // (each passing its lane 63 on to lane 0 of the next) and lanes 0..q of
 // Q[j].  The lane number lives in m0 (v_readlane / v_writelane select).
 // All 64 lanes hold list entries, so the loop runs with the full exec mask
-// (set here, five wait states before the first DPP, restored at the end);
+// (set here, five wait states before the first DPP, restored at the end;
+// m0 is saved and restored around the loop as well);
 // a DPP source needs two wait states after a vector write: the fast path's
 // was written a dozen instructions earlier, the others get an s_nop.
 __device__ __forceinline__ void mtf_batch(uint32_t &Q0, uint32_t &Q1, uint32_t &Q2, uint32_t &Q3, uint32_t &mine,
                                           uint64_t todo, uint32_t vl) {
-  uint32_t v, q, c0, c1, c2, t;
+  uint32_t v, q, c0, c1, c2, t, m0s;
   uint64_t mq, m1, m2, mk, ex;
   asm volatile(
+      "s_mov_b32 %[m0s], m0\n\t"
       "s_mov_b64 %[ex], exec\n\t"
       "s_mov_b64 exec, -1\n\t"
       "s_nop 4\n"
@@ -479,12 +481,14 @@ __device__ __forceinline__ void mtf_batch(uint32_t &Q0, uint32_t &Q1, uint32_t &
       "v_writelane_b32 %[mine], %[q], m0\n\t"
       "s_branch 1b\n"
       "9:\n\t"
-      "s_mov_b64 exec, %[ex]"
+      "s_mov_b64 exec, %[ex]\n\t"
+      "s_mov_b32 m0, %[m0s]\n\t"
+      "s_nop 0"
       : [Q0] "+v"(Q0), [Q1] "+v"(Q1), [Q2] "+v"(Q2), [Q3] "+v"(Q3), [mine] "+v"(mine), [todo] "+s"(todo),
         [v] "=&s"(v), [q] "=&s"(q), [c0] "=&s"(c0), [c1] "=&s"(c1), [c2] "=&s"(c2), [mq] "=&s"(mq), [m1] "=&s"(m1),
-        [m2] "=&s"(m2), [mk] "=&s"(mk), [t] "=&v"(t), [ex] "=&s"(ex)
+        [m2] "=&s"(m2), [mk] "=&s"(mk), [t] "=&v"(t), [ex] "=&s"(ex), [m0s] "=&s"(m0s)
       : [vl] "v"(vl)
-      : "scc", "m0");
+      : "scc");
 }
 
 // wavefront shift right by one lane; lane 0 takes `in`

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kTThreads) void k_sym_offs(const uint16_t *sym, con
 // writer's word index space.  One thread; blocks are few.
 __global__ void k_layout(const uint32_t *d_nb, const BlockDesc *blocks, BlockCode *codes, const uint32_t *sym_off,
                          const uint32_t *blk_sym_start, const FrameOut *frames, uint32_t n_frames,
-                         const BandDesc *bands, uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start,
+                         const BandDesc * /*bands*/, uint32_t *band_len, uint64_t *frame_len, uint32_t *word_start,
                          uint32_t *d_words) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const uint32_t nb = *d_nb;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) void k_write(const uint32_t *d_words, const ui
 }
 
 __global__ __launch_bounds__(256) void k_header(const FrameOut *frames, const uint64_t *frame_len,
-                                                const BandDesc *bands, const uint8_t *choice,
+                                                const BandDesc * /*bands*/, const uint8_t *choice,
                                                 const uint32_t *band_len) {
   const FrameOut F = frames[blockIdx.x];
   if (frame_len[blockIdx.x] > F.cap) return;

@@ -179,7 +179,7 @@ __device__ __forceinline__ uint32_t out_end(const uint32_t *runstart, const uint
 }
 
 // One thread per band: greedy cuts into block slots.
-__global__ void k_cut(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t N,
+__global__ void k_cut(const BandDesc *bands, uint32_t n_bands, const uint32_t *band_start, uint32_t /*N*/,
                       const uint32_t *runstart, const uint32_t *off, BlockDesc *slots, uint32_t *slot_count,
                       uint32_t *err) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
